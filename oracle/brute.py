@@ -1,0 +1,114 @@
+"""O1: brute-force incremental matches.  TEST INFRASTRUCTURE (see the
+package docstring).
+
+This is the problem statement of Sec. II-A taken literally:
+  * Def. 2: a match of Q in a graph H is an injective map f: V(Q) -> V(H)
+    with L(f(u)) = L(u) for every query vertex and {f(u), f(u')} in E(H) for
+    every query edge (a non-induced embedding; automorphic images are
+    distinct matches).
+  * Def. 1 / problem statement: a batch is a set of edge insertions and
+    deletions; G' is G after the batch, and the incremental matches are the
+    difference of the match sets of G and G' (read here as the net change:
+    result(+) = M(G') minus M(G), result(-) = M(G) minus M(G'); the paper's
+    Example 1 reports only the net effect of a batch).
+It enumerates M(G) and M(G') completely by backtracking over the query
+vertices in id order (candidates: every unused data vertex with the right
+label; an edge is checked once both its ends are placed) and returns the two
+set differences.  No seeds, no order rule, no intersections.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Set, Tuple
+
+
+def canonical(n: int, edges: Set[Tuple[int, int]], ups):
+    """Canonicalise a batch [(op, u, v)] (op 1 = insert, 0 = delete).
+
+    Returns (status, I, D, n_noop, n_dup) with status in {"ok", "invalid",
+    "conflict"}; I and D are sorted lists of (lo, hi)."""
+    seen: Dict[Tuple[int, int], int] = {}
+    n_dup = 0
+    for (op, u, v) in ups:
+        if u == v or not (0 <= u < n) or not (0 <= v < n):
+            return "invalid", [], [], 0, 0
+        e = (min(u, v), max(u, v))
+        if e in seen:
+            if seen[e] != op:
+                return "conflict", [], [], 0, 0
+            n_dup += 1
+            continue
+        seen[e] = op
+    I, D, n_noop = [], [], 0
+    for e, op in seen.items():
+        present = e in edges
+        if op == 1 and not present:
+            I.append(e)
+        elif op == 0 and present:
+            D.append(e)
+        else:
+            n_noop += 1
+    return "ok", sorted(I), sorted(D), n_noop, n_dup
+
+
+def all_matches(n: int, labels, adj: Dict[int, Set[int]], k: int, qlabels, qedges) -> Set[tuple]:
+    """Every match of Q in H (Def. 2) by plain backtracking."""
+    qadj = [[False] * k for _ in range(k)]
+    for (a, b) in qedges:
+        qadj[a][b] = qadj[b][a] = True
+    by_label: Dict[int, List[int]] = {}
+    for v in range(n):
+        by_label.setdefault(int(labels[v]), []).append(v)
+    out: Set[tuple] = set()
+    f = [-1] * k
+
+    def rec(u: int):
+        if u == k:
+            out.add(tuple(f))
+            return
+        for c in by_label.get(int(qlabels[u]), []):
+            if c in f[:u]:
+                continue
+            ok = True
+            for w in range(u):
+                if qadj[u][w] and c not in adj.get(f[w], ()):
+                    ok = False
+                    break
+            if ok:
+                f[u] = c
+                rec(u + 1)
+                f[u] = -1
+
+    rec(0)
+    return out
+
+
+def edge_set(graph) -> Set[Tuple[int, int]]:
+    s = set()
+    for v in range(graph.n):
+        for w in graph.neighbors(v).tolist():
+            if v < w:
+                s.add((v, int(w)))
+    return s
+
+
+def adjacency(n: int, edges: Set[Tuple[int, int]]) -> Dict[int, Set[int]]:
+    adj: Dict[int, Set[int]] = {}
+    for (a, b) in edges:
+        adj.setdefault(a, set()).add(b)
+        adj.setdefault(b, set()).add(a)
+    return adj
+
+
+def bdsm(graph, query, batch) -> dict:
+    """O1 result for one batch: {status, plus, minus, I, D, n_noop, n_dup}."""
+    E = edge_set(graph)
+    ups = list(zip(batch.op.tolist(), batch.src.tolist(), batch.dst.tolist()))
+    status, I, D, n_noop, n_dup = canonical(graph.n, E, ups)
+    if status != "ok":
+        return {"status": status}
+    E2 = (E | set(I)) - set(D)
+    qe = [tuple(e) for e in query.edges.tolist()]
+    M1 = all_matches(graph.n, graph.labels, adjacency(graph.n, E), query.k, query.labels, qe)
+    M2 = all_matches(graph.n, graph.labels, adjacency(graph.n, E2), query.k, query.labels, qe)
+    return {"status": "ok", "plus": M2 - M1, "minus": M1 - M2, "I": I, "D": D, "n_noop": n_noop,
+            "n_dup": n_dup, "E2": E2}
