@@ -1,0 +1,230 @@
+/*
+ * gamma.h - C ABI of the MI355X (gfx950) batch-dynamic subgraph matching
+ * library.
+ *
+ * Problem (paper Sec. II-A, Def. 1, Def. 2 and the problem statement): a
+ * data graph G = (V, E, L) is undirected, simple and vertex-labelled; a query
+ * Q is a small connected labelled graph; a batch is a set of edge insertions
+ * and deletions.  A match is an injective map f: V(Q) -> V with L(f(u)) =
+ * L(u) for every query vertex and {f(u), f(w)} in E for every query edge (not
+ * induced; automorphic images are distinct matches).  For every batch the
+ * library reports the incremental matches: the matches of the updated graph
+ * G' that are not matches of G (insertion results, sign +) and the matches
+ * of G that are not matches of G' (deletion results, sign -).
+ *
+ * Method (Sec. IV): the batch is applied to a dynamic CSR; a neighbourhood
+ * label frequency filter (Sec. IV-B) marks candidate vertices per query
+ * vertex; for every batch edge and every query edge it can map to, a
+ * depth-first search extends partial matches by intersecting sorted
+ * neighbour lists (Algorithm 1), and a total order over the batch edges
+ * makes each match come from exactly one of them (the rule stated after
+ * Algorithm 1).  Everything after the input copy runs in HIP kernels on the
+ * device; there is no CPU fallback.
+ *
+ * Conventions
+ *   - Vertex ids are uint32 in [0, n), n < 2^31.  Labels are uint32 < 65536.
+ *   - All functions return gamma_status.  0 (GAMMA_OK) and 1
+ *     (GAMMA_TRUNCATED) are successes; negative values are failures.  Every
+ *     failure other than GAMMA_EDEVICE leaves the graph and the registered
+ *     queries unchanged (inputs are validated before anything is mutated).
+ *     GAMMA_EDEVICE poisons the context: every later call returns it.
+ *   - Callers own every input array; the library reads it during the call
+ *     and keeps its own copy.  `where` tells whether a pointer is host
+ *     memory or device memory on the context's device (device inputs are
+ *     read on the context stream, ordered after work the caller queued on
+ *     that stream).
+ *   - The library owns the graph, the queries, all scratch memory and the
+ *     result buffers.  Result pointers stay valid until the next
+ *     gamma_apply_batch on the context, gamma_result_release or
+ *     gamma_destroy.
+ *   - One host thread at a time per context.
+ */
+#ifndef GAMMA_H
+#define GAMMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gamma_status {
+  GAMMA_OK = 0,
+  GAMMA_TRUNCATED = 1,      /* success; tuple capacity reached, counts/hashes still exact */
+  GAMMA_EINVAL = -1,        /* malformed argument (ids out of range, self loop, bad CSR, ...) */
+  GAMMA_ECONFLICT = -2,     /* the batch inserts and deletes the same edge */
+  GAMMA_ENOMEM = -3,        /* device or host allocation failed (nothing mutated) */
+  GAMMA_EUNSUPPORTED = -4,  /* outside the supported envelope (k > 16, disconnected query, ...) */
+  GAMMA_ESTATE = -5,        /* call order (e.g. apply_batch before load_graph) */
+  GAMMA_ETIMEDOUT = -6,     /* reserved: deadline exceeded, batch not committed */
+  GAMMA_EDEVICE = -7        /* HIP runtime error; the context is poisoned */
+} gamma_status;
+
+typedef enum gamma_mem { GAMMA_MEM_HOST = 0, GAMMA_MEM_DEVICE = 1 } gamma_mem;
+
+/* Context options.  Zero-initialise and set what you need. */
+typedef struct gamma_options {
+  int32_t device;            /* HIP device ordinal */
+  void* stream;              /* hipStream_t to run on; NULL = library-created stream */
+  uint64_t tuple_capacity;   /* max tuple records stored per batch (0 = no tuple buffer) */
+  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 8) */
+  uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
+  uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
+  uint32_t reserved[8];
+} gamma_options;
+
+/* Flags of gamma_apply_batch. */
+enum {
+  GAMMA_F_COUNT = 1u << 0,          /* counts per query and sign (always on) */
+  GAMMA_F_HASH = 1u << 1,           /* order-independent multiset hash per query and sign */
+  GAMMA_F_TUPLES = 1u << 2,         /* store match tuples (up to tuple_capacity records) */
+  GAMMA_F_SEED_ATTR = 1u << 3,      /* store the seed ord of each tuple record */
+  GAMMA_F_PER_UPDATE = 1u << 4,     /* count / hash per canonical batch edge (attribution) */
+  GAMMA_F_CANONICAL = 1u << 5       /* return the canonical batch on the host */
+};
+
+/* Per query results of one batch.  Index 1 = insertion results (+),
+ * index 0 = deletion results (-). */
+typedef struct gamma_query_result {
+  uint32_t qid;
+  uint32_t k;
+  uint64_t count[2];
+  uint64_t hash_sum[2];  /* sum mod 2^64 of the per-tuple hash (GAMMA_F_HASH) */
+  uint64_t hash_xor[2];  /* xor of the per-tuple hash (GAMMA_F_HASH) */
+} gamma_query_result;
+
+typedef struct gamma_batch_stats {
+  uint32_t n_input;        /* updates passed in */
+  uint32_t n_canonical;    /* |I| + |D| */
+  uint32_t n_insert;       /* |I| */
+  uint32_t n_delete;       /* |D| */
+  uint32_t n_noop;         /* +e with e in E, or -e with e not in E (skipped) */
+  uint32_t n_duplicate;    /* repeated updates collapsed */
+  uint32_t n_touched;      /* vertices whose neighbour list changed */
+  uint32_t reserved0;
+  uint64_t n_seeds;        /* (batch edge x directed query edge) pairs that pass the filter */
+  uint64_t dfs_nodes;      /* partial matches extended (levels >= 2) */
+  uint64_t steals;         /* successful work steals */
+  uint64_t cand_scanned;   /* candidate-list entries examined */
+  uint64_t bytes_alg_dfs;  /* algorithmic bytes read by the search kernel */
+  uint64_t bytes_alg_update; /* algorithmic bytes of the graph update (merge + commit) */
+  float ms_canon, ms_merge, ms_filter, ms_seed, ms_dfs, ms_commit, ms_total;
+  float reserved1;
+} gamma_batch_stats;
+
+typedef struct gamma_batch_result {
+  uint32_t n_queries;
+  uint32_t tuple_width;           /* words per tuple row = max k over registered queries */
+  gamma_query_result* queries;    /* host array [n_queries], library-owned */
+  /* tuple records (GAMMA_F_TUPLES): device pointers, library-owned.
+   * tuples  [n_tuples * tuple_width] external vertex ids in query-vertex order,
+   *         unused trailing words are 0xFFFFFFFF;
+   * meta    [n_tuples] = qid << 1 | sign;
+   * ord     [n_tuples] seed ord (GAMMA_F_SEED_ATTR), else NULL. */
+  uint64_t n_tuples;              /* records stored */
+  uint64_t n_tuples_found;        /* records found (> n_tuples when truncated) */
+  uint32_t* tuples;
+  uint32_t* meta;
+  uint32_t* ord;
+  /* canonical batch on the host (GAMMA_F_CANONICAL), ascending (lo, hi),
+   * entry i has ord i; external ids. */
+  uint32_t n_canonical;
+  uint32_t reserved0;
+  uint32_t* canon_lo;
+  uint32_t* canon_hi;
+  uint8_t* canon_sign;
+  /* per canonical batch edge, indexed by ord (GAMMA_F_PER_UPDATE): totals
+   * over every registered query of the matches attributed to that edge. */
+  uint64_t* upd_count;
+  uint64_t* upd_hash_sum;
+  uint64_t* upd_hash_xor;
+  gamma_batch_stats stats;
+} gamma_batch_result;
+
+typedef struct gamma_ctx gamma_ctx;
+
+/* Create a context on opt->device (all fields of opt may be zero).
+ * Errors: EINVAL (null out), EDEVICE (no such device / HIP failure). */
+gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out);
+
+/* Free every library allocation of the context.  NULL is accepted. */
+gamma_status gamma_destroy(gamma_ctx* ctx);
+
+/* Load (replace) the data graph: symmetric CSR with ascending rows.
+ *   n        number of vertices (1 <= n < 2^31)
+ *   nnz      row_ptr[n] = number of directed entries (= 2|E|)
+ *   row_ptr  [n+1] uint64, non-decreasing, row_ptr[0] = 0
+ *   col      [nnz] uint32, each row strictly ascending, no self loops,
+ *            every entry (v, w) has its mirror (w, v)
+ *   labels   [n] uint32 < 65536
+ * The paper's data model (Sec. II-A).  Registered queries are kept and their
+ * candidate filters are rebuilt.  Errors: EINVAL (malformed CSR, leaves the
+ * previous graph in place), ENOMEM, EDEVICE. */
+gamma_status gamma_load_graph(gamma_ctx* ctx, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                              const uint32_t* col, const uint32_t* labels, gamma_mem where);
+
+/* Register a standing query (host arrays).
+ *   k        vertices, 2 <= k <= 16
+ *   qlabels  [k] labels < 65536
+ *   m        edges, k-1 <= m <= k(k-1)/2
+ *   qedges   [2m] pairs (a, b), a != b, < k, no repeated pair
+ * The query must be connected.  A matching order is planned for each
+ * directed query edge (Sec. IV-C: more selective query vertices first) and
+ * the candidate filter (Sec. IV-B) is built over the whole graph.
+ * Errors: EINVAL, EUNSUPPORTED (disconnected, k > 16, too many queries),
+ * ENOMEM, EDEVICE.  *out_qid receives the query id (0, 1, ...). */
+gamma_status gamma_register_query(gamma_ctx* ctx, uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                  const uint32_t* qedges, uint32_t* out_qid);
+
+/* Apply one batch and report its incremental matches for every registered
+ * query (the problem statement of Sec. II-A; Algorithm 1 of Sec. IV-C).
+ *   n_upd    updates, <= 2^20 per call
+ *   src,dst  [n_upd] endpoints (either orientation)
+ *   op       [n_upd] 1 = insert, 0 = delete
+ *   where    memory kind of src/dst/op
+ *   flags    GAMMA_F_* (COUNT is implied)
+ *   out      filled on success (library-owned buffers, see above)
+ * Canonical semantics: duplicates collapse; +e with e in E and -e with e not
+ * in E are skipped as no-ops; a self loop or an id >= n gives EINVAL; +e
+ * together with -e gives ECONFLICT.  Either error leaves the graph unchanged.
+ * Returns OK or TRUNCATED (tuple capacity reached; counts and hashes exact). */
+gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
+                               const uint32_t* dst, const uint8_t* op, gamma_mem where,
+                               uint32_t flags, gamma_batch_result* out);
+
+/* Copy up to max_records tuple records of the last batch into caller
+ * buffers (any may be NULL) on the context stream; `where` is the memory
+ * kind of the destinations.  Layout as in gamma_batch_result.  Errors:
+ * ESTATE (no batch result), EDEVICE. */
+gamma_status gamma_copy_tuples(gamma_ctx* ctx, uint32_t* tuples, uint32_t* meta, uint32_t* ord,
+                               uint64_t max_records, gamma_mem where);
+
+/* Release the result buffers of the last batch early (optional). */
+gamma_status gamma_result_release(gamma_ctx* ctx, gamma_batch_result* res);
+
+/* Snapshot the current graph into caller host buffers: row_ptr [n+1],
+ * col [nnz] (ascending rows, external ids), labels [n].  Query sizes first
+ * with col == NULL: *n_out and *nnz_out are always written. */
+gamma_status gamma_export_graph(gamma_ctx* ctx, uint32_t* n_out, uint64_t* nnz_out,
+                                uint64_t* row_ptr, uint32_t* col, uint32_t* labels);
+
+/* Host-only validators (no device needed); same rules as the calls above. */
+gamma_status gamma_validate_graph(uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                  const uint32_t* col, const uint32_t* labels);
+gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                  const uint32_t* qedges);
+gamma_status gamma_validate_batch(uint32_t n, uint32_t n_upd, const uint32_t* src,
+                                  const uint32_t* dst, const uint8_t* op);
+
+/* Text of a status code, and of the last error on a context. */
+const char* gamma_status_string(gamma_status s);
+const char* gamma_last_error(const gamma_ctx* ctx);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+uint32_t gamma_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAMMA_H */

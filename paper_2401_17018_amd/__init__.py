@@ -1,0 +1,263 @@
+"""MI355X-native batch-dynamic subgraph matching (GAMMA, arXiv 2401.17018).
+
+Python binding over the C ABI of libgamma.so (include/gamma.h).  The binding
+only marshals arguments: graph loading, batch canonicalisation, the graph
+update, the candidate filter, seeding, the search and the commit all run in
+the library's HIP kernels on the GPU.  Inputs may be numpy arrays (host
+memory) or torch tensors on the context's device; torch is used for device
+memory and streams only.
+
+    ctx = Context(device=0)
+    ctx.load_graph(row_ptr, col, labels)
+    qid = ctx.register_query(k, qlabels, qedges)
+    res = ctx.apply_batch(src, dst, op, tuples=True)
+    res.count(qid, +1), res.tuples
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import capi
+from .capi import (F_CANONICAL, F_COUNT, F_HASH, F_PER_UPDATE, F_SEED_ATTR, F_TUPLES, GAMMA_MEM_DEVICE,
+                   GAMMA_MEM_HOST)
+
+__all__ = ["Context", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch"]
+
+
+class GammaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (status %d)" % (message, status))
+        self.status = status
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _arg(x, dtype):
+    """(pointer, keepalive, where) for a numpy array or a torch tensor."""
+    if x is None:
+        return None, None, GAMMA_MEM_HOST
+    if _is_torch(x):
+        if x.is_cuda:
+            t = x.contiguous()
+            return ctypes.c_void_p(t.data_ptr()), t, GAMMA_MEM_DEVICE
+        x = x.cpu().numpy()
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), a, GAMMA_MEM_HOST
+
+
+def _check(lib, ctx_ptr, st: int, what: str):
+    if st < 0:
+        msg = lib.gamma_last_error(ctx_ptr) if ctx_ptr else lib.gamma_status_string(st)
+        raise GammaError(st, "%s: %s" % (what, (msg or b"").decode()))
+    return st
+
+
+@dataclass
+class BatchOutput:
+    status: int
+    counts: np.ndarray        # [n_queries, 2] (index 1 = insertion results, 0 = deletion results)
+    hash_sum: np.ndarray      # [n_queries, 2]
+    hash_xor: np.ndarray      # [n_queries, 2]
+    n_tuples: int
+    n_tuples_found: int
+    tuples: Optional[np.ndarray] = None   # [n_tuples, width] external ids, 0xFFFFFFFF padded
+    meta: Optional[np.ndarray] = None     # [n_tuples] qid << 1 | sign
+    ord: Optional[np.ndarray] = None      # [n_tuples] seed ord
+    canon_lo: Optional[np.ndarray] = None
+    canon_hi: Optional[np.ndarray] = None
+    canon_sign: Optional[np.ndarray] = None
+    upd_count: Optional[np.ndarray] = None
+    upd_hash_sum: Optional[np.ndarray] = None
+    upd_hash_xor: Optional[np.ndarray] = None
+    stats: dict = field(default_factory=dict)
+
+    @property
+    def truncated(self) -> bool:
+        return self.status == capi.GAMMA_TRUNCATED
+
+    def count(self, qid: int, sign: int) -> int:
+        return int(self.counts[qid, 1 if sign > 0 else 0])
+
+    def tuple_set(self, qid: int, sign: int, k: int) -> set:
+        """Set of match tuples of one query and sign (requires tuples=True)."""
+        if self.tuples is None:
+            raise ValueError("tuples were not requested")
+        sel = self.meta == ((qid << 1) | (1 if sign > 0 else 0))
+        rows = self.tuples[sel][:, :k]
+        return {tuple(int(v) for v in r) for r in rows}
+
+
+class Context:
+    """A device context holding one dynamic data graph and its standing queries."""
+
+    def __init__(self, device: int = 0, stream=None, tuple_capacity: int = 0, waves_per_cu: int = 0,
+                 steal: Optional[bool] = None):
+        self._lib = capi.load_library()
+        opt = capi.Options()
+        opt.device = device
+        if stream is not None:
+            opt.stream = ctypes.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+        opt.tuple_capacity = int(tuple_capacity)
+        opt.waves_per_cu = int(waves_per_cu)
+        if steal is not None:
+            opt.steal = 1 if steal else 0
+            opt.steal_set = 1
+        self._ptr = ctypes.c_void_p()
+        st = self._lib.gamma_create(ctypes.byref(opt), ctypes.byref(self._ptr))
+        if st < 0:
+            raise GammaError(st, "gamma_create: %s" % self._lib.gamma_status_string(st).decode())
+        self.tuple_capacity = int(tuple_capacity)
+        self.query_k: List[int] = []
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            self._lib.gamma_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ calls
+
+    def load_graph(self, row_ptr, col, labels):
+        rp, k1, w1 = _arg(row_ptr, np.uint64)
+        cl, k2, w2 = _arg(col, np.uint32)
+        lb, k3, w3 = _arg(labels, np.uint32)
+        if len({w1, w2, w3}) != 1:
+            raise ValueError("row_ptr, col and labels must all be host arrays or all device tensors")
+        n = int(k3.shape[0])
+        nnz = int(k2.shape[0])
+        _check(self._lib, self._ptr, self._lib.gamma_load_graph(self._ptr, n, nnz, rp, cl if nnz else None, lb, w1),
+               "load_graph")
+
+    def register_query(self, k: int, labels, edges) -> int:
+        ql = np.ascontiguousarray(np.asarray(labels), dtype=np.uint32)
+        qe = np.ascontiguousarray(np.asarray(edges), dtype=np.uint32).reshape(-1)
+        qid = ctypes.c_uint32()
+        _check(self._lib, self._ptr,
+               self._lib.gamma_register_query(self._ptr, int(k), ql.ctypes.data_as(ctypes.c_void_p),
+                                              int(qe.shape[0] // 2), qe.ctypes.data_as(ctypes.c_void_p),
+                                              ctypes.byref(qid)),
+               "register_query")
+        self.query_k.append(int(k))
+        return int(qid.value)
+
+    def apply_batch(self, src, dst, op, hash: bool = True, tuples: bool = False, seed_attr: bool = False,
+                    per_update: bool = False, canonical: bool = False) -> BatchOutput:
+        s, k1, w1 = _arg(src, np.uint32)
+        d, k2, w2 = _arg(dst, np.uint32)
+        o, k3, w3 = _arg(op, np.uint8)
+        if len({w1, w2, w3}) != 1:
+            raise ValueError("src, dst and op must all be host arrays or all device tensors")
+        n_upd = int(k1.shape[0])
+        flags = F_COUNT
+        flags |= F_HASH if hash else 0
+        flags |= F_TUPLES if tuples else 0
+        flags |= F_SEED_ATTR if seed_attr else 0
+        flags |= F_PER_UPDATE if per_update else 0
+        flags |= F_CANONICAL if canonical else 0
+        res = capi.BatchResult()
+        st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                         o if n_upd else None, w1, flags, ctypes.byref(res))
+        _check(self._lib, self._ptr, st, "apply_batch")
+        nq = int(res.n_queries)
+        counts = np.zeros((nq, 2), dtype=np.uint64)
+        hs = np.zeros((nq, 2), dtype=np.uint64)
+        hx = np.zeros((nq, 2), dtype=np.uint64)
+        for i in range(nq):
+            q = res.queries[i]
+            for sg in range(2):
+                counts[i, sg] = q.count[sg]
+                hs[i, sg] = q.hash_sum[sg]
+                hx[i, sg] = q.hash_xor[sg]
+        out = BatchOutput(status=int(st), counts=counts, hash_sum=hs, hash_xor=hx, n_tuples=int(res.n_tuples),
+                          n_tuples_found=int(res.n_tuples_found))
+        nc = int(res.n_canonical)
+        if canonical and nc:
+            out.canon_lo = np.ctypeslib.as_array(res.canon_lo, (nc,)).copy()
+            out.canon_hi = np.ctypeslib.as_array(res.canon_hi, (nc,)).copy()
+            out.canon_sign = np.ctypeslib.as_array(res.canon_sign, (nc,)).copy()
+        elif canonical:
+            out.canon_lo = np.zeros(0, np.uint32)
+            out.canon_hi = np.zeros(0, np.uint32)
+            out.canon_sign = np.zeros(0, np.uint8)
+        if per_update:
+            if nc:
+                out.upd_count = np.ctypeslib.as_array(res.upd_count, (nc,)).copy()
+                out.upd_hash_sum = np.ctypeslib.as_array(res.upd_hash_sum, (nc,)).copy()
+                out.upd_hash_xor = np.ctypeslib.as_array(res.upd_hash_xor, (nc,)).copy()
+            else:
+                out.upd_count = out.upd_hash_sum = out.upd_hash_xor = np.zeros(0, np.uint64)
+        if tuples:
+            nt, w = int(res.n_tuples), int(res.tuple_width)
+            t = np.zeros((nt, w), dtype=np.uint32)
+            m = np.zeros(nt, dtype=np.uint32)
+            od = np.zeros(nt, dtype=np.uint32) if seed_attr else None
+            if nt:
+                _check(self._lib, self._ptr,
+                       self._lib.gamma_copy_tuples(self._ptr, t.ctypes.data_as(ctypes.c_void_p),
+                                                   m.ctypes.data_as(ctypes.c_void_p),
+                                                   od.ctypes.data_as(ctypes.c_void_p) if od is not None else None,
+                                                   nt, GAMMA_MEM_HOST),
+                       "copy_tuples")
+            out.tuples, out.meta, out.ord = t, m, od
+        stt = res.stats
+        out.stats = {name: getattr(stt, name) for name, _ in capi.BatchStats._fields_ if not name.startswith("reserved")}
+        return out
+
+    def export_graph(self):
+        n = ctypes.c_uint32()
+        nnz = ctypes.c_uint64()
+        _check(self._lib, self._ptr,
+               self._lib.gamma_export_graph(self._ptr, ctypes.byref(n), ctypes.byref(nnz), None, None, None),
+               "export_graph")
+        rp = np.zeros(n.value + 1, dtype=np.uint64)
+        col = np.zeros(max(nnz.value, 1), dtype=np.uint32)
+        lab = np.zeros(n.value, dtype=np.uint32)
+        _check(self._lib, self._ptr,
+               self._lib.gamma_export_graph(self._ptr, ctypes.byref(n), ctypes.byref(nnz),
+                                            rp.ctypes.data_as(ctypes.c_void_p), col.ctypes.data_as(ctypes.c_void_p),
+                                            lab.ctypes.data_as(ctypes.c_void_p)),
+               "export_graph")
+        return rp, col[: nnz.value], lab
+
+
+def validate_graph(row_ptr, col, labels) -> int:
+    lib = capi.load_library()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+    cl = np.ascontiguousarray(col, dtype=np.uint32)
+    lb = np.ascontiguousarray(labels, dtype=np.uint32)
+    return int(lib.gamma_validate_graph(int(lb.shape[0]), int(cl.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
+                                        cl.ctypes.data_as(ctypes.c_void_p), lb.ctypes.data_as(ctypes.c_void_p)))
+
+
+def validate_query(k, labels, edges) -> int:
+    lib = capi.load_library()
+    ql = np.ascontiguousarray(labels, dtype=np.uint32)
+    qe = np.ascontiguousarray(edges, dtype=np.uint32).reshape(-1)
+    return int(lib.gamma_validate_query(int(k), ql.ctypes.data_as(ctypes.c_void_p), int(qe.shape[0] // 2),
+                                        qe.ctypes.data_as(ctypes.c_void_p)))
+
+
+def validate_batch(n, src, dst, op) -> int:
+    lib = capi.load_library()
+    s = np.ascontiguousarray(src, dtype=np.uint32)
+    d = np.ascontiguousarray(dst, dtype=np.uint32)
+    o = np.ascontiguousarray(op, dtype=np.uint8)
+    return int(lib.gamma_validate_batch(int(n), int(s.shape[0]), s.ctypes.data_as(ctypes.c_void_p),
+                                        d.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p)))

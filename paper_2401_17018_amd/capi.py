@@ -1,0 +1,147 @@
+"""ctypes declarations of the C ABI in include/gamma.h (argument marshalling only).
+
+The shared library is built in-tree (paper_2401_17018_amd/libgamma.so) by
+``paper_2401_17018_amd.build``.  There is no fallback: if the library is
+missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgamma.so")
+
+GAMMA_OK, GAMMA_TRUNCATED = 0, 1
+GAMMA_EINVAL, GAMMA_ECONFLICT, GAMMA_ENOMEM, GAMMA_EUNSUPPORTED = -1, -2, -3, -4
+GAMMA_ESTATE, GAMMA_ETIMEDOUT, GAMMA_EDEVICE = -5, -6, -7
+
+GAMMA_MEM_HOST, GAMMA_MEM_DEVICE = 0, 1
+
+F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL = 1, 2, 4, 8, 16, 32
+
+# every function declared in include/gamma.h
+EXPORTS = [
+    "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
+    "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
+    "gamma_validate_query", "gamma_validate_batch", "gamma_status_string", "gamma_last_error",
+    "gamma_version",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+        ("tuple_capacity", ctypes.c_uint64),
+        ("waves_per_cu", ctypes.c_uint32),
+        ("steal", ctypes.c_uint32),
+        ("steal_set", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 8),
+    ]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [
+        ("qid", ctypes.c_uint32),
+        ("k", ctypes.c_uint32),
+        ("count", ctypes.c_uint64 * 2),
+        ("hash_sum", ctypes.c_uint64 * 2),
+        ("hash_xor", ctypes.c_uint64 * 2),
+    ]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("n_input", ctypes.c_uint32),
+        ("n_canonical", ctypes.c_uint32),
+        ("n_insert", ctypes.c_uint32),
+        ("n_delete", ctypes.c_uint32),
+        ("n_noop", ctypes.c_uint32),
+        ("n_duplicate", ctypes.c_uint32),
+        ("n_touched", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("n_seeds", ctypes.c_uint64),
+        ("dfs_nodes", ctypes.c_uint64),
+        ("steals", ctypes.c_uint64),
+        ("cand_scanned", ctypes.c_uint64),
+        ("bytes_alg_dfs", ctypes.c_uint64),
+        ("bytes_alg_update", ctypes.c_uint64),
+        ("ms_canon", ctypes.c_float),
+        ("ms_merge", ctypes.c_float),
+        ("ms_filter", ctypes.c_float),
+        ("ms_seed", ctypes.c_float),
+        ("ms_dfs", ctypes.c_float),
+        ("ms_commit", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+        ("reserved1", ctypes.c_float),
+    ]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [
+        ("n_queries", ctypes.c_uint32),
+        ("tuple_width", ctypes.c_uint32),
+        ("queries", ctypes.POINTER(QueryResult)),
+        ("n_tuples", ctypes.c_uint64),
+        ("n_tuples_found", ctypes.c_uint64),
+        ("tuples", ctypes.c_void_p),
+        ("meta", ctypes.c_void_p),
+        ("ord", ctypes.c_void_p),
+        ("n_canonical", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32),
+        ("canon_lo", ctypes.POINTER(ctypes.c_uint32)),
+        ("canon_hi", ctypes.POINTER(ctypes.c_uint32)),
+        ("canon_sign", ctypes.POINTER(ctypes.c_uint8)),
+        ("upd_count", ctypes.POINTER(ctypes.c_uint64)),
+        ("upd_hash_sum", ctypes.POINTER(ctypes.c_uint64)),
+        ("upd_hash_xor", ctypes.POINTER(ctypes.c_uint64)),
+        ("stats", BatchStats),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgamma.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgamma.so is not built (%s); run __graft_entry__.build() or "
+                           "python paper_2401_17018_amd/build.py" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+    lib.gamma_create.restype = st
+    lib.gamma_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(P)]
+    lib.gamma_destroy.restype = st
+    lib.gamma_destroy.argtypes = [P]
+    lib.gamma_load_graph.restype = st
+    lib.gamma_load_graph.argtypes = [P, u32, u64, P, P, P, ctypes.c_int]
+    lib.gamma_register_query.restype = st
+    lib.gamma_register_query.argtypes = [P, u32, P, u32, P, ctypes.POINTER(u32)]
+    lib.gamma_apply_batch.restype = st
+    lib.gamma_apply_batch.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, ctypes.POINTER(BatchResult)]
+    lib.gamma_copy_tuples.restype = st
+    lib.gamma_copy_tuples.argtypes = [P, P, P, P, u64, ctypes.c_int]
+    lib.gamma_result_release.restype = st
+    lib.gamma_result_release.argtypes = [P, ctypes.POINTER(BatchResult)]
+    lib.gamma_export_graph.restype = st
+    lib.gamma_export_graph.argtypes = [P, ctypes.POINTER(u32), ctypes.POINTER(u64), P, P, P]
+    lib.gamma_validate_graph.restype = st
+    lib.gamma_validate_graph.argtypes = [u32, u64, P, P, P]
+    lib.gamma_validate_query.restype = st
+    lib.gamma_validate_query.argtypes = [u32, P, u32, P]
+    lib.gamma_validate_batch.restype = st
+    lib.gamma_validate_batch.argtypes = [u32, u32, P, P, P]
+    lib.gamma_status_string.restype = ctypes.c_char_p
+    lib.gamma_status_string.argtypes = [st]
+    lib.gamma_last_error.restype = ctypes.c_char_p
+    lib.gamma_last_error.argtypes = [P]
+    lib.gamma_version.restype = u32
+    lib.gamma_version.argtypes = []
+    _lib = lib
+    return lib

@@ -1,0 +1,175 @@
+// Query validation, matching-order planning and filter tables (host).
+#include "host_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <set>
+
+#include "../../include/gamma.h"
+
+namespace gm {
+
+int validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges,
+                   std::string* msg) {
+  if (k < 2 || k > GM_MAX_K) {
+    if (msg) *msg = "query size k must be in [2, 16]";
+    return k > GM_MAX_K ? GAMMA_EUNSUPPORTED : GAMMA_EINVAL;
+  }
+  if (!qlabels || !qedges) {
+    if (msg) *msg = "null query array";
+    return GAMMA_EINVAL;
+  }
+  if (m < k - 1 || m > k * (k - 1) / 2) {
+    if (msg) *msg = "edge count out of range for a connected simple query";
+    return GAMMA_EINVAL;
+  }
+  for (uint32_t u = 0; u < k; ++u)
+    if (qlabels[u] > 0xFFFFu) {
+      if (msg) *msg = "query label >= 65536";
+      return GAMMA_EINVAL;
+    }
+  std::set<std::pair<uint32_t, uint32_t>> seen;
+  std::vector<std::vector<uint32_t>> adj(k);
+  for (uint32_t e = 0; e < m; ++e) {
+    uint32_t a = qedges[2 * e], b = qedges[2 * e + 1];
+    if (a >= k || b >= k || a == b) {
+      if (msg) *msg = "query edge endpoint out of range or self loop";
+      return GAMMA_EINVAL;
+    }
+    auto key = std::make_pair(std::min(a, b), std::max(a, b));
+    if (!seen.insert(key).second) {
+      if (msg) *msg = "repeated query edge";
+      return GAMMA_EINVAL;
+    }
+    adj[a].push_back(b);
+    adj[b].push_back(a);
+  }
+  std::vector<char> vis(k, 0);
+  std::vector<uint32_t> st{0};
+  vis[0] = 1;
+  uint32_t cnt = 1;
+  while (!st.empty()) {
+    uint32_t v = st.back();
+    st.pop_back();
+    for (uint32_t w : adj[v])
+      if (!vis[w]) {
+        vis[w] = 1;
+        ++cnt;
+        st.push_back(w);
+      }
+  }
+  if (cnt != k) {
+    if (msg) *msg = "query is not connected";
+    return GAMMA_EUNSUPPORTED;
+  }
+  return GAMMA_OK;
+}
+
+void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& label_count) {
+  const uint32_t k = q.k;
+  std::vector<uint32_t> adjm(k, 0), deg(k, 0);
+  for (auto& e : q.edges) {
+    adjm[e.first] |= 1u << e.second;
+    adjm[e.second] |= 1u << e.first;
+    deg[e.first]++;
+    deg[e.second]++;
+  }
+  auto lcount = [&](uint32_t u) -> uint64_t {
+    uint32_t l = q.labels[u];
+    return l < label_count.size() ? label_count[l] : 0;
+  };
+  q.plans.clear();
+  std::vector<std::pair<uint32_t, uint32_t>> dirs;
+  for (auto& e : q.edges) {
+    dirs.push_back({e.first, e.second});
+    dirs.push_back({e.second, e.first});
+  }
+  for (auto& d : dirs) {
+    GmPlan p;
+    std::memset(&p, 0, sizeof(p));
+    p.k = (uint8_t)k;
+    p.x = (uint8_t)d.first;
+    p.y = (uint8_t)d.second;
+    p.q = qindex;
+    uint32_t matched = (1u << d.first) | (1u << d.second);
+    p.order[0] = (uint8_t)d.first;
+    p.order[1] = (uint8_t)d.second;
+    for (uint32_t l = 2; l < k; ++l) {
+      int best = -1;
+      for (uint32_t u = 0; u < k; ++u) {
+        if (matched & (1u << u)) continue;
+        uint32_t mn = __builtin_popcount(adjm[u] & matched);
+        if (mn == 0) continue;
+        if (best < 0) {
+          best = (int)u;
+          continue;
+        }
+        uint32_t bm = __builtin_popcount(adjm[best] & matched);
+        if (mn != bm) {
+          if (mn > bm) best = (int)u;
+          continue;
+        }
+        if (deg[u] != deg[best]) {
+          if (deg[u] > deg[best]) best = (int)u;
+          continue;
+        }
+        if (lcount(u) != lcount(best)) {
+          if (lcount(u) < lcount(best)) best = (int)u;
+          continue;
+        }
+      }
+      p.order[l] = (uint8_t)best;
+      matched |= 1u << best;
+    }
+    uint32_t bofs = 0;
+    uint32_t placed = 0;
+    for (uint32_t l = 0; l < k; ++l) {
+      uint32_t u = p.order[l];
+      p.pos[u] = (uint8_t)l;
+      p.lab[l] = (uint16_t)q.labels[u];
+      p.back[l] = (uint16_t)(l >= 2 ? (adjm[u] & placed) : 0);
+      p.bofs[l] = (uint8_t)bofs;
+      if (l >= 2) bofs += __builtin_popcount(p.back[l]);
+      placed |= 1u << u;
+    }
+    q.plans.push_back(p);
+  }
+}
+
+void build_filter_tables(const std::vector<HostQuery>& qs, uint32_t label_slots,
+                         std::vector<uint32_t>& lab_fstart, std::vector<GmFilterEntry>& entries,
+                         std::vector<GmReq>& reqs) {
+  std::vector<std::vector<GmFilterEntry>> per_label(label_slots);
+  reqs.clear();
+  for (uint32_t qi = 0; qi < qs.size(); ++qi) {
+    const HostQuery& q = qs[qi];
+    std::vector<std::map<uint32_t, uint32_t>> need(q.k);
+    for (auto& e : q.edges) {
+      need[e.first][q.labels[e.second]]++;
+      need[e.second][q.labels[e.first]]++;
+    }
+    for (uint32_t u = 0; u < q.k; ++u) {
+      uint32_t lab = q.labels[u];
+      if (lab >= label_slots) continue;  // no data vertex carries this label
+      GmFilterEntry fe;
+      fe.q = qi;
+      fe.u = u;
+      fe.req_off = (uint32_t)reqs.size();
+      fe.req_n = (uint32_t)need[u].size();
+      for (auto& kv : need[u]) reqs.push_back(GmReq{(uint16_t)kv.first, (uint16_t)kv.second});
+      per_label[lab].push_back(fe);
+    }
+  }
+  lab_fstart.assign(label_slots + 1, 0);
+  entries.clear();
+  for (uint32_t l = 0; l < label_slots; ++l) {
+    lab_fstart[l] = (uint32_t)entries.size();
+    for (auto& fe : per_label[l]) entries.push_back(fe);
+  }
+  lab_fstart[label_slots] = (uint32_t)entries.size();
+  if (reqs.empty()) reqs.push_back(GmReq{0, 0});
+  if (entries.empty()) entries.push_back(GmFilterEntry{0, 0, 0, 0});
+}
+
+}  // namespace gm

@@ -1,0 +1,132 @@
+// Candidate filter and seed generation.
+//
+// Filter (Sec. IV-B): data vertex v is a candidate of query vertex u when
+// L(v) = L(u) and, for every label l among u's query neighbours, v has at
+// least as many neighbours of label l as u has.  The paper packs these
+// counts into saturating per-label bit fields and ANDs codes; here the exact
+// counts are compared, which accepts the same vertices or fewer and is still
+// sound (every vertex of a match passes).  Because internal ids are grouped
+// by label, |N^l(v)| is the length of a subrange of v's sorted row: two
+// binary searches, no scan.  One bit per query vertex, one uint16 per
+// (query, data vertex): the candidate table of Sec. IV-B.  During a batch the
+// touched rows hold G u I, whose counts bound those of G and of G' from
+// above, so the filter stays sound for both search passes.
+//
+// Seeds (Algorithm 1, the loop over query edges and its label test): for
+// every canonical batch edge (a, b) and every directed query edge (x, y) of
+// every query, (x -> a, y -> b) is a seed when a is a candidate of x and b of
+// y.  Both orientations of each query edge are plans of their own.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace {
+
+__device__ inline uint32_t lb_masked(const uint32_t* col, uint64_t a, uint32_t len, uint32_t key) {
+  uint32_t lo = 0, hi = len;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if ((col[a + mid] & GM_IDMASK) < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_filter(GmGraphDev G, const uint32_t* __restrict__ verts, uint32_t nv,
+                         const uint32_t* __restrict__ lab_fstart, const GmFilterEntry* __restrict__ fe,
+                         const GmReq* __restrict__ reqs, uint16_t* __restrict__ cand, uint32_t only_q) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+    const uint32_t v = verts ? verts[i] : i;
+    const uint32_t lab = G.vlabel[v];
+    if (lab >= G.label_slots) continue;
+    const uint32_t e0 = lab_fstart[lab], e1 = lab_fstart[lab + 1];
+    if (e0 == e1) continue;
+    const uint64_t off = G.row_off[v];
+    const uint32_t len = G.row_len[v];
+    uint32_t cur_q = 0xFFFFFFFFu;
+    uint32_t mask = 0;
+    for (uint32_t e = e0; e < e1; ++e) {
+      const GmFilterEntry E = fe[e];
+      if (only_q != 0xFFFFFFFFu && E.q != only_q) continue;
+      if (E.q != cur_q) {
+        if (cur_q != 0xFFFFFFFFu) cand[(uint64_t)cur_q * G.n + v] = (uint16_t)mask;
+        cur_q = E.q;
+        mask = 0;
+      }
+      bool ok = true;
+      for (uint32_t r = 0; r < E.req_n && ok; ++r) {
+        const GmReq R = reqs[E.req_off + r];
+        uint32_t have = 0;
+        if (R.lab < G.label_slots) {
+          uint32_t s0 = lb_masked(G.col, off, len, G.label_start[R.lab]);
+          uint32_t s1 = lb_masked(G.col, off, len, G.label_start[R.lab + 1]);
+          have = s1 - s0;
+        }
+        ok = have >= R.cnt;
+      }
+      if (ok) mask |= 1u << E.u;
+    }
+    if (cur_q != 0xFFFFFFFFu) cand[(uint64_t)cur_q * G.n + v] = (uint16_t)mask;
+  }
+}
+
+// Thread per (canonical batch edge, query).
+__global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __restrict__ canon_b,
+                        const uint8_t* __restrict__ canon_sign, uint32_t n_canon,
+                        const GmQueryDev* __restrict__ qs, uint32_t nq, const GmPlan* __restrict__ plans,
+                        const uint16_t* __restrict__ cand, uint32_t n, GmSeed* __restrict__ seeds,
+                        uint64_t cap, GmCounters* ctr) {
+  const uint64_t total = (uint64_t)n_canon * nq;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t o = (uint32_t)(w / nq), q = (uint32_t)(w % nq);
+    const uint32_t a = canon_a[o], b = canon_b[o];
+    const uint32_t ca = cand[(uint64_t)q * n + a], cb = cand[(uint64_t)q * n + b];
+    if (!ca || !cb) continue;
+    const GmQueryDev Q = qs[q];
+    for (uint32_t d = 0; d < Q.n_plans; ++d) {
+      const GmPlan& P = plans[Q.plan_base + d];
+      if (((ca >> P.x) & 1u) && ((cb >> P.y) & 1u)) {
+        unsigned long long pos = atomicAdd(&ctr->n_seeds, 1ull);
+        if (pos < cap) {
+          GmSeed sd;
+          sd.qd = (q << 8) | d;
+          sd.os = (o << 1) | canon_sign[o];
+          sd.a = a;
+          sd.b = b;
+          seeds[pos] = sd;
+        }
+      }
+    }
+  }
+}
+
+unsigned grid_for(uint64_t work, unsigned per_block) {
+  uint64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+namespace gm {
+
+void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,
+                   const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
+                   hipStream_t s) {
+  if (!nv) return;
+  k_filter<<<grid_for(nv, 256), 256, 0, s>>>(G, verts, nv, lab_fstart, fe, reqs, cand, only_q);
+}
+
+void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
+                  uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
+                  const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
+                  hipStream_t s) {
+  if (!n_canon || !nq) return;
+  k_seeds<<<grid_for((uint64_t)n_canon * nq, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, n_canon,
+                                                                qs, nq, plans, cand, n, seeds, cap, ctr);
+}
+
+}  // namespace gm

@@ -1,0 +1,244 @@
+// Graph loading, relabelling and arena maintenance.
+//
+// Data layout (device):
+//   Vertices are renumbered so that internal ids are grouped by label
+//   (internal id = rank of (label, external id)).  Every neighbour list is
+//   sorted by internal id, so the neighbours of one label form a contiguous
+//   subrange: the candidate lists of the search (candidates must carry the
+//   query vertex's label, Def. 2) and the neighbourhood label counts of the
+//   candidate filter (Sec. IV-B) are found by binary search instead of a scan.
+//   Row v lives at col[row_off[v] .. row_off[v] + row_len[v]) in an arena; a
+//   batch writes the rows it changes to fresh arena space (Sec. V-C replaces
+//   the paper's packed memory array).
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace {
+
+__device__ inline uint64_t lower_bound_u32(const uint32_t* p, uint64_t lo, uint64_t hi, uint32_t key) {
+  while (lo < hi) {
+    uint64_t mid = lo + ((hi - lo) >> 1);
+    if ((p[mid] & GM_IDMASK) < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One wave per vertex: offsets, order, range, self loops, symmetry, labels.
+__global__ __launch_bounds__(256) void k_validate_csr(const uint64_t* __restrict__ rp,
+                                                      const uint32_t* __restrict__ col,
+                                                      const uint32_t* __restrict__ labels,
+                                                      uint32_t n, uint64_t nnz,
+                                                      uint32_t* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t v = gw; v < n; v += nw) {
+    uint64_t a = rp[v], b = rp[v + 1];
+    if (lane == 0) {
+      if (labels[v] > 0xFFFFu) atomicOr(err, GM_ERR_RANGE);
+      if (v == 0 && a != 0) atomicOr(err, GM_ERR_CSR);
+      if (v == n - 1 && b != nnz) atomicOr(err, GM_ERR_CSR);
+    }
+    if (a > b || b > nnz) {
+      if (lane == 0) atomicOr(err, GM_ERR_CSR);
+      continue;
+    }
+    for (uint64_t j = a + lane; j < b; j += 64) {
+      uint32_t x = col[j];
+      uint32_t e = 0;
+      if (x >= n) {
+        e |= GM_ERR_RANGE;
+      } else {
+        if (x == v) e |= GM_ERR_SELFLOOP;
+        if (j > a && col[j - 1] >= x) e |= GM_ERR_CSR;
+        uint64_t xa = rp[x], xb = rp[x + 1];
+        if (xa > xb || xb > nnz) {
+          e |= GM_ERR_CSR;
+        } else {
+          uint64_t p = lower_bound_u32(col, xa, xb, (uint32_t)v);
+          if (p >= xb || col[p] != (uint32_t)v) e |= GM_ERR_CSR;
+        }
+      }
+      if (e) atomicOr(err, e);
+    }
+  }
+}
+
+__global__ void k_relabel_keys(const uint32_t* __restrict__ labels, uint32_t n,
+                               uint64_t* __restrict__ keys) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    keys[v] = ((uint64_t)(labels[v] & 0xFFFFu) << 32) | v;
+}
+
+__global__ void k_relabel_apply(const uint64_t* __restrict__ sorted, uint32_t n,
+                                uint32_t* __restrict__ new_of_old, uint32_t* __restrict__ old_of_new,
+                                uint16_t* __restrict__ vlabel) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t key = sorted[p];
+    uint32_t v = (uint32_t)key;
+    new_of_old[v] = (uint32_t)p;
+    old_of_new[p] = v;
+    vlabel[p] = (uint16_t)(key >> 32);
+  }
+}
+
+// label_start[l] = first internal id whose label is >= l, for l in [0, slots].
+__global__ void k_label_start(const uint16_t* __restrict__ vlabel, uint32_t n, uint32_t slots,
+                              uint32_t* __restrict__ label_start) {
+  for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l <= slots; l += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+      uint32_t mid = lo + ((hi - lo) >> 1);
+      if (vlabel[mid] < l)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    label_start[l] = lo;
+  }
+}
+
+// Keys map[src] << idbits | map[dst] for every entry of a CSR (one wave per row).
+// With flag_aware, entries carry the batch flag bit, which is stripped.
+__global__ __launch_bounds__(256) void k_csr_keys(const uint64_t* __restrict__ row_off,
+                                                  const uint32_t* __restrict__ row_len,
+                                                  const uint64_t* __restrict__ rp,
+                                                  const uint32_t* __restrict__ col,
+                                                  const uint32_t* __restrict__ map, uint32_t n,
+                                                  int idbits, const uint64_t* __restrict__ out_off,
+                                                  uint64_t* __restrict__ keys) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t v = gw; v < n; v += nw) {
+    uint64_t a, len;
+    if (rp) {
+      a = rp[v];
+      len = rp[v + 1] - a;
+    } else {
+      a = row_off[v];
+      len = row_len[v];
+    }
+    uint64_t src = (uint64_t)map[v] << idbits;
+    uint64_t o = out_off ? out_off[v] : a;
+    for (uint64_t j = lane; j < len; j += 64) keys[o + j] = src | map[col[a + j] & GM_IDMASK];
+  }
+}
+
+__global__ void k_csr_extract(const uint64_t* __restrict__ keys, uint64_t nnz, uint64_t idmask,
+                              uint32_t* __restrict__ col_out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    col_out[i] = (uint32_t)(keys[i] & idmask);
+}
+
+// deg_out[map[v]] = degree of v (from a CSR row_ptr or from row_len).
+__global__ void k_deg_mapped(const uint64_t* __restrict__ rp, const uint32_t* __restrict__ row_len,
+                             const uint32_t* __restrict__ map, uint32_t n,
+                             uint64_t* __restrict__ deg_out) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t d = rp ? rp[v + 1] - rp[v] : row_len[v];
+    deg_out[map ? map[v] : v] = d;
+  }
+}
+
+__global__ void k_rows_from_scan(const uint64_t* __restrict__ offs, const uint64_t* __restrict__ deg,
+                                 uint32_t n, uint64_t base, uint64_t* __restrict__ row_off,
+                                 uint32_t* __restrict__ row_len) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x) {
+    row_off[v] = base + offs[v];
+    if (row_len) row_len[v] = (uint32_t)deg[v];
+  }
+}
+
+// Copy every row to its new offset (one wave per row).
+__global__ __launch_bounds__(256) void k_copy_rows(const uint64_t* __restrict__ row_off,
+                                                   const uint32_t* __restrict__ row_len,
+                                                   const uint32_t* __restrict__ src,
+                                                   const uint64_t* __restrict__ new_off,
+                                                   uint32_t* __restrict__ dst, uint32_t n) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t v = gw; v < n; v += nw) {
+    uint64_t a = row_off[v], o = new_off[v];
+    uint32_t len = row_len[v];
+    for (uint32_t j = lane; j < len; j += 64) dst[o + j] = src[a + j];
+  }
+}
+
+__global__ void k_u32_to_u64(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint32_t n) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    out[v] = in[v];
+}
+
+unsigned grid_for(uint64_t work, unsigned per_block) {
+  uint64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+namespace gm {
+
+void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, uint32_t n,
+                         uint64_t nnz, uint32_t* err, hipStream_t s) {
+  k_validate_csr<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(rp, col, labels, n, nnz, err);
+}
+
+void launch_relabel_keys(const uint32_t* labels, uint32_t n, uint64_t* keys, hipStream_t s) {
+  k_relabel_keys<<<grid_for(n, 256), 256, 0, s>>>(labels, n, keys);
+}
+
+void launch_relabel_apply(const uint64_t* sorted, uint32_t n, uint32_t* new_of_old,
+                          uint32_t* old_of_new, uint16_t* vlabel, hipStream_t s) {
+  k_relabel_apply<<<grid_for(n, 256), 256, 0, s>>>(sorted, n, new_of_old, old_of_new, vlabel);
+}
+
+void launch_label_start(const uint16_t* vlabel, uint32_t n, uint32_t slots, uint32_t* label_start,
+                        hipStream_t s) {
+  k_label_start<<<grid_for((uint64_t)slots + 1, 256), 256, 0, s>>>(vlabel, n, slots, label_start);
+}
+
+void launch_csr_keys(const uint64_t* row_off, const uint32_t* row_len, const uint64_t* rp,
+                     const uint32_t* col, const uint32_t* map, uint32_t n, int idbits,
+                     const uint64_t* out_off, uint64_t* keys, hipStream_t s) {
+  k_csr_keys<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(row_off, row_len, rp, col, map, n, idbits,
+                                                            out_off, keys);
+}
+
+void launch_csr_extract(const uint64_t* keys, uint64_t nnz, uint64_t idmask, uint32_t* col_out,
+                        hipStream_t s) {
+  k_csr_extract<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, idmask, col_out);
+}
+
+void launch_deg_mapped(const uint64_t* rp, const uint32_t* row_len, const uint32_t* map, uint32_t n,
+                       uint64_t* deg_out, hipStream_t s) {
+  k_deg_mapped<<<grid_for(n, 256), 256, 0, s>>>(rp, row_len, map, n, deg_out);
+}
+
+void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n, uint64_t base,
+                           uint64_t* row_off, uint32_t* row_len, hipStream_t s) {
+  k_rows_from_scan<<<grid_for(n, 256), 256, 0, s>>>(offs, deg, n, base, row_off, row_len);
+}
+
+void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
+                      const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s) {
+  k_copy_rows<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(row_off, row_len, src, new_off, dst, n);
+}
+
+void launch_u32_to_u64(const uint32_t* in, uint64_t* out, uint32_t n, hipStream_t s) {
+  k_u32_to_u64<<<grid_for(n, 256), 256, 0, s>>>(in, out, n);
+}
+
+}  // namespace gm

@@ -1,0 +1,124 @@
+// Host-callable launchers of the device kernels, and the parameter blocks
+// they take.  Internal to the library.
+#pragma once
+
+#include "dev_common.h"
+
+// The dynamic graph as the kernels see it (internal, label-grouped ids).
+struct GmGraphDev {
+  uint32_t n;
+  int32_t idbits;                 // bits needed for an id < n
+  uint64_t* row_off;              // [n]
+  uint32_t* row_len;              // [n]
+  uint32_t* col;                  // arena; bit 31 marks batch entries
+  const uint16_t* vlabel;         // [n]
+  const uint32_t* label_start;    // [label_slots + 1]
+  uint32_t label_slots;           // labels >= label_slots occur nowhere
+  const uint32_t* new_of_old;     // [n] external -> internal
+  const uint32_t* old_of_new;     // [n] internal -> external
+};
+
+// The batch hash: undirected internal edge key -> ord << 1 | sign.
+struct GmBatchHash {
+  uint64_t* keys;
+  uint32_t* vals;
+  uint32_t mask;
+};
+
+// Device counters of one batch (zeroed before each batch).
+struct GmCounters {
+  uint32_t err;
+  uint32_t n_dup;
+  uint32_t n_noop;
+  uint32_t pad;
+  unsigned long long n_seeds;
+  unsigned long long seed_head;
+  unsigned long long tuples_found;
+  unsigned long long dfs_nodes;
+  unsigned long long cand_scanned;
+  unsigned long long bytes_alg;
+  unsigned long long steals;
+  unsigned long long bytes_update;
+};
+
+struct GmDfsParams {
+  GmGraphDev G;
+  const GmPlan* plans;
+  const GmQueryDev* queries;
+  const uint16_t* cand;           // [nq][n]
+  const GmSeed* seeds;
+  GmBatchHash H;
+  GmCounters* ctr;
+  uint32_t flags;
+  uint32_t twidth;
+  unsigned long long* qres;       // [nq][2][3]: count, hash sum, hash xor
+  uint32_t* tuples;
+  uint32_t* tmeta;
+  uint32_t* tord;
+  uint64_t tcap;
+  unsigned long long* upd_res;    // [n_canon][3]
+};
+
+namespace gm {
+
+// graph (k_graph.hip)
+void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, uint32_t n,
+                         uint64_t nnz, uint32_t* err, hipStream_t s);
+void launch_relabel_keys(const uint32_t* labels, uint32_t n, uint64_t* keys, hipStream_t s);
+void launch_relabel_apply(const uint64_t* sorted, uint32_t n, uint32_t* new_of_old,
+                          uint32_t* old_of_new, uint16_t* vlabel, hipStream_t s);
+void launch_label_start(const uint16_t* vlabel, uint32_t n, uint32_t slots, uint32_t* label_start,
+                        hipStream_t s);
+void launch_csr_keys(const uint64_t* row_off, const uint32_t* row_len, const uint64_t* rp,
+                     const uint32_t* col, const uint32_t* map, uint32_t n, int idbits,
+                     const uint64_t* out_off, uint64_t* keys, hipStream_t s);
+void launch_csr_extract(const uint64_t* keys, uint64_t nnz, uint64_t idmask, uint32_t* col_out,
+                        hipStream_t s);
+void launch_deg_mapped(const uint64_t* rp, const uint32_t* row_len, const uint32_t* map, uint32_t n,
+                       uint64_t* deg_out, hipStream_t s);
+void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n, uint64_t base,
+                           uint64_t* row_off, uint32_t* row_len, hipStream_t s);
+void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
+                      const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s);
+void launch_u32_to_u64(const uint32_t* in, uint64_t* out, uint32_t n, hipStream_t s);
+
+// batch (k_batch.hip)
+void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd,
+                       uint32_t n, int eb, uint64_t* keys, GmCounters* ctr, hipStream_t s);
+void launch_canon_classify(const uint64_t* keys, uint32_t n_upd, int eb, GmGraphDev G,
+                           uint32_t* keep, GmCounters* ctr, hipStream_t s);
+void launch_canon_emit(const uint64_t* keys, const uint32_t* keep, const uint32_t* ords,
+                       uint32_t n_upd, int eb, GmGraphDev G, uint32_t* canon_lo, uint32_t* canon_hi,
+                       uint8_t* canon_sign, uint32_t* canon_a, uint32_t* canon_b, GmBatchHash H,
+                       uint64_t* dkeys, hipStream_t s);
+void launch_runs_flags(const uint64_t* dkeys, uint32_t N, int ib, uint64_t* vals, hipStream_t s);
+void launch_runs_fill(const uint64_t* dkeys, const uint64_t* runscan, uint32_t N, int ib,
+                      uint32_t* touched, uint32_t* run_start, uint32_t* run_end, hipStream_t s);
+void launch_touched_sizes(const uint32_t* touched, const uint32_t* run_start, const uint32_t* run_end,
+                          const uint64_t* runscan, uint32_t n_touched, GmGraphDev G, uint64_t* sizes,
+                          hipStream_t s);
+void launch_merge(const uint64_t* dkeys, const uint64_t* runscan, const uint32_t* touched,
+                  const uint32_t* run_start, const uint32_t* run_end, const uint64_t* r1off,
+                  uint32_t n_touched, uint64_t r1_total, uint64_t base1, uint64_t base2, int ib,
+                  GmGraphDev G, hipStream_t s);
+void launch_rows_set(const uint32_t* touched, const uint32_t* run_start, const uint32_t* run_end,
+                     const uint64_t* runscan, const uint64_t* r1off, uint32_t n_touched,
+                     uint64_t base1, uint64_t base2, GmGraphDev G, uint64_t* r2_off,
+                     uint32_t* r2_len, hipStream_t s);
+void launch_rows_commit(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
+                        uint32_t n_touched, GmGraphDev G, hipStream_t s);
+
+// filter and seeds (k_filter.hip)
+void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,
+                   const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
+                   hipStream_t s);
+void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
+                  uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
+                  const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
+                  hipStream_t s);
+
+// search (k_dfs.hip)
+void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);
+unsigned dfs_block_threads();
+
+}  // namespace gm

@@ -1,0 +1,935 @@
+// Host runtime behind the C ABI (include/gamma.h): context, device memory,
+// graph loading, query registration and the per-batch pipeline.
+//
+// Per batch (the four components of Sec. IV-A, with the search kernel of
+// Sec. IV-C): canonicalise the batch and build the batch hash, delta-merge
+// the touched rows, refresh the candidate filter of the touched vertices,
+// generate seeds, search, commit G', refresh the filter again, return the
+// results.  Every step is a HIP kernel on the context stream; the host only
+// sizes buffers (one synchronisation after canonicalisation, before
+// anything is mutated) and copies the small results back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gamma.h"
+#include "dev_common.h"
+#include "host_plan.h"
+#include "kernels.h"
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct DeviceError {
+  hipError_t e;
+  const char* what;
+};
+struct StatusError {
+  gamma_status s;
+  std::string msg;
+};
+
+inline void chk(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw DeviceError{e, what};
+}
+
+int bits_for(uint64_t x) {  // bits to hold any value < x (at least 1)
+  int b = 1;
+  while (b < 63 && (1ull << b) < x) ++b;
+  return b;
+}
+
+}  // namespace
+
+struct gamma_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  gamma_options opt{};
+  std::string last_error;
+  bool poisoned = false;
+  int n_cu = 256;
+
+  std::vector<DevBuf*> all;
+
+  // graph
+  bool has_graph = false;
+  uint32_t n = 0;
+  int idbits = 1;
+  uint64_t live = 0;
+  uint64_t arena_cap = 0, arena_top = 0;
+  uint32_t label_slots = 1;
+  std::vector<uint64_t> label_count;  // data vertices per label
+  DevBuf row_off, row_len, vlabel, label_start, new_of_old, old_of_new, arena;
+
+  // queries
+  std::vector<gm::HostQuery> queries;
+  uint32_t total_plans = 0;
+  uint32_t kmax = 2;
+  DevBuf plans, qdev, cand, lab_fstart, fentries, reqs;
+
+  // batch scratch
+  DevBuf b_src, b_dst, b_op, keys, keys_tmp, hist, hist_scan, scan_tmp, keep, ords;
+  DevBuf canon_lo, canon_hi, canon_sign, canon_a, canon_b, hkeys, hvals, dkeys, dkeys_tmp;
+  DevBuf runvals, runscan, touched, run_start, run_end, sizes, r1off, r2_off, r2_len;
+  DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
+  DevBuf tmp64a, tmp64b, tmp32a;
+
+  // host side results
+  void* h_pinned = nullptr;
+  size_t h_pinned_bytes = 0;
+  std::vector<gamma_query_result> hq;
+  std::vector<uint32_t> h_canon_lo, h_canon_hi;
+  std::vector<uint8_t> h_canon_sign;
+  std::vector<uint64_t> h_upd;  // n_canon * 3
+  std::vector<uint64_t> h_upd_cnt, h_upd_sum, h_upd_xor;
+  bool has_result = false;
+  uint64_t last_tuples = 0;
+  uint32_t last_twidth = 0;
+  bool last_has_ord = false;
+
+  hipEvent_t ev[8]{};
+
+  gamma_ctx() {
+    DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
+                      &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
+                      &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
+                      &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
+                      &runvals, &runscan, &touched, &run_start, &run_end, &sizes, &r1off, &r2_off,
+                      &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &tmp64a,
+                      &tmp64b, &tmp32a};
+    for (DevBuf* b : list) all.push_back(b);
+  }
+
+  template <typename T>
+  T* ensure(DevBuf& b, size_t count, bool keep_contents = false) {
+    size_t need = count * sizeof(T);
+    if (need == 0) need = sizeof(T);
+    if (b.bytes >= need) return (T*)b.p;
+    size_t alloc = std::max(need, b.bytes + b.bytes / 2);
+    void* p = nullptr;
+    if (hipMalloc(&p, alloc) != hipSuccess) {
+      (void)hipGetLastError();
+      alloc = need;
+      if (hipMalloc(&p, alloc) != hipSuccess) {
+        (void)hipGetLastError();
+        throw StatusError{GAMMA_ENOMEM, "device allocation failed"};
+      }
+    }
+    if (keep_contents && b.p && b.bytes) {
+      chk(hipMemcpyAsync(p, b.p, b.bytes, hipMemcpyDeviceToDevice, stream), "copy");
+      chk(hipStreamSynchronize(stream), "sync");
+    }
+    if (b.p) {
+      chk(hipStreamSynchronize(stream), "sync");
+      chk(hipFree(b.p), "free");
+    }
+    b.p = p;
+    b.bytes = alloc;
+    return (T*)p;
+  }
+
+  void release(DevBuf& b) {
+    if (b.p) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+
+  void* pinned(size_t bytes) {
+    if (h_pinned_bytes < bytes) {
+      if (h_pinned) (void)hipHostFree(h_pinned);
+      h_pinned = nullptr;
+      size_t alloc = std::max(bytes, (size_t)4096);
+      if (hipHostMalloc(&h_pinned, alloc, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        h_pinned = nullptr;
+        h_pinned_bytes = 0;
+        throw StatusError{GAMMA_ENOMEM, "pinned host allocation failed"};
+      }
+      h_pinned_bytes = alloc;
+    }
+    return h_pinned;
+  }
+
+  GmGraphDev G() {
+    GmGraphDev g;
+    g.n = n;
+    g.idbits = idbits;
+    g.row_off = (uint64_t*)row_off.p;
+    g.row_len = (uint32_t*)row_len.p;
+    g.col = (uint32_t*)arena.p;
+    g.vlabel = (const uint16_t*)vlabel.p;
+    g.label_start = (const uint32_t*)label_start.p;
+    g.label_slots = label_slots;
+    g.new_of_old = (const uint32_t*)new_of_old.p;
+    g.old_of_new = (const uint32_t*)old_of_new.p;
+    return g;
+  }
+
+  void sort_keys(uint64_t* k, uint64_t* tmp, size_t cnt, int bits) {
+    if (cnt < 2) return;
+    uint32_t* h = ensure<uint32_t>(hist, gm::radix_hist_elems(cnt));
+    uint32_t* hs = ensure<uint32_t>(hist_scan, gm::radix_hist_elems(cnt) + 1);
+    uint32_t* st = ensure<uint32_t>(scan_tmp, gm::scan_tmp_elems(gm::radix_hist_elems(cnt)));
+    gm::radix_sort_u64(k, tmp, cnt, bits, h, hs, st, stream);
+  }
+
+  void scan64(const uint64_t* in, uint64_t* out, size_t cnt) {
+    uint64_t* t = ensure<uint64_t>(tmp64b, gm::scan_tmp_elems(cnt));
+    gm::scan_u64(in, out, cnt, t, stream);
+  }
+  void scan32(const uint32_t* in, uint32_t* out, size_t cnt) {
+    uint32_t* t = ensure<uint32_t>(tmp32a, gm::scan_tmp_elems(cnt));
+    gm::scan_u32(in, out, cnt, t, stream);
+  }
+
+  void rebuild_filter_tables() {
+    std::vector<uint32_t> fs;
+    std::vector<GmFilterEntry> fe;
+    std::vector<GmReq> rq;
+    gm::build_filter_tables(queries, label_slots, fs, fe, rq);
+    uint32_t* dfs = ensure<uint32_t>(lab_fstart, fs.size());
+    GmFilterEntry* dfe = ensure<GmFilterEntry>(fentries, fe.size());
+    GmReq* drq = ensure<GmReq>(reqs, rq.size());
+    chk(hipMemcpyAsync(dfs, fs.data(), fs.size() * 4, hipMemcpyHostToDevice, stream), "h2d");
+    chk(hipMemcpyAsync(dfe, fe.data(), fe.size() * sizeof(GmFilterEntry), hipMemcpyHostToDevice, stream),
+        "h2d");
+    chk(hipMemcpyAsync(drq, rq.data(), rq.size() * sizeof(GmReq), hipMemcpyHostToDevice, stream), "h2d");
+    chk(hipStreamSynchronize(stream), "sync");
+  }
+
+  void upload_plans() {
+    std::vector<GmPlan> all_plans;
+    std::vector<GmQueryDev> qd;
+    for (auto& q : queries) {
+      GmQueryDev d{};
+      d.k = q.k;
+      d.plan_base = (uint32_t)all_plans.size();
+      d.n_plans = (uint32_t)q.plans.size();
+      qd.push_back(d);
+      for (auto& p : q.plans) all_plans.push_back(p);
+    }
+    total_plans = (uint32_t)all_plans.size();
+    GmPlan* dp = ensure<GmPlan>(plans, std::max<size_t>(all_plans.size(), 1));
+    GmQueryDev* dq = ensure<GmQueryDev>(qdev, std::max<size_t>(qd.size(), 1));
+    if (!all_plans.empty())
+      chk(hipMemcpyAsync(dp, all_plans.data(), all_plans.size() * sizeof(GmPlan), hipMemcpyHostToDevice,
+                         stream),
+          "h2d");
+    if (!qd.empty())
+      chk(hipMemcpyAsync(dq, qd.data(), qd.size() * sizeof(GmQueryDev), hipMemcpyHostToDevice, stream),
+          "h2d");
+    chk(hipStreamSynchronize(stream), "sync");
+  }
+
+  // Candidate table for every query (or one) over all vertices.
+  void full_filter(uint32_t only_q) {
+    if (!has_graph || queries.empty()) return;
+    uint16_t* c = ensure<uint16_t>(cand, (size_t)queries.size() * n, true);
+    if (only_q == 0xFFFFFFFFu) {
+      gm::fill_u32((uint32_t*)c, 0, ((size_t)queries.size() * n + 1) / 2, stream);
+    } else {
+      chk(hipMemsetAsync(c + (size_t)only_q * n, 0, (size_t)n * 2, stream), "memset");
+    }
+    gm::launch_filter(G(), nullptr, n, (const uint32_t*)lab_fstart.p, (const GmFilterEntry*)fentries.p,
+                      (const GmReq*)reqs.p, c, only_q, stream);
+    chk(hipGetLastError(), "filter launch");
+    chk(hipStreamSynchronize(stream), "sync");
+  }
+};
+
+namespace {
+
+gamma_status fail(gamma_ctx* c, gamma_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+template <typename F>
+gamma_status guarded(gamma_ctx* c, F&& f) {
+  if (!c) return GAMMA_EINVAL;
+  if (c->poisoned) return GAMMA_EDEVICE;
+  try {
+    return f();
+  } catch (const DeviceError& e) {
+    c->poisoned = true;
+    c->last_error = std::string(e.what) + ": " + hipGetErrorString(e.e);
+    return GAMMA_EDEVICE;
+  } catch (const StatusError& e) {
+    c->last_error = e.msg;
+    return e.s;
+  } catch (const std::bad_alloc&) {
+    c->last_error = "host allocation failed";
+    return GAMMA_ENOMEM;
+  }
+}
+
+// Host copy of a possibly-device input into a device buffer.
+template <typename T>
+const T* stage_in(gamma_ctx* c, DevBuf& buf, const T* src, size_t count, gamma_mem where) {
+  if (where == GAMMA_MEM_DEVICE) return src;
+  T* d = c->ensure<T>(buf, count);
+  if (count) chk(hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream), "h2d");
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t gamma_version(void) { return 100; }
+
+const char* gamma_status_string(gamma_status s) {
+  switch (s) {
+    case GAMMA_OK: return "ok";
+    case GAMMA_TRUNCATED: return "tuple capacity reached (counts exact)";
+    case GAMMA_EINVAL: return "invalid argument";
+    case GAMMA_ECONFLICT: return "batch inserts and deletes the same edge";
+    case GAMMA_ENOMEM: return "out of memory";
+    case GAMMA_EUNSUPPORTED: return "unsupported";
+    case GAMMA_ESTATE: return "invalid call order";
+    case GAMMA_ETIMEDOUT: return "deadline exceeded";
+    case GAMMA_EDEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* gamma_last_error(const gamma_ctx* ctx) {
+  return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
+  if (!out) return GAMMA_EINVAL;
+  *out = nullptr;
+  gamma_ctx* c = new (std::nothrow) gamma_ctx();
+  if (!c) return GAMMA_ENOMEM;
+  if (opt) c->opt = *opt;
+  c->device = c->opt.device;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || c->device < 0 || c->device >= ndev) {
+    (void)hipGetLastError();
+    delete c;
+    return GAMMA_EDEVICE;
+  }
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return GAMMA_EDEVICE;
+  }
+  if (c->opt.stream) {
+    c->stream = (hipStream_t)c->opt.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return GAMMA_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0)
+    c->n_cu = cu;
+  for (auto& e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete c;
+      return GAMMA_EDEVICE;
+    }
+  *out = c;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_destroy(gamma_ctx* c) {
+  if (!c) return GAMMA_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : c->all)
+    if (b->p) (void)hipFree(b->p);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                              const uint32_t* col, const uint32_t* labels, gamma_mem where) {
+  return guarded(c, [&]() -> gamma_status {
+    if (n == 0 || n >= 0x80000000u || !row_ptr || !labels || (nnz && !col))
+      return fail(c, GAMMA_EINVAL, "load_graph: bad sizes or null arrays");
+    if (nnz >= 0xFFFFFFFFull) return fail(c, GAMMA_EUNSUPPORTED, "load_graph: nnz must be < 2^32");
+    chk(hipSetDevice(c->device), "set device");
+    hipStream_t s = c->stream;
+    // stage inputs
+    DevBuf in_rp, in_col, in_lab;
+    struct Tmp {
+      gamma_ctx* c;
+      DevBuf* b[3];
+      ~Tmp() {
+        for (DevBuf* x : b) c->release(*x);
+      }
+    } tmp{c, {&in_rp, &in_col, &in_lab}};
+    const uint64_t* d_rp = stage_in<uint64_t>(c, in_rp, row_ptr, (size_t)n + 1, where);
+    const uint32_t* d_col = nnz ? stage_in<uint32_t>(c, in_col, col, nnz, where) : nullptr;
+    const uint32_t* d_lab = stage_in<uint32_t>(c, in_lab, labels, n, where);
+    uint32_t* ctrw = (uint32_t*)c->ensure<GmCounters>(c->ctr, 1);
+    gm::fill_u32(ctrw, 0, sizeof(GmCounters) / 4, s);
+    uint32_t* dummy_col = nullptr;
+    if (!d_col) {
+      dummy_col = c->ensure<uint32_t>(c->tmp32a, 1);
+      d_col = dummy_col;
+    }
+    gm::launch_validate_csr(d_rp, d_col, d_lab, n, nnz, ctrw, s);
+    chk(hipGetLastError(), "validate launch");
+    uint32_t err = 0;
+    chk(hipMemcpyAsync(&err, ctrw, 4, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipStreamSynchronize(s), "sync");
+    if (err) return fail(c, GAMMA_EINVAL, "load_graph: malformed CSR or labels (error bits " +
+                                              std::to_string(err) + ")");
+
+    // new graph buffers (built aside, swapped in at the end)
+    gamma_ctx& C = *c;
+    DevBuf n_row_off, n_row_len, n_vlabel, n_label_start, n_n2o, n_o2n, n_arena;
+    const int ib = bits_for(n);
+    {
+      uint64_t* keys = C.ensure<uint64_t>(C.keys, n);
+      uint64_t* kt = C.ensure<uint64_t>(C.keys_tmp, n);
+      gm::launch_relabel_keys(d_lab, n, keys, s);
+      C.sort_keys(keys, kt, n, 48);
+      uint32_t* n2o = C.ensure<uint32_t>(n_n2o, n);
+      uint32_t* o2n = C.ensure<uint32_t>(n_o2n, n);
+      uint16_t* vl = C.ensure<uint16_t>(n_vlabel, n);
+      gm::launch_relabel_apply(keys, n, n2o, o2n, vl, s);
+      uint16_t maxlab = 0;
+      chk(hipMemcpyAsync(&maxlab, vl + (n - 1), 2, hipMemcpyDeviceToHost, s), "d2h");
+      chk(hipStreamSynchronize(s), "sync");
+      uint32_t slots = (uint32_t)maxlab + 1;
+      uint32_t* ls = C.ensure<uint32_t>(n_label_start, slots + 1);
+      gm::launch_label_start(vl, n, slots, ls, s);
+      std::vector<uint32_t> hls(slots + 1);
+      chk(hipMemcpyAsync(hls.data(), ls, (slots + 1) * 4, hipMemcpyDeviceToHost, s), "d2h");
+      chk(hipStreamSynchronize(s), "sync");
+      C.label_slots = slots;
+      C.label_count.assign(slots, 0);
+      for (uint32_t l = 0; l < slots; ++l) C.label_count[l] = hls[l + 1] - hls[l];
+      // rows in internal ids
+      uint64_t* deg = C.ensure<uint64_t>(C.tmp64a, (size_t)n + 1);
+      gm::launch_deg_mapped(d_rp, nullptr, n2o, n, deg, s);
+      uint64_t* offs = C.ensure<uint64_t>(C.sizes, (size_t)n + 1);
+      C.scan64(deg, offs, n);
+      uint64_t* ro = C.ensure<uint64_t>(n_row_off, n);
+      uint32_t* rl = C.ensure<uint32_t>(n_row_len, n);
+      gm::launch_rows_from_scan(offs, deg, n, 0, ro, rl, s);
+      uint64_t cap = nnz + std::max<uint64_t>(nnz / 2, 1u << 20);
+      uint32_t* ar = C.ensure<uint32_t>(n_arena, cap);
+      if (nnz) {
+        uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
+        uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
+        gm::launch_csr_keys(nullptr, nullptr, d_rp, d_col, n2o, n, ib, nullptr, ek, s);
+        C.sort_keys(ek, et, nnz, 2 * ib);
+        gm::launch_csr_extract(ek, nnz, (1ull << ib) - 1, ar, s);
+      }
+      chk(hipGetLastError(), "load launch");
+      chk(hipStreamSynchronize(s), "sync");
+      // the load-time sort buffers are sized by nnz; batches need far less
+      C.release(C.keys);
+      C.release(C.keys_tmp);
+      C.arena_cap = cap;
+      C.arena_top = nnz;
+    }
+    // swap in
+    auto swap_in = [&](DevBuf& dst, DevBuf& src) {
+      C.release(dst);
+      dst = src;
+      src = DevBuf{};
+    };
+    swap_in(C.row_off, n_row_off);
+    swap_in(C.row_len, n_row_len);
+    swap_in(C.vlabel, n_vlabel);
+    swap_in(C.label_start, n_label_start);
+    swap_in(C.new_of_old, n_n2o);
+    swap_in(C.old_of_new, n_o2n);
+    swap_in(C.arena, n_arena);
+    C.n = n;
+    C.idbits = ib;
+    C.live = nnz;
+    C.has_graph = true;
+    C.has_result = false;
+    // queries: re-plan (label frequencies changed), re-filter
+    if (!C.queries.empty()) {
+      for (uint32_t qi = 0; qi < C.queries.size(); ++qi) gm::plan_query(C.queries[qi], qi, C.label_count);
+      C.upload_plans();
+      C.rebuild_filter_tables();
+      C.release(C.cand);
+      C.full_filter(0xFFFFFFFFu);
+    }
+    return GAMMA_OK;
+  });
+}
+
+gamma_status gamma_register_query(gamma_ctx* c, uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                  const uint32_t* qedges, uint32_t* out_qid) {
+  return guarded(c, [&]() -> gamma_status {
+    std::string msg;
+    int st = gm::validate_query(k, qlabels, m, qedges, &msg);
+    if (st != GAMMA_OK) return fail(c, (gamma_status)st, "register_query: " + msg);
+    if (c->queries.size() >= 4096) return fail(c, GAMMA_EUNSUPPORTED, "register_query: too many queries");
+    chk(hipSetDevice(c->device), "set device");
+    gm::HostQuery q;
+    q.k = k;
+    q.labels.assign(qlabels, qlabels + k);
+    for (uint32_t e = 0; e < m; ++e) q.edges.push_back({qedges[2 * e], qedges[2 * e + 1]});
+    uint32_t qi = (uint32_t)c->queries.size();
+    gm::plan_query(q, qi, c->label_count);
+    c->queries.push_back(q);
+    try {
+      c->upload_plans();
+      c->kmax = std::max(c->kmax, k);
+      if (c->has_graph) {
+        c->rebuild_filter_tables();
+        c->full_filter(qi);
+      }
+    } catch (const StatusError&) {
+      c->queries.pop_back();
+      throw;
+    }
+    if (out_qid) *out_qid = qi;
+    return GAMMA_OK;
+  });
+}
+
+namespace {
+
+// Move every row into a fresh, larger arena (rows contiguous, no garbage).
+void compact_arena(gamma_ctx* c, uint64_t need) {
+  hipStream_t s = c->stream;
+  const uint32_t n = c->n;
+  uint64_t cap = std::max<uint64_t>(c->arena_cap, 2 * (c->live + need) + (1u << 20));
+  DevBuf na;
+  uint32_t* dst = c->ensure<uint32_t>(na, cap);
+  uint64_t* deg = c->ensure<uint64_t>(c->tmp64a, (size_t)n + 1);
+  gm::launch_deg_mapped(nullptr, (const uint32_t*)c->row_len.p, nullptr, n, deg, s);
+  uint64_t* offs = c->ensure<uint64_t>(c->sizes, (size_t)n + 1);
+  c->scan64(deg, offs, n);
+  gm::launch_copy_rows((const uint64_t*)c->row_off.p, (const uint32_t*)c->row_len.p,
+                       (const uint32_t*)c->arena.p, offs, dst, n, s);
+  gm::launch_rows_from_scan(offs, deg, n, 0, (uint64_t*)c->row_off.p, nullptr, s);
+  chk(hipGetLastError(), "compact launch");
+  chk(hipStreamSynchronize(s), "sync");
+  c->release(c->arena);
+  c->arena = na;
+  c->arena_cap = cap;
+  c->arena_top = c->live;
+}
+
+}  // namespace
+
+gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                               const uint8_t* op, gamma_mem where, uint32_t flags,
+                               gamma_batch_result* out) {
+  return guarded(c, [&]() -> gamma_status {
+    if (!out) return fail(c, GAMMA_EINVAL, "apply_batch: null result");
+    if (!c->has_graph) return fail(c, GAMMA_ESTATE, "apply_batch: no graph loaded");
+    if (n_upd > (1u << 20)) return fail(c, GAMMA_EINVAL, "apply_batch: more than 2^20 updates");
+    if (n_upd && (!src || !dst || !op)) return fail(c, GAMMA_EINVAL, "apply_batch: null update arrays");
+    if ((flags & GAMMA_F_TUPLES) && c->opt.tuple_capacity == 0)
+      return fail(c, GAMMA_EINVAL, "apply_batch: TUPLES requested but tuple_capacity is 0");
+    chk(hipSetDevice(c->device), "set device");
+    gamma_ctx& C = *c;
+    hipStream_t s = C.stream;
+    C.has_result = false;
+    const uint32_t nq = (uint32_t)C.queries.size();
+    const uint32_t n = C.n;
+    const int eb = C.idbits;
+    const int ib = C.idbits;
+    chk(hipEventRecord(C.ev[0], s), "event");
+
+    // ---------------------------------------------------------- canonicalise
+    const uint32_t* d_src = stage_in<uint32_t>(c, C.b_src, src, n_upd, where);
+    const uint32_t* d_dst = stage_in<uint32_t>(c, C.b_dst, dst, n_upd, where);
+    const uint8_t* d_op = stage_in<uint8_t>(c, C.b_op, op, n_upd, where);
+    GmCounters* ctr = C.ensure<GmCounters>(C.ctr, 1);
+    gm::fill_u32((uint32_t*)ctr, 0, sizeof(GmCounters) / 4, s);
+    const size_t nu = std::max<uint32_t>(n_upd, 1);
+    uint64_t* keys = C.ensure<uint64_t>(C.keys, nu);
+    uint64_t* kt = C.ensure<uint64_t>(C.keys_tmp, std::max<size_t>(2 * nu, 2));
+    uint32_t* keep = C.ensure<uint32_t>(C.keep, nu);
+    uint32_t* ords = C.ensure<uint32_t>(C.ords, nu + 1);
+    GmGraphDev G = C.G();
+    gm::launch_canon_keys(d_src, d_dst, d_op, n_upd, n, eb, keys, ctr, s);
+    C.sort_keys(keys, kt, n_upd, 2 * eb + 1);
+    gm::launch_canon_classify(keys, n_upd, eb, G, keep, ctr, s);
+    C.scan32(keep, ords, n_upd);
+    uint32_t hcap = 64;
+    while (hcap < 2 * nu) hcap <<= 1;
+    GmBatchHash H;
+    H.keys = C.ensure<uint64_t>(C.hkeys, hcap);
+    H.vals = C.ensure<uint32_t>(C.hvals, hcap);
+    H.mask = hcap - 1;
+    gm::fill_u64(H.keys, GM_EMPTY64, hcap, s);
+    uint32_t* clo = C.ensure<uint32_t>(C.canon_lo, nu);
+    uint32_t* chi = C.ensure<uint32_t>(C.canon_hi, nu);
+    uint8_t* csg = C.ensure<uint8_t>(C.canon_sign, nu);
+    uint32_t* ca = C.ensure<uint32_t>(C.canon_a, nu);
+    uint32_t* cb = C.ensure<uint32_t>(C.canon_b, nu);
+    const size_t N2 = 2 * nu;  // directed entries, padded
+    uint64_t* dk = C.ensure<uint64_t>(C.dkeys, N2);
+    uint64_t* dkt = C.ensure<uint64_t>(C.dkeys_tmp, N2);
+    gm::launch_canon_emit(keys, keep, ords, n_upd, eb, G, clo, chi, csg, ca, cb, H, dk, s);
+    // the canonical count decides the directed sort length: one sync here,
+    // before anything is mutated, also reports validation errors
+    struct {
+      uint32_t n_canon;
+      uint32_t pad;
+    } h1{};
+    GmCounters hc{};
+    chk(hipMemcpyAsync(&h1.n_canon, ords + n_upd, 4, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipMemcpyAsync(&hc, ctr, sizeof(GmCounters), hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipStreamSynchronize(s), "sync");
+    chk(hipGetLastError(), "canon launch");
+    if (hc.err & (GM_ERR_RANGE | GM_ERR_SELFLOOP))
+      return fail(c, GAMMA_EINVAL, "apply_batch: vertex id out of range or self loop");
+    if (hc.err & GM_ERR_CONFLICT)
+      return fail(c, GAMMA_ECONFLICT, "apply_batch: an edge is both inserted and deleted");
+    const uint32_t n_canon = n_upd ? h1.n_canon : 0;
+    const uint32_t N = 2 * n_canon;
+    C.sort_keys(dk, dkt, N, 2 * ib + 1);
+    uint64_t* rv = C.ensure<uint64_t>(C.runvals, std::max<uint32_t>(N, 1));
+    uint64_t* rsc = C.ensure<uint64_t>(C.runscan, (size_t)N + 1);
+    gm::launch_runs_flags(dk, N, ib, rv, s);
+    C.scan64(rv, rsc, N);
+    uint32_t* tch = C.ensure<uint32_t>(C.touched, std::max<uint32_t>(N, 1));
+    uint32_t* rs_ = C.ensure<uint32_t>(C.run_start, std::max<uint32_t>(N, 1));
+    uint32_t* re_ = C.ensure<uint32_t>(C.run_end, std::max<uint32_t>(N, 1));
+    gm::launch_runs_fill(dk, rsc, N, ib, tch, rs_, re_, s);
+    uint64_t hrun = 0;
+    chk(hipMemcpyAsync(&hrun, rsc + N, 8, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipStreamSynchronize(s), "sync");
+    const uint32_t n_touched = (uint32_t)hrun;
+    const uint32_t n_ins_dir = (uint32_t)(hrun >> 32);
+    const uint32_t n_insert = n_ins_dir / 2;
+    const uint32_t n_delete = n_canon - n_insert;
+    uint64_t* sz = C.ensure<uint64_t>(C.sizes, std::max<uint32_t>(n_touched, 1));
+    uint64_t* r1 = C.ensure<uint64_t>(C.r1off, (size_t)n_touched + 1);
+    gm::launch_touched_sizes(tch, rs_, re_, rsc, n_touched, G, sz, s);
+    C.scan64(sz, r1, n_touched);
+    uint64_t r1_total = 0;
+    chk(hipMemcpyAsync(&r1_total, r1 + n_touched, 8, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipStreamSynchronize(s), "sync");
+    chk(hipGetLastError(), "runs launch");
+    chk(hipEventRecord(C.ev[1], s), "event");
+
+    // ---------------------------------------------------------- delta-merge
+    const uint64_t r2_total = r1_total - 2ull * n_delete;
+    if (C.arena_top + r1_total + r2_total > C.arena_cap) {
+      compact_arena(c, r1_total + r2_total);
+      G = C.G();
+    }
+    const uint64_t base1 = C.arena_top, base2 = base1 + r1_total;
+    uint64_t* r2o = C.ensure<uint64_t>(C.r2_off, std::max<uint32_t>(n_touched, 1));
+    uint32_t* r2l = C.ensure<uint32_t>(C.r2_len, std::max<uint32_t>(n_touched, 1));
+    G = C.G();
+    gm::launch_merge(dk, rsc, tch, rs_, re_, r1, n_touched, r1_total, base1, base2, ib, G, s);
+    gm::launch_rows_set(tch, rs_, re_, rsc, r1, n_touched, base1, base2, G, r2o, r2l, s);
+    C.arena_top += r1_total + r2_total;
+    chk(hipEventRecord(C.ev[2], s), "event");
+
+    // ---------------------------------------------------------- filter refresh (G u I)
+    if (nq)
+      gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
+                        (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
+                        (uint16_t*)C.cand.p, 0xFFFFFFFFu, s);
+    chk(hipEventRecord(C.ev[3], s), "event");
+
+    // ---------------------------------------------------------- seeds
+    const uint64_t seed_cap = std::max<uint64_t>((uint64_t)n_canon * C.total_plans, 1);
+    GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
+    if (nq)
+      gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
+                       (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, s);
+    chk(hipEventRecord(C.ev[4], s), "event");
+
+    // ---------------------------------------------------------- search
+    const size_t qres_n = std::max<size_t>((size_t)nq * 6, 6);
+    unsigned long long* qres = C.ensure<unsigned long long>(C.qres, qres_n);
+    gm::fill_u64((uint64_t*)qres, 0, qres_n, s);
+    unsigned long long* upd = nullptr;
+    if (flags & GAMMA_F_PER_UPDATE) {
+      upd = C.ensure<unsigned long long>(C.upd_res, std::max<size_t>((size_t)n_canon * 3, 3));
+      gm::fill_u64((uint64_t*)upd, 0, (size_t)n_canon * 3, s);
+    }
+    const uint32_t tw = C.kmax;
+    uint64_t tcap = 0;
+    if (flags & GAMMA_F_TUPLES) {
+      tcap = C.opt.tuple_capacity;
+      C.ensure<uint32_t>(C.tuples, tcap * tw);
+      C.ensure<uint32_t>(C.tmeta, tcap);
+      if (flags & GAMMA_F_SEED_ATTR) C.ensure<uint32_t>(C.tord, tcap);
+    }
+    if (nq && n_canon) {
+      GmDfsParams P;
+      P.G = G;
+      P.plans = (const GmPlan*)C.plans.p;
+      P.queries = (const GmQueryDev*)C.qdev.p;
+      P.cand = (const uint16_t*)C.cand.p;
+      P.seeds = sd;
+      P.H = H;
+      P.ctr = ctr;
+      P.flags = flags & (GM_F_HASH | GM_F_TUPLES | GM_F_SEED_ATTR | GM_F_PER_UPDATE);
+      P.twidth = tw;
+      P.qres = qres;
+      P.tuples = (uint32_t*)C.tuples.p;
+      P.tmeta = (uint32_t*)C.tmeta.p;
+      P.tord = (uint32_t*)C.tord.p;
+      P.tcap = tcap;
+      P.upd_res = upd;
+      uint32_t wpc = C.opt.waves_per_cu ? C.opt.waves_per_cu : 16;
+      unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / 4);
+      gm::launch_dfs(P, blocks, s);
+    }
+    chk(hipEventRecord(C.ev[5], s), "event");
+
+    // ---------------------------------------------------------- commit G', refresh filter on G'
+    gm::launch_rows_commit(tch, r2o, r2l, n_touched, G, s);
+    if (nq)
+      gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
+                        (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
+                        (uint16_t*)C.cand.p, 0xFFFFFFFFu, s);
+    C.live = C.live + 2ull * n_insert - 2ull * n_delete;
+    chk(hipEventRecord(C.ev[6], s), "event");
+
+    // ---------------------------------------------------------- results to host
+    size_t hbytes = qres_n * 8 + sizeof(GmCounters);
+    if (flags & GAMMA_F_PER_UPDATE) hbytes += (size_t)n_canon * 24;
+    if (flags & GAMMA_F_CANONICAL) hbytes += (size_t)n_canon * 9;
+    char* hp = (char*)C.pinned(hbytes);
+    uint64_t* h_qres = (uint64_t*)hp;
+    GmCounters* h_ctr = (GmCounters*)(hp + qres_n * 8);
+    char* tail = hp + qres_n * 8 + sizeof(GmCounters);
+    chk(hipMemcpyAsync(h_qres, qres, qres_n * 8, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipMemcpyAsync(h_ctr, ctr, sizeof(GmCounters), hipMemcpyDeviceToHost, s), "d2h");
+    uint64_t* h_upd = nullptr;
+    if ((flags & GAMMA_F_PER_UPDATE) && n_canon) {
+      h_upd = (uint64_t*)tail;
+      chk(hipMemcpyAsync(h_upd, upd, (size_t)n_canon * 24, hipMemcpyDeviceToHost, s), "d2h");
+      tail += (size_t)n_canon * 24;
+    }
+    uint32_t* h_clo = nullptr;
+    if ((flags & GAMMA_F_CANONICAL) && n_canon) {
+      h_clo = (uint32_t*)tail;
+      chk(hipMemcpyAsync(h_clo, clo, (size_t)n_canon * 4, hipMemcpyDeviceToHost, s), "d2h");
+      chk(hipMemcpyAsync(h_clo + n_canon, chi, (size_t)n_canon * 4, hipMemcpyDeviceToHost, s), "d2h");
+      chk(hipMemcpyAsync(h_clo + 2 * (size_t)n_canon, csg, n_canon, hipMemcpyDeviceToHost, s), "d2h");
+    }
+    chk(hipEventRecord(C.ev[7], s), "event");
+    chk(hipStreamSynchronize(s), "sync");
+    chk(hipGetLastError(), "batch launch");
+
+    // ---------------------------------------------------------- fill the result
+    C.hq.assign(nq, gamma_query_result{});
+    for (uint32_t q = 0; q < nq; ++q) {
+      gamma_query_result& r = C.hq[q];
+      r.qid = q;
+      r.k = C.queries[q].k;
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        const uint64_t* p = h_qres + ((size_t)q * 2 + sgn) * 3;
+        r.count[sgn] = p[0];
+        r.hash_sum[sgn] = (flags & GAMMA_F_HASH) ? p[1] : 0;
+        r.hash_xor[sgn] = (flags & GAMMA_F_HASH) ? p[2] : 0;
+      }
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->n_queries = nq;
+    out->tuple_width = tw;
+    out->queries = C.hq.data();
+    out->n_tuples_found = (flags & GAMMA_F_TUPLES) ? h_ctr->tuples_found : 0;
+    out->n_tuples = std::min<uint64_t>(out->n_tuples_found, tcap);
+    out->tuples = (flags & GAMMA_F_TUPLES) ? (uint32_t*)C.tuples.p : nullptr;
+    out->meta = (flags & GAMMA_F_TUPLES) ? (uint32_t*)C.tmeta.p : nullptr;
+    out->ord = ((flags & GAMMA_F_TUPLES) && (flags & GAMMA_F_SEED_ATTR)) ? (uint32_t*)C.tord.p : nullptr;
+    out->n_canonical = n_canon;
+    if (flags & GAMMA_F_CANONICAL) {
+      C.h_canon_lo.assign(h_clo ? h_clo : nullptr, h_clo ? h_clo + n_canon : nullptr);
+      C.h_canon_hi.assign(h_clo ? h_clo + n_canon : nullptr, h_clo ? h_clo + 2 * (size_t)n_canon : nullptr);
+      const uint8_t* sg = h_clo ? (const uint8_t*)(h_clo + 2 * (size_t)n_canon) : nullptr;
+      C.h_canon_sign.assign(sg, sg ? sg + n_canon : nullptr);
+      out->canon_lo = C.h_canon_lo.data();
+      out->canon_hi = C.h_canon_hi.data();
+      out->canon_sign = C.h_canon_sign.data();
+    }
+    if (flags & GAMMA_F_PER_UPDATE) {
+      C.h_upd_cnt.resize(n_canon);
+      C.h_upd_sum.resize(n_canon);
+      C.h_upd_xor.resize(n_canon);
+      for (uint32_t i = 0; i < n_canon; ++i) {
+        C.h_upd_cnt[i] = h_upd[3 * (size_t)i];
+        C.h_upd_sum[i] = h_upd[3 * (size_t)i + 1];
+        C.h_upd_xor[i] = h_upd[3 * (size_t)i + 2];
+      }
+      out->upd_count = C.h_upd_cnt.data();
+      out->upd_hash_sum = C.h_upd_sum.data();
+      out->upd_hash_xor = C.h_upd_xor.data();
+    }
+    gamma_batch_stats& st = out->stats;
+    st.n_input = n_upd;
+    st.n_canonical = n_canon;
+    st.n_insert = n_insert;
+    st.n_delete = n_delete;
+    st.n_noop = hc.n_noop;
+    st.n_duplicate = hc.n_dup;
+    st.n_touched = n_touched;
+    st.n_seeds = h_ctr->n_seeds;
+    st.dfs_nodes = h_ctr->dfs_nodes;
+    st.steals = h_ctr->steals;
+    st.cand_scanned = h_ctr->cand_scanned;
+    st.bytes_alg_dfs = h_ctr->bytes_alg;
+    // merge: read old rows, write R1 and R2; commit: row pointers only
+    st.bytes_alg_update = (r1_total - 2ull * n_insert) * 4 + r1_total * 4 + r2_total * 4 + (uint64_t)n_upd * 9;
+    float ms = 0;
+    auto el = [&](int a, int b) {
+      float t = 0;
+      (void)hipEventElapsedTime(&t, C.ev[a], C.ev[b]);
+      return t;
+    };
+    st.ms_canon = el(0, 1);
+    st.ms_merge = el(1, 2);
+    st.ms_filter = el(2, 3);
+    st.ms_seed = el(3, 4);
+    st.ms_dfs = el(4, 5);
+    st.ms_commit = el(5, 6);
+    ms = el(0, 7);
+    st.ms_total = ms;
+    C.has_result = true;
+    C.last_tuples = out->n_tuples;
+    C.last_twidth = tw;
+    C.last_has_ord = out->ord != nullptr;
+    return out->n_tuples < out->n_tuples_found ? GAMMA_TRUNCATED : GAMMA_OK;
+  });
+}
+
+gamma_status gamma_copy_tuples(gamma_ctx* c, uint32_t* tuples, uint32_t* meta, uint32_t* ord,
+                               uint64_t max_records, gamma_mem where) {
+  return guarded(c, [&]() -> gamma_status {
+    if (!c->has_result) return fail(c, GAMMA_ESTATE, "copy_tuples: no batch result");
+    uint64_t nrec = std::min<uint64_t>(max_records, c->last_tuples);
+    hipMemcpyKind kind = where == GAMMA_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (nrec && tuples)
+      chk(hipMemcpyAsync(tuples, c->tuples.p, nrec * c->last_twidth * 4, kind, c->stream), "copy");
+    if (nrec && meta) chk(hipMemcpyAsync(meta, c->tmeta.p, nrec * 4, kind, c->stream), "copy");
+    if (nrec && ord) {
+      if (!c->last_has_ord) return fail(c, GAMMA_ESTATE, "copy_tuples: no seed attribution stored");
+      chk(hipMemcpyAsync(ord, c->tord.p, nrec * 4, kind, c->stream), "copy");
+    }
+    chk(hipStreamSynchronize(c->stream), "sync");
+    return GAMMA_OK;
+  });
+}
+
+gamma_status gamma_result_release(gamma_ctx* c, gamma_batch_result* res) {
+  return guarded(c, [&]() -> gamma_status {
+    c->has_result = false;
+    if (res) std::memset(res, 0, sizeof(*res));
+    return GAMMA_OK;
+  });
+}
+
+gamma_status gamma_export_graph(gamma_ctx* c, uint32_t* n_out, uint64_t* nnz_out, uint64_t* row_ptr,
+                                uint32_t* col, uint32_t* labels) {
+  return guarded(c, [&]() -> gamma_status {
+    if (!c->has_graph) return fail(c, GAMMA_ESTATE, "export_graph: no graph loaded");
+    if (n_out) *n_out = c->n;
+    if (nnz_out) *nnz_out = c->live;
+    if (!col && !row_ptr && !labels) return GAMMA_OK;
+    gamma_ctx& C = *c;
+    hipStream_t s = C.stream;
+    const uint32_t n = C.n;
+    const int ib = C.idbits;
+    const uint64_t nnz = C.live;
+    uint64_t* deg = C.ensure<uint64_t>(C.tmp64a, (size_t)n + 1);
+    gm::launch_deg_mapped(nullptr, (const uint32_t*)C.row_len.p, (const uint32_t*)C.old_of_new.p, n, deg, s);
+    uint64_t* offs = C.ensure<uint64_t>(C.sizes, (size_t)n + 1);
+    C.scan64(deg, offs, n);
+    if (row_ptr) {
+      chk(hipMemcpyAsync(row_ptr, offs, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost, s), "d2h");
+    }
+    if (col && nnz) {
+      uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
+      uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
+      // internal row offsets packed densely: scan of row_len in internal order
+      uint64_t* ideg = C.ensure<uint64_t>(C.runvals, (size_t)n + 1);
+      gm::launch_deg_mapped(nullptr, (const uint32_t*)C.row_len.p, nullptr, n, ideg, s);
+      uint64_t* ioffs = C.ensure<uint64_t>(C.runscan, (size_t)n + 1);
+      C.scan64(ideg, ioffs, n);
+      gm::launch_csr_keys((const uint64_t*)C.row_off.p, (const uint32_t*)C.row_len.p, nullptr,
+                          (const uint32_t*)C.arena.p, (const uint32_t*)C.old_of_new.p, n, ib, ioffs, ek, s);
+      C.sort_keys(ek, et, nnz, 2 * ib);
+      uint32_t* oc = C.ensure<uint32_t>(C.tmp32a, nnz);
+      gm::launch_csr_extract(ek, nnz, (1ull << ib) - 1, oc, s);
+      chk(hipMemcpyAsync(col, oc, nnz * 4, hipMemcpyDeviceToHost, s), "d2h");
+    }
+    chk(hipStreamSynchronize(s), "sync");
+    if (labels) {
+      std::vector<uint16_t> vl(n);
+      std::vector<uint32_t> o2n(n);
+      chk(hipMemcpy(vl.data(), C.vlabel.p, (size_t)n * 2, hipMemcpyDeviceToHost), "d2h");
+      chk(hipMemcpy(o2n.data(), C.old_of_new.p, (size_t)n * 4, hipMemcpyDeviceToHost), "d2h");
+      for (uint32_t v = 0; v < n; ++v) labels[o2n[v]] = vl[v];
+    }
+    chk(hipGetLastError(), "export launch");
+    return GAMMA_OK;
+  });
+}
+
+// ------------------------------------------------------------------ host validators
+
+gamma_status gamma_validate_graph(uint32_t n, uint64_t nnz, const uint64_t* rp, const uint32_t* col,
+                                  const uint32_t* labels) {
+  if (n == 0 || n >= 0x80000000u || !rp || !labels || (nnz && !col)) return GAMMA_EINVAL;
+  if (rp[0] != 0 || rp[n] != nnz) return GAMMA_EINVAL;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (labels[v] > 0xFFFFu) return GAMMA_EINVAL;
+    if (rp[v] > rp[v + 1] || rp[v + 1] > nnz) return GAMMA_EINVAL;
+  }
+  for (uint32_t v = 0; v < n; ++v) {
+    for (uint64_t j = rp[v]; j < rp[v + 1]; ++j) {
+      uint32_t x = col[j];
+      if (x >= n || x == v) return GAMMA_EINVAL;
+      if (j > rp[v] && col[j - 1] >= x) return GAMMA_EINVAL;
+      if (!std::binary_search(col + rp[x], col + rp[x + 1], v)) return GAMMA_EINVAL;
+    }
+  }
+  return GAMMA_OK;
+}
+
+gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges) {
+  return (gamma_status)gm::validate_query(k, qlabels, m, qedges, nullptr);
+}
+
+gamma_status gamma_validate_batch(uint32_t n, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                  const uint8_t* op) {
+  if (n_upd > (1u << 20)) return GAMMA_EINVAL;
+  if (n_upd && (!src || !dst || !op)) return GAMMA_EINVAL;
+  std::vector<uint64_t> keys;
+  keys.reserve(n_upd);
+  for (uint32_t i = 0; i < n_upd; ++i) {
+    if (src[i] >= n || dst[i] >= n || src[i] == dst[i]) return GAMMA_EINVAL;
+    uint64_t lo = std::min(src[i], dst[i]), hi = std::max(src[i], dst[i]);
+    keys.push_back((lo << 33) | (hi << 1) | (op[i] ? 1u : 0u));
+  }
+  std::sort(keys.begin(), keys.end());
+  for (size_t i = 1; i < keys.size(); ++i)
+    if ((keys[i] >> 1) == (keys[i - 1] >> 1) && keys[i] != keys[i - 1]) return GAMMA_ECONFLICT;
+  return GAMMA_OK;
+}
+
+}  // extern "C"
