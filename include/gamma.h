@@ -110,6 +110,13 @@ typedef struct gamma_batch_stats {
   uint64_t bytes_alg_update; /* algorithmic bytes of the graph update (merge + commit) */
   float ms_canon, ms_merge, ms_filter, ms_seed, ms_dfs, ms_commit, ms_total;
   float reserved1;
+  /* search-kernel time split, summed over waves, in shader clock cycles */
+  uint64_t cyc_idle;       /* waiting for work */
+  uint64_t cyc_init;       /* setting up a level (neighbour-list subranges) */
+  uint64_t cyc_inner;      /* evaluating candidate chunks above the last level */
+  uint64_t cyc_leaf;       /* evaluating and emitting last-level chunks */
+  uint64_t cyc_handover;   /* handing work to idle waves */
+  uint64_t tasks_received; /* work items received from other waves */
 } gamma_batch_stats;
 
 typedef struct gamma_batch_result {

@@ -75,6 +75,12 @@ class BatchStats(ctypes.Structure):
         ("ms_commit", ctypes.c_float),
         ("ms_total", ctypes.c_float),
         ("reserved1", ctypes.c_float),
+        ("cyc_idle", ctypes.c_uint64),
+        ("cyc_init", ctypes.c_uint64),
+        ("cyc_inner", ctypes.c_uint64),
+        ("cyc_leaf", ctypes.c_uint64),
+        ("cyc_handover", ctypes.c_uint64),
+        ("tasks_received", ctypes.c_uint64),
     ]
 
 

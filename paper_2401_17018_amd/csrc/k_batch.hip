@@ -203,8 +203,13 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ dkey
       const uint32_t ins_lt = ins_prefix(runscan, a) - insb;
       const uint32_t del_lt = r - ins_lt;
       const bool deleted = a < re && ((dkeys[a] >> 1) & idmask) == x && !(dkeys[a] & 1);
+      const uint32_t xe = G.ext[off + jj];
       G.col[o1 + jj + ins_lt] = deleted ? (x | GM_FLAG) : x;
-      if (!deleted) G.col[o2 + jj + ins_lt - del_lt] = x;
+      G.ext[o1 + jj + ins_lt] = xe;
+      if (!deleted) {
+        G.col[o2 + jj + ins_lt - del_lt] = x;
+        G.ext[o2 + jj + ins_lt - del_lt] = xe;
+      }
     } else {
       const uint32_t i = (uint32_t)(jj - L);  // i-th insertion of the run
       uint32_t a = rs, b = re;                // first entry whose inclusive insert count > i
@@ -218,8 +223,11 @@ __global__ __launch_bounds__(256) void k_merge(const uint64_t* __restrict__ dkey
       const uint32_t r = a - rs;
       const uint32_t x = (uint32_t)((dkeys[a] >> 1) & idmask);
       const uint64_t p = lb_row(G.col, off, L, x);
+      const uint32_t xe = G.old_of_new[x];
       G.col[o1 + p + i] = x | GM_FLAG;
+      G.ext[o1 + p + i] = xe;
       G.col[o2 + p + i - (r - i)] = x;
+      G.ext[o2 + p + i - (r - i)] = xe;
     }
   }
 }

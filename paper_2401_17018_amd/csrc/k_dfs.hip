@@ -1,28 +1,39 @@
 // The search kernel: depth-first extension of seeds into incremental
-// matches (Algorithm 1 of Sec. IV-C, with the order rule stated after it).
+// matches (Algorithm 1 of Sec. IV-C, with the order rule stated after it),
+// with wavefront-level work hand-over for load balance (Sec. V-A).
 //
-// One wavefront (64 lanes) owns one task at a time and keeps its whole DFS
-// state in LDS (the paper keeps a warp's state in shared memory too).  A task
-// is a seed: batch edge e_ord mapped onto the directed query edge (x, y).
-// Query vertices are matched in the plan's order; at level l the candidates
-// of u = order[l] are the label-l subrange of the shortest neighbour list
-// among u's already-matched query neighbours (GenCandidates: candidate table
-// bit, then intersection with every matched neighbour's list).  The 64 lanes
-// take 64 consecutive entries of that subrange per step (one coalesced
-// read); each lane checks its entry against the candidate table, the
-// injectivity of the partial match, and membership in every other
+// One wavefront (64 lanes) owns one work item at a time and keeps its DFS
+// state in LDS.  A work item is a seed (batch edge e_ord mapped onto the
+// directed query edge (x, y)) or a piece of another wave's search handed
+// over to it.  Query vertices are matched in the plan's order; at level l
+// the candidates of u = order[l] are the label subrange of the shortest
+// neighbour list among u's already-matched query neighbours (GenCandidates:
+// candidate-table bit, then intersection with every matched neighbour's
+// list).  The 64 lanes take 64 consecutive entries of that subrange per step
+// (one coalesced read); each lane checks its entry against the candidate
+// table, the injectivity of the partial match and membership in every other
 // neighbour list (per-lane binary search restricted to the same label
 // subrange), and a ballot gives the survivor mask.  The wave then descends
-// into survivors one by one (DFS: only the current path is materialised,
-// Sec. IV-C), and at the last level every survivor is a match.
+// into survivors one at a time (only the current path is materialised,
+// Sec. IV-C); at the last level every survivor is a match.
 //
 // Visibility of batch edges (the order rule).  Rows touched by the batch
 // hold G u I with batch entries flagged.  An unflagged entry is an edge of
-// both G and G'.  A flagged entry is usable by the seed with ord i in pass
-// s (1 = insertions, searched on G'; 0 = deletions, searched on G) iff the
-// edge's sign is s and its ord is > i: matches are formed from the seed
-// towards higher-order batch edges, so each match comes from its
-// minimum-ord batch edge exactly once.
+// both G and G'.  A flagged entry is usable by the seed with ord i in pass s
+// (1 = insertions, searched on G'; 0 = deletions, searched on G) iff the
+// edge's sign is s and its ord is > i, so every match is found once, from
+// its minimum-ord batch edge.
+//
+// Load balance.  The paper balances warps inside a thread block through
+// shared memory (Sec. V-A).  A single seed can hold most of a batch's work,
+// so here the balancing spans the whole chip: an idle wave advertises itself
+// in a global bitmap; a busy wave that sees advertised idle waves (it polls
+// a replicated counter every few microseconds) hands over the upper half of
+// its shallowest unexplored work - the untouched part of a level's candidate
+// range, or half the pending survivors of a level's current chunk - together
+// with the partial match above it, through the idle wave's mailbox.
+// Termination: `pending` counts unfinished work items (initially the seeds);
+// the wave that finishes the last one sends every wave the stop message.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -31,12 +42,17 @@ namespace {
 constexpr int DFS_THREADS = 256;
 constexpr int DFS_WAVES = DFS_THREADS / GM_WAVE;
 constexpr int MAX_OTH = 120;  // >= |E(Q)| - 1 for any simple query with k <= 16
+constexpr int TASK_WORDS = 32;
+constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
+constexpr uint64_t POLL_TICKS = 256;                 // wall-clock ticks between polls (100 MHz)
+constexpr uint32_t LEAF_MIN_SPLIT = 8 * GM_WAVE;     // smallest last-level range worth handing over
+constexpr uint32_t INNER_MIN_SPLIT = 2 * GM_WAVE;
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
   uint32_t fx[GM_MAX_K];   // external id of the same
   uint64_t drv[GM_MAX_K];  // arena index where level l's candidate subrange starts
-  uint32_t len[GM_MAX_K];  // length of that subrange
+  uint32_t len[GM_MAX_K];  // end of the range to examine at level l
   uint32_t cur[GM_MAX_K];  // next subrange entry to examine
   uint32_t chunk[GM_MAX_K];
   uint64_t mask[GM_MAX_K]; // survivors of the current chunk not descended into yet
@@ -58,6 +74,11 @@ __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
   int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, GM_WAVE);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
+__device__ inline uint64_t shfl64(uint64_t v, int src) {
+  int lo = __shfl((int)(uint32_t)v, src, GM_WAVE);
+  int hi = __shfl((int)(uint32_t)(v >> 32), src, GM_WAVE);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
 __device__ inline uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
@@ -69,9 +90,15 @@ __device__ inline uint64_t wave_xor64(uint64_t v) {
   return v;
 }
 
+__device__ inline uint32_t ld_coherent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t ld_coherent64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Wave-cooperative lower bound in a sorted (masked) list: first index whose
-// value >= key.  Each step samples 64 evenly spaced entries (64-ary search),
-// so a list of length L takes about log64(L) dependent loads.
+// value >= key.  Each step samples 64 evenly spaced entries (64-ary search).
 __device__ inline uint32_t wave_lb(const uint32_t* __restrict__ col, uint64_t base, uint32_t len,
                                    uint32_t key, int lane, uint64_t& bytes) {
   uint32_t lo = 0, hi = len;
@@ -163,9 +190,9 @@ __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
 }
 
 // Emit the matches of one ballot: lane bit set <=> (prefix, u -> cx) is a match.
-__device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, const GmPlan* pl, uint32_t k,
-                            uint32_t u, bool ok, uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q,
-                            uint32_t sign, uint32_t ord, int lane, uint64_t lt, uint64_t& bytes) {
+__device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t k, uint32_t u, bool ok,
+                            uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q, uint32_t sign,
+                            uint32_t ord, int lane, uint64_t lt, uint64_t& bytes) {
   if (ok) A.cnt += 1;
   uint64_t h = 0;
   if (P.flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
@@ -180,7 +207,7 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, const Gm
     const uint32_t nok = (uint32_t)__popcll(m);
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&P.ctr->tuples_found, (unsigned long long)nok);
-    base = __shfl(base, 0, GM_WAVE);
+    base = shfl64(base, 0);
     const uint64_t pos = base + (uint64_t)__popcll(m & lt);
     if (ok && pos < P.tcap) {
       uint32_t* row = P.tuples + pos * P.twidth;
@@ -203,27 +230,94 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, const Gm
   }
 }
 
+// Tell every wave slot to stop (all work is done; the message carries no data).
+__device__ inline void broadcast_stop(const GmDfsParams& P, int lane) {
+  for (uint32_t s = (uint32_t)lane; s < P.n_slots; s += GM_WAVE)
+    __hip_atomic_store(&P.mflag[s], MSG_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
   __shared__ WaveState WS[DFS_WAVES];
   const int lane = threadIdx.x & 63;
-  WaveState& S = WS[threadIdx.x >> 6];
+  const int wid = threadIdx.x >> 6;
+  WaveState& S = WS[wid];
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const uint32_t n = P.G.n;
   const uint32_t* __restrict__ col = P.G.col;
-  const uint32_t* __restrict__ o2n = P.G.old_of_new;
+  const uint32_t* __restrict__ ext = P.G.ext;
+  // slots are numbered so that waves of one XCD (blocks dispatched round
+  // robin over 8 XCDs) are contiguous: idle searches start near home
+  const uint32_t bpx = (gridDim.x + 7) / 8;
+  const uint32_t slot = ((blockIdx.x & 7) * bpx + (blockIdx.x >> 3)) * DFS_WAVES + wid;
+  const uint32_t nwords = (P.n_slots + 63) / 64;
   Acc A{0, 0, 0, 0xFFFFFFFFu};
-  uint64_t st_nodes = 0, st_scan = 0, st_bytes = 0;
+  uint64_t st_nodes = 0, st_scan = 0, st_bytes = 0, st_steals = 0;
+  uint64_t cy_idle = 0, cy_init = 0, cy_inner = 0, cy_leaf = 0, cy_hand = 0, n_recv = 0;
   const unsigned long long n_seeds = P.ctr->n_seeds;
+  if (n_seeds == 0) return;  // nothing to search (and nobody would send the stop message)
+  bool seeds_left = true;
+  uint64_t last_poll = wall_clock64();
 
   for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&P.ctr->seed_head, 1ull);
-    t = __shfl(t, 0, GM_WAVE);
-    if (t >= n_seeds) break;
-    const GmSeed sd = P.seeds[t];
-    const uint32_t q = uni(sd.qd >> 8), dq = uni(sd.qd & 255u);
-    const uint32_t ord = uni(sd.os >> 1), sign = uni(sd.os & 1u);
-    const uint32_t a = uni(sd.a), b = uni(sd.b);
+    // ------------------------------------------------------------ obtain work
+    uint32_t q, dq, ord, sign, base_l;
+    uint32_t tword = 0;  // handed-over work: lane w holds word w of the task record
+    bool handed = false;
+    if (seeds_left) {
+      unsigned long long t = 0;
+      if (lane == 0) t = atomicAdd(&P.ctr->seed_head, 1ull);
+      t = shfl64(t, 0);
+      if (t < n_seeds) {
+        const GmSeed sd = P.seeds[t];
+        q = uni(sd.qd >> 8);
+        dq = uni(sd.qd & 255u);
+        ord = uni(sd.os >> 1);
+        sign = uni(sd.os & 1u);
+        const GmPlan* pl = P.plans + P.queries[q].plan_base + dq;
+        const uint32_t x = uni(pl->x), y = uni(pl->y);
+        S.f[x] = uni(sd.a);
+        S.f[y] = uni(sd.b);
+        base_l = 2;
+      } else {
+        seeds_left = false;
+      }
+    }
+    if (!seeds_left) {
+      if (!P.donate) break;
+      // advertise, then wait for a task or the stop message
+      const uint64_t bit = 1ull << (slot & 63);
+      atomicAdd(&P.idle_rep[lane], 1u);  // count first: a claimer decrements after claiming the bit
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) atomicOr(&P.idle_bits[slot >> 6], (unsigned long long)bit);
+      uint32_t msg = 0;
+      int nap = 1;
+      const uint64_t t_idle0 = __builtin_readcyclecounter();
+      for (;;) {
+        if (lane == 0) msg = ld_coherent(&P.mflag[slot]);
+        msg = uni(__shfl(msg, 0, GM_WAVE));
+        if (msg) break;
+        for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(32);
+        nap = nap < 16 ? nap * 2 : 16;
+      }
+      cy_idle += __builtin_readcyclecounter() - t_idle0;
+      if (msg == MSG_STOP) break;
+      ++n_recv;
+      // MSG_TASK: the donor cleared our idle bit and the replicated count;
+      // its release store on the flag orders the task record before it
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      tword = lane < TASK_WORDS ? P.mbox[(uint64_t)slot * TASK_WORDS + lane] : 0;
+      if (lane == 0) __hip_atomic_store(&P.mflag[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t w = tword;
+      q = uni(__shfl((int)w, 0, GM_WAVE)) >> 8;
+      dq = uni(__shfl((int)w, 0, GM_WAVE)) & 255u;
+      const uint32_t os = uni(__shfl((int)w, 1, GM_WAVE));
+      ord = os >> 1;
+      sign = os & 1u;
+      base_l = uni(__shfl((int)w, 2, GM_WAVE));
+      if (lane >= 8 && lane < 8 + GM_MAX_K) S.f[lane - 8] = w;
+      handed = true;
+    }
+
     const GmPlan* __restrict__ pl = P.plans + P.queries[q].plan_base + dq;
     const uint32_t k = uni(pl->k);
     const uint32_t key = (q << 1) | sign;
@@ -231,25 +325,28 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       flush_acc(P, A, lane);
       A.key = key;
     }
-    const uint32_t x = uni(pl->x), y = uni(pl->y);
-    const uint32_t ax = uni(o2n[a]), bx = uni(o2n[b]);
-    S.f[x] = a;
-    S.f[y] = b;
-    S.fx[x] = ax;
-    S.fx[y] = bx;
-    st_bytes += 16 + 8;
+    // external ids of the matched prefix (positions < base_l)
+    if ((uint32_t)lane < base_l) {
+      const uint32_t u = pl->order[lane];
+      S.fx[u] = P.G.old_of_new[S.f[u]];
+    }
+    st_bytes += 4ull * base_l;
 
     if (k == 2) {
       // the seed itself is the whole match
       uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
       h = hash_step(h, S.fx[0], 0);
-      const bool ok = lane == 0;
-      emit(P, S, A, pl, 2, 1, ok, 1ull, S.fx[1], h, q, sign, ord, lane, lt, st_bytes);
+      emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], h, q, sign, ord, lane, lt, st_bytes);
+      if (P.donate) {
+        unsigned long long left = 1;
+        if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
+        if (shfl64(left, 0) == 1) broadcast_stop(P, lane);
+      }
       continue;
     }
 
     // ---- level initialisation: candidate subrange of order[l]
-    auto init_level = [&](uint32_t l) -> bool {
+    auto init_level_impl = [&](uint32_t l, bool count) -> bool {
       const uint32_t lab = uni(pl->lab[l]);
       if (lab >= P.G.label_slots) return false;
       const uint32_t lo_id = uni(P.G.label_start[lab]);
@@ -288,7 +385,7 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       S.oth_n[l] = cnt - 1;
       S.cur[l] = 0;
       S.mask[l] = 0;
-      if (lane == 0) ++st_nodes;
+      if (count && lane == 0) ++st_nodes;
       if (l == k - 1) {
         const uint32_t u = uni(pl->order[l]);
         uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
@@ -298,8 +395,15 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       return true;
     };
 
+    auto init_level = [&](uint32_t l, bool count) -> bool {
+      const uint64_t t0 = __builtin_readcyclecounter();
+      const bool r = init_level_impl(l, count);
+      cy_init += __builtin_readcyclecounter() - t0;
+      return r;
+    };
+
     // ---- one chunk of 64 candidates at level l; returns the survivor ballot
-    auto eval_chunk = [&](uint32_t l, uint32_t cur, uint32_t& c_out, bool& ok_out) -> uint64_t {
+    auto eval_chunk = [&](uint32_t l, uint32_t cur, uint32_t& c_out, uint32_t& e_idx, bool& ok_out) -> uint64_t {
       const uint32_t u = uni(pl->order[l]);
       const uint32_t len = uni(S.len[l]);
       const uint32_t idx = cur + (uint32_t)lane;
@@ -338,57 +442,178 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
         }
       }
       c_out = c;
+      e_idx = idx;
       ok_out = ok;
       return __ballot(ok);
     };
 
-    uint32_t l = 2;
-    if (!init_level(2)) continue;
-    for (;;) {
-      uint64_t m = uni64(S.mask[l]);
-      if (m == 0) {
-        const uint32_t cur = uni(S.cur[l]);
-        if (cur >= uni(S.len[l])) {
-          if (l == 2) break;
-          --l;
-          continue;
+    // ---- hand the upper half of the shallowest unexplored work to an idle wave
+    auto try_donate_impl = [&](uint32_t lcur) {
+      uint32_t lv = 0xFFFFFFFFu, kind = 0, mid = 0, old_len = 0;
+      uint64_t give = 0;
+      for (uint32_t x = base_l; x <= lcur; ++x) {
+        const uint32_t cur = uni(S.cur[x]), len = uni(S.len[x]);
+        const uint32_t min_split = (x == k - 1) ? LEAF_MIN_SPLIT : INNER_MIN_SPLIT;
+        if (len > cur && len - cur >= min_split) {
+          lv = x;
+          kind = 1;
+          mid = cur + ((len - cur) >> 1);
+          old_len = len;
+          break;
         }
-        S.cur[l] = cur + GM_WAVE;
-        S.chunk[l] = cur;
-        uint32_t c;
-        bool ok;
-        m = eval_chunk(l, cur, c, ok);
-        if (l == k - 1) {
-          if (m) {
-            const uint32_t u = uni(pl->order[l]);
-            uint32_t cx = 0;
-            if (ok && (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE))) {
-              cx = o2n[c];
-              st_bytes += 4;
-            }
-            emit(P, S, A, pl, k, u, ok, m, cx, uni64(S.hpre), q, sign, ord, lane, lt, st_bytes);
+        if (x + 1 < k) {
+          const uint64_t m = uni64(S.mask[x]);
+          const int pc = __popcll(m);
+          if (pc >= 2) {
+            uint64_t hi = m;
+            for (int i = 0; i < (pc + 1) / 2; ++i) hi &= hi - 1;  // drop the lower half
+            lv = x;
+            kind = 2;
+            give = hi;
+            break;
           }
-          continue;
         }
-        S.mask[l] = m;
-        if (m == 0) continue;
       }
-      const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;
-      S.mask[l] = m & (m - 1);
-      const uint32_t c = uni(col[uni64(S.drv[l]) + uni(S.chunk[l]) + bit] & GM_IDMASK);
-      const uint32_t u = uni(pl->order[l]);
-      S.f[u] = c;
-      S.fx[u] = uni(o2n[c]);
-      st_bytes += 8;
-      if (init_level(l + 1)) ++l;
+      if (kind == 0) return;
+      // claim an advertised idle wave, searching from this wave's own region
+      int32_t target = -1;
+      const uint32_t start = slot >> 6;
+      for (uint32_t r = 0; r < nwords && target < 0; r += GM_WAVE) {
+        const uint32_t wi = (start + r + (uint32_t)lane) % nwords;
+        const uint64_t v = (r + (uint32_t)lane < nwords) ? ld_coherent64(&P.idle_bits[wi]) : 0ull;
+        uint64_t nz = __ballot(v != 0);
+        int tries = 0;
+        while (nz && target < 0 && tries < 4) {
+          const int ln = __ffsll((unsigned long long)nz) - 1;
+          nz &= nz - 1;
+          ++tries;
+          uint64_t vv = shfl64(v, ln);
+          const uint32_t word = (start + r + (uint32_t)ln) % nwords;
+          while (vv && target < 0) {
+            const int b = __ffsll((unsigned long long)vv) - 1;
+            unsigned long long old = 0;
+            if (lane == 0) old = atomicAnd(&P.idle_bits[word], ~(1ull << b));
+            old = shfl64(old, 0);
+            if ((old >> b) & 1ull)
+              target = (int32_t)(word * 64 + b);
+            else
+              vv = old & ~(1ull << b);
+          }
+        }
+      }
+      if (target < 0) return;
+      atomicSub(&P.idle_rep[lane], 1u);
+      if (kind == 1)
+        S.len[lv] = mid;
+      else
+        S.mask[lv] = uni64(S.mask[lv]) & ~give;
+      uint32_t w = 0;
+      if (lane == 0) w = (q << 8) | dq;
+      else if (lane == 1) w = (ord << 1) | sign;
+      else if (lane == 2) w = lv;
+      else if (lane == 3) w = kind == 2 ? uni(S.chunk[lv]) : 0u;
+      else if (lane == 4) w = (uint32_t)give;
+      else if (lane == 5) w = (uint32_t)(give >> 32);
+      else if (lane == 6) w = kind == 1 ? mid : 0u;
+      else if (lane == 7) w = kind == 1 ? old_len : 0u;
+      else if (lane < 8 + GM_MAX_K) w = S.f[lane - 8];
+      if (lane == 0) atomicAdd(&P.ctr->pending, 1ull);
+      if (lane < TASK_WORDS) P.mbox[(uint64_t)target * TASK_WORDS + lane] = w;
+      if (lane == 0) {
+        __hip_atomic_store(&P.mflag[target], MSG_TASK, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ++st_steals;
+      }
+    };
+
+    auto try_donate = [&](uint32_t lcur) {
+      const uint64_t t0 = __builtin_readcyclecounter();
+      try_donate_impl(lcur);
+      cy_hand += __builtin_readcyclecounter() - t0;
+    };
+
+    uint32_t l = base_l;
+    if (!init_level(l, !handed)) {
+      // an empty first level (a seed with no extension)
+    } else {
+      if (handed) {
+        S.cur[l] = uni(__shfl((int)tword, 6, GM_WAVE));
+        S.len[l] = uni(__shfl((int)tword, 7, GM_WAVE));
+        S.chunk[l] = uni(__shfl((int)tword, 3, GM_WAVE));
+        const uint32_t mlo = uni(__shfl((int)tword, 4, GM_WAVE));
+        const uint32_t mhi = uni(__shfl((int)tword, 5, GM_WAVE));
+        S.mask[l] = ((uint64_t)mhi << 32) | mlo;
+      }
+      for (;;) {
+        uint64_t m = uni64(S.mask[l]);
+        if (m == 0) {
+          if (P.donate) {
+            const uint64_t now = wall_clock64();
+            if (now - last_poll >= POLL_TICKS) {
+              last_poll = now;
+              if (ld_coherent(&P.idle_rep[slot & 63]) != 0) try_donate(l);
+            }
+          }
+          const uint32_t cur = uni(S.cur[l]);
+          if (cur >= uni(S.len[l])) {
+            if (l == base_l) break;
+            --l;
+            continue;
+          }
+          S.cur[l] = cur + GM_WAVE;
+          S.chunk[l] = cur;
+          uint32_t c, eidx;
+          bool ok;
+          const uint64_t t_ev = __builtin_readcyclecounter();
+          m = eval_chunk(l, cur, c, eidx, ok);
+          if (l == k - 1) {
+            if (m) {
+              const uint32_t u = uni(pl->order[l]);
+              uint32_t cx = 0;
+              if (ok && (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE))) {
+                cx = ext[uni64(S.drv[l]) + eidx];
+                st_bytes += 4;
+              }
+              emit(P, S, A, k, u, ok, m, cx, uni64(S.hpre), q, sign, ord, lane, lt, st_bytes);
+            }
+            cy_leaf += __builtin_readcyclecounter() - t_ev;
+            continue;
+          }
+          cy_inner += __builtin_readcyclecounter() - t_ev;
+          S.mask[l] = m;
+          if (m == 0) continue;
+        }
+        const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;
+        S.mask[l] = m & (m - 1);
+        const uint64_t at = uni64(S.drv[l]) + uni(S.chunk[l]) + bit;
+        const uint32_t c = uni(col[at] & GM_IDMASK);
+        const uint32_t u = uni(pl->order[l]);
+        S.f[u] = c;
+        S.fx[u] = uni(ext[at]);
+        st_bytes += 8;
+        if (init_level(l + 1, true)) ++l;
+      }
+    }
+    // ---- work item finished
+    if (P.donate) {
+      unsigned long long left = 1;
+      if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
+      if (shfl64(left, 0) == 1) broadcast_stop(P, lane);
     }
   }
   flush_acc(P, A, lane);
   const uint64_t sn = wave_sum64(st_nodes), ss = wave_sum64(st_scan), sb = wave_sum64(st_bytes);
+  const uint64_t sw = wave_sum64(st_steals);
   if (lane == 0) {
+    atomicAdd(&P.ctr->cyc[0], (unsigned long long)cy_idle);
+    atomicAdd(&P.ctr->cyc[1], (unsigned long long)cy_init);
+    atomicAdd(&P.ctr->cyc[2], (unsigned long long)cy_inner);
+    atomicAdd(&P.ctr->cyc[3], (unsigned long long)cy_leaf);
+    atomicAdd(&P.ctr->cyc[4], (unsigned long long)cy_hand);
+    atomicAdd(&P.ctr->cyc[5], (unsigned long long)n_recv);
     atomicAdd(&P.ctr->dfs_nodes, (unsigned long long)sn);
     atomicAdd(&P.ctr->cand_scanned, (unsigned long long)ss);
     atomicAdd(&P.ctr->bytes_alg, (unsigned long long)sb);
+    atomicAdd(&P.ctr->steals, (unsigned long long)sw);
   }
 }
 
@@ -397,6 +622,8 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
 namespace gm {
 
 unsigned dfs_block_threads() { return DFS_THREADS; }
+unsigned dfs_waves_per_block() { return DFS_WAVES; }
+uint32_t dfs_slots(unsigned blocks) { return 8u * ((blocks + 7) / 8) * DFS_WAVES; }
 
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s) {
   k_dfs<<<blocks, DFS_THREADS, 0, s>>>(P);

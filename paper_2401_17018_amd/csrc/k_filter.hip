@@ -102,6 +102,9 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
   }
 }
 
+// The search starts with one unfinished work item per seed.
+__global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds; }
+
 unsigned grid_for(uint64_t work, unsigned per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -119,6 +122,8 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint3
   if (!nv) return;
   k_filter<<<grid_for(nv, 256), 256, 0, s>>>(G, verts, nv, lab_fstart, fe, reqs, cand, only_q);
 }
+
+void launch_pending_init(GmCounters* ctr, hipStream_t s) { k_pending_init<<<1, 1, 0, s>>>(ctr); }
 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,

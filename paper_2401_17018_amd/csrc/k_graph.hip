@@ -180,6 +180,13 @@ __global__ void k_u32_to_u64(const uint32_t* __restrict__ in, uint64_t* __restri
     out[v] = in[v];
 }
 
+__global__ void k_gather_ext(const uint32_t* __restrict__ col, const uint32_t* __restrict__ o2n,
+                             uint64_t nnz, uint32_t* __restrict__ ext) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    ext[i] = o2n[col[i] & GM_IDMASK];
+}
+
 unsigned grid_for(uint64_t work, unsigned per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -235,6 +242,12 @@ void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n
 void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
                       const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s) {
   k_copy_rows<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(row_off, row_len, src, new_off, dst, n);
+}
+
+void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,
+                       hipStream_t s) {
+  if (!nnz) return;
+  k_gather_ext<<<grid_for(nnz, 256), 256, 0, s>>>(col, old_of_new, nnz, ext);
 }
 
 void launch_u32_to_u64(const uint32_t* in, uint64_t* out, uint32_t n, hipStream_t s) {

@@ -11,6 +11,7 @@ struct GmGraphDev {
   uint64_t* row_off;              // [n]
   uint32_t* row_len;              // [n]
   uint32_t* col;                  // arena; bit 31 marks batch entries
+  uint32_t* ext;                  // parallel arena: external id of each col entry
   const uint16_t* vlabel;         // [n]
   const uint32_t* label_start;    // [label_slots + 1]
   uint32_t label_slots;           // labels >= label_slots occur nowhere
@@ -39,6 +40,10 @@ struct GmCounters {
   unsigned long long bytes_alg;
   unsigned long long steals;
   unsigned long long bytes_update;
+  unsigned long long cyc[6];      // idle, init, inner, leaf, hand-over cycles; tasks received
+  unsigned long long pending;     // work items taken or handed over and not finished
+  unsigned int idle_count;        // waves advertised in the idle bitmap
+  unsigned int seeds_done;        // set once a wave found the seed queue empty
 };
 
 struct GmDfsParams {
@@ -57,6 +62,13 @@ struct GmDfsParams {
   uint32_t* tord;
   uint64_t tcap;
   unsigned long long* upd_res;    // [n_canon][3]
+  // work hand-over between waves (one mailbox per wave slot)
+  uint32_t* mbox;                 // [n_slots][32] task records
+  uint32_t* mflag;                // [n_slots] 1 = a task waits in the mailbox
+  unsigned long long* idle_bits;  // [ceil(n_slots / 64)]
+  uint32_t* idle_rep;             // [64] replicated count of advertised idle waves
+  uint32_t n_slots;
+  uint32_t donate;                // 0 = no hand-over (each wave keeps its seed)
 };
 
 namespace gm {
@@ -81,6 +93,8 @@ void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n
 void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
                       const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s);
 void launch_u32_to_u64(const uint32_t* in, uint64_t* out, uint32_t n, hipStream_t s);
+void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,
+                       hipStream_t s);
 
 // batch (k_batch.hip)
 void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd,
@@ -112,6 +126,7 @@ void launch_rows_commit(const uint32_t* touched, const uint64_t* r2_off, const u
 void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s);
+void launch_pending_init(GmCounters* ctr, hipStream_t s);
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
@@ -120,5 +135,8 @@ void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_
 // search (k_dfs.hip)
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);
 unsigned dfs_block_threads();
+unsigned dfs_waves_per_block();
+// mailbox slots needed for a grid of `blocks` search blocks
+uint32_t dfs_slots(unsigned blocks);
 
 }  // namespace gm

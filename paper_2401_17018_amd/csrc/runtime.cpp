@@ -69,7 +69,7 @@ struct gamma_ctx {
   uint64_t arena_cap = 0, arena_top = 0;
   uint32_t label_slots = 1;
   std::vector<uint64_t> label_count;  // data vertices per label
-  DevBuf row_off, row_len, vlabel, label_start, new_of_old, old_of_new, arena;
+  DevBuf row_off, row_len, vlabel, label_start, new_of_old, old_of_new, arena, arena_ext;
 
   // queries
   std::vector<gm::HostQuery> queries;
@@ -83,6 +83,7 @@ struct gamma_ctx {
   DevBuf runvals, runscan, touched, run_start, run_end, sizes, r1off, r2_off, r2_len;
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
   DevBuf tmp64a, tmp64b, tmp32a;
+  DevBuf mbox, mflag, idle_bits, idle_rep;
 
   // host side results
   void* h_pinned = nullptr;
@@ -101,6 +102,7 @@ struct gamma_ctx {
 
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
+                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep,
                       &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
@@ -170,6 +172,7 @@ struct gamma_ctx {
     g.row_off = (uint64_t*)row_off.p;
     g.row_len = (uint32_t*)row_len.p;
     g.col = (uint32_t*)arena.p;
+    g.ext = (uint32_t*)arena_ext.p;
     g.vlabel = (const uint16_t*)vlabel.p;
     g.label_start = (const uint32_t*)label_start.p;
     g.label_slots = label_slots;
@@ -399,7 +402,7 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
 
     // new graph buffers (built aside, swapped in at the end)
     gamma_ctx& C = *c;
-    DevBuf n_row_off, n_row_len, n_vlabel, n_label_start, n_n2o, n_o2n, n_arena;
+    DevBuf n_row_off, n_row_len, n_vlabel, n_label_start, n_n2o, n_o2n, n_arena, n_ext;
     const int ib = bits_for(n);
     {
       uint64_t* keys = C.ensure<uint64_t>(C.keys, n);
@@ -432,12 +435,14 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
       gm::launch_rows_from_scan(offs, deg, n, 0, ro, rl, s);
       uint64_t cap = nnz + std::max<uint64_t>(nnz / 2, 1u << 20);
       uint32_t* ar = C.ensure<uint32_t>(n_arena, cap);
+      uint32_t* ax = C.ensure<uint32_t>(n_ext, cap);
       if (nnz) {
         uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
         uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
         gm::launch_csr_keys(nullptr, nullptr, d_rp, d_col, n2o, n, ib, nullptr, ek, s);
         C.sort_keys(ek, et, nnz, 2 * ib);
         gm::launch_csr_extract(ek, nnz, (1ull << ib) - 1, ar, s);
+        gm::launch_gather_ext(ar, o2n, nnz, ax, s);
       }
       chk(hipGetLastError(), "load launch");
       chk(hipStreamSynchronize(s), "sync");
@@ -460,6 +465,7 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
     swap_in(C.new_of_old, n_n2o);
     swap_in(C.old_of_new, n_o2n);
     swap_in(C.arena, n_arena);
+    swap_in(C.arena_ext, n_ext);
     C.n = n;
     C.idbits = ib;
     C.live = nnz;
@@ -515,19 +521,24 @@ void compact_arena(gamma_ctx* c, uint64_t need) {
   hipStream_t s = c->stream;
   const uint32_t n = c->n;
   uint64_t cap = std::max<uint64_t>(c->arena_cap, 2 * (c->live + need) + (1u << 20));
-  DevBuf na;
+  DevBuf na, nx;
   uint32_t* dst = c->ensure<uint32_t>(na, cap);
+  uint32_t* dstx = c->ensure<uint32_t>(nx, cap);
   uint64_t* deg = c->ensure<uint64_t>(c->tmp64a, (size_t)n + 1);
   gm::launch_deg_mapped(nullptr, (const uint32_t*)c->row_len.p, nullptr, n, deg, s);
   uint64_t* offs = c->ensure<uint64_t>(c->sizes, (size_t)n + 1);
   c->scan64(deg, offs, n);
   gm::launch_copy_rows((const uint64_t*)c->row_off.p, (const uint32_t*)c->row_len.p,
                        (const uint32_t*)c->arena.p, offs, dst, n, s);
+  gm::launch_copy_rows((const uint64_t*)c->row_off.p, (const uint32_t*)c->row_len.p,
+                       (const uint32_t*)c->arena_ext.p, offs, dstx, n, s);
   gm::launch_rows_from_scan(offs, deg, n, 0, (uint64_t*)c->row_off.p, nullptr, s);
   chk(hipGetLastError(), "compact launch");
   chk(hipStreamSynchronize(s), "sync");
   c->release(c->arena);
+  c->release(c->arena_ext);
   c->arena = na;
+  c->arena_ext = nx;
   c->arena_cap = cap;
   c->arena_top = c->live;
 }
@@ -694,7 +705,18 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.tcap = tcap;
       P.upd_res = upd;
       uint32_t wpc = C.opt.waves_per_cu ? C.opt.waves_per_cu : 16;
-      unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / 4);
+      unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / gm::dfs_waves_per_block());
+      const uint32_t slots = gm::dfs_slots(blocks);
+      P.mbox = C.ensure<uint32_t>(C.mbox, (size_t)slots * 32);
+      P.mflag = C.ensure<uint32_t>(C.mflag, slots);
+      P.idle_bits = (unsigned long long*)C.ensure<uint64_t>(C.idle_bits, (slots + 63) / 64);
+      P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 64);
+      P.n_slots = slots;
+      P.donate = (C.opt.steal_set && !C.opt.steal) ? 0u : 1u;
+      gm::fill_u32(P.mflag, 0, slots, s);
+      gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
+      gm::fill_u32(P.idle_rep, 0, 64, s);
+      gm::launch_pending_init(ctr, s);
       gm::launch_dfs(P, blocks, s);
     }
     chk(hipEventRecord(C.ev[5], s), "event");
@@ -792,6 +814,12 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     st.dfs_nodes = h_ctr->dfs_nodes;
     st.steals = h_ctr->steals;
     st.cand_scanned = h_ctr->cand_scanned;
+    st.cyc_idle = h_ctr->cyc[0];
+    st.cyc_init = h_ctr->cyc[1];
+    st.cyc_inner = h_ctr->cyc[2];
+    st.cyc_leaf = h_ctr->cyc[3];
+    st.cyc_handover = h_ctr->cyc[4];
+    st.tasks_received = h_ctr->cyc[5];
     st.bytes_alg_dfs = h_ctr->bytes_alg;
     // merge: read old rows, write R1 and R2; commit: row pointers only
     st.bytes_alg_update = (r1_total - 2ull * n_insert) * 4 + r1_total * 4 + r2_total * 4 + (uint64_t)n_upd * 9;

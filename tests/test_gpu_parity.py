@@ -260,3 +260,30 @@ def test_star_and_edge_closed_forms_on_mid_graph():
         return int(np.sum((cnt1 * cnt2)[centre]))
 
     assert res.count(0, 1) - res.count(0, 0) == star_total(rp2, col2) - star_total(g.row_ptr, g.col)
+
+
+def _skewed_graph(seed):
+    """A small R-MAT graph: hubs give long candidate ranges to split."""
+    lo, hi = W.rmat_edges(12, 30000, seed)
+    rp, col = W.csr_from_edges(1 << 12, lo, hi)
+    return W.Graph(1 << 12, rp, col, W.labels_uniform(1 << 12, 2, seed + 1))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_work_handover_on_off_identical(seed):
+    """Results do not depend on the hand-over of work between waves."""
+    g = _skewed_graph(seed)
+    q = W.query_from_edges(4, [(0, 1), (1, 2), (2, 3)], (0, 1, 0, 1))
+    b = _mixed_batch(g, seed, 300, 100)
+    outs = []
+    for steal in (False, True):
+        with make_ctx(cap=1 << 22, steal=steal) as ctx:
+            ctx.load_graph(g.row_ptr, g.col, g.labels)
+            ctx.register_query(q.k, q.labels, q.edges)
+            outs.append(ctx.apply_batch(b.src, b.dst, b.op, tuples=True, per_update=True))
+    off, on = outs
+    assert np.array_equal(off.counts, on.counts)
+    assert np.array_equal(off.hash_sum, on.hash_sum) and np.array_equal(off.hash_xor, on.hash_xor)
+    assert np.array_equal(off.upd_count, on.upd_count)
+    assert on.stats["steals"] > 0 and off.stats["steals"] == 0
+    check_against_o2(on, g, q, b, check_tuples=not on.truncated)
