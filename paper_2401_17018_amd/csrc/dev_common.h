@@ -36,6 +36,7 @@ struct alignas(16) GmPlan {
   uint16_t lab[GM_MAX_K];  // label of order[l]
   uint8_t pos[GM_MAX_K];   // pos[u] = level at which query vertex u is matched
   uint8_t bofs[GM_MAX_K];  // first slot of level l's neighbour-list records
+  uint8_t lslot[GM_MAX_K]; // label-index slot of order[l]'s label
 };
 
 // Per query: plan range and size.

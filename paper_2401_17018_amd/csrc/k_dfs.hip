@@ -44,9 +44,10 @@ constexpr int DFS_WAVES = DFS_THREADS / GM_WAVE;
 constexpr int MAX_OTH = 120;  // >= |E(Q)| - 1 for any simple query with k <= 16
 constexpr int TASK_WORDS = 32;
 constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
-constexpr uint64_t POLL_TICKS = 256;                 // wall-clock ticks between polls (100 MHz)
+constexpr uint64_t POLL_CYCLES = 6000;               // shader-clock cycles between polls (~2.5 us)
 constexpr uint32_t LEAF_MIN_SPLIT = 8 * GM_WAVE;     // smallest last-level range worth handing over
 constexpr uint32_t INNER_MIN_SPLIT = 2 * GM_WAVE;
+constexpr int LEAF_UNROLL = 4;                       // last-level chunks examined per step
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
@@ -249,14 +250,13 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
   // robin over 8 XCDs) are contiguous: idle searches start near home
   const uint32_t bpx = (gridDim.x + 7) / 8;
   const uint32_t slot = ((blockIdx.x & 7) * bpx + (blockIdx.x >> 3)) * DFS_WAVES + wid;
-  const uint32_t nwords = (P.n_slots + 63) / 64;
   Acc A{0, 0, 0, 0xFFFFFFFFu};
   uint64_t st_nodes = 0, st_scan = 0, st_bytes = 0, st_steals = 0;
   uint64_t cy_idle = 0, cy_init = 0, cy_inner = 0, cy_leaf = 0, cy_hand = 0, n_recv = 0;
   const unsigned long long n_seeds = P.ctr->n_seeds;
   if (n_seeds == 0) return;  // nothing to search (and nobody would send the stop message)
   bool seeds_left = true;
-  uint64_t last_poll = wall_clock64();
+  uint64_t last_poll = __builtin_readcyclecounter();
 
   for (;;) {
     // ------------------------------------------------------------ obtain work
@@ -285,10 +285,10 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
     if (!seeds_left) {
       if (!P.donate) break;
       // advertise, then wait for a task or the stop message
-      const uint64_t bit = 1ull << (slot & 63);
-      atomicAdd(&P.idle_rep[lane], 1u);  // count first: a claimer decrements after claiming the bit
+      // count first (a claimer decrements after claiming), then set our bit
+      atomicAdd(&P.idle_rep[lane], 1u);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (lane == 0) atomicOr(&P.idle_bits[slot >> 6], (unsigned long long)bit);
+      if (lane == 0) atomicOr(&P.idle_bits[slot >> 6], 1ull << (slot & 63));
       uint32_t msg = 0;
       int nap = 1;
       const uint64_t t_idle0 = __builtin_readcyclecounter();
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       cy_idle += __builtin_readcyclecounter() - t_idle0;
       if (msg == MSG_STOP) break;
       ++n_recv;
-      // MSG_TASK: the donor cleared our idle bit and the replicated count;
+      // MSG_TASK: the donor cleared our bit and lowered the idle count;
       // its release store on the flag orders the task record before it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       tword = lane < TASK_WORDS ? P.mbox[(uint64_t)slot * TASK_WORDS + lane] : 0;
@@ -354,16 +354,18 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       st_bytes += 8;
       if (lo_id >= hi_id) return false;
       const uint32_t ob = uni(pl->bofs[l]);
+      const uint32_t ls = uni(pl->lslot[l]);
       uint32_t cnt = 0, best = 0xFFFFFFFFu, besti = 0;
       for (uint32_t bm = uni(pl->back[l]); bm; bm &= bm - 1) {
         const uint32_t w = (uint32_t)__ffs(bm) - 1;
         const uint32_t v = uni(S.f[w]);
+        // label subrange of v's row from the label index (row offset and
+        // index entry are independent loads)
         const uint64_t off = uni64(P.G.row_off[v]);
-        const uint32_t len = uni(P.G.row_len[v]);
-        st_bytes += 12;
-        const uint32_t s0 = uni(wave_lb(col, off, len, lo_id, lane, st_bytes));
-        const uint32_t s1 = s0 + uni(wave_lb(col, off + s0, len - s0, hi_id, lane, st_bytes));
-        const uint32_t sub = s1 - s0;
+        const uint64_t li = uni64(P.lix[(uint64_t)v * P.lix_slots + ls]);
+        st_bytes += 16;
+        const uint32_t s0 = (uint32_t)li;
+        const uint32_t sub = (uint32_t)(li >> 32);
         if (sub == 0) return false;
         S.oth_base[ob + cnt] = off + s0;
         S.oth_len[ob + cnt] = sub;
@@ -475,21 +477,21 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
         }
       }
       if (kind == 0) return;
-      // claim an advertised idle wave, searching from this wave's own region
+      // claim an idle wave: scan the bitmap (64 words per coherent load) from
+      // a pseudo-random word, clear one set bit with an atomic AND.  No waiting.
       int32_t target = -1;
-      const uint32_t start = slot >> 6;
+      const uint32_t nwords = (P.n_slots + 63) / 64;
+      const uint32_t start = (uint32_t)(gm_mix64(((uint64_t)slot << 20) ^ __builtin_readcyclecounter()) % nwords);
       for (uint32_t r = 0; r < nwords && target < 0; r += GM_WAVE) {
         const uint32_t wi = (start + r + (uint32_t)lane) % nwords;
         const uint64_t v = (r + (uint32_t)lane < nwords) ? ld_coherent64(&P.idle_bits[wi]) : 0ull;
         uint64_t nz = __ballot(v != 0);
-        int tries = 0;
-        while (nz && target < 0 && tries < 4) {
+        for (int tries = 0; nz && target < 0 && tries < 2; ++tries) {
           const int ln = __ffsll((unsigned long long)nz) - 1;
           nz &= nz - 1;
-          ++tries;
           uint64_t vv = shfl64(v, ln);
           const uint32_t word = (start + r + (uint32_t)ln) % nwords;
-          while (vv && target < 0) {
+          for (int b_try = 0; vv && target < 0 && b_try < 4; ++b_try) {
             const int b = __ffsll((unsigned long long)vv) - 1;
             unsigned long long old = 0;
             if (lane == 0) old = atomicAnd(&P.idle_bits[word], ~(1ull << b));
@@ -525,6 +527,97 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       }
     };
 
+    // ---- last level: LEAF_UNROLL chunks per step.  Ids and external ids are
+    // loaded together, and the binary searches in the other back-neighbour
+    // lists run interleaved, so every memory round trip serves 4 chunks.
+    auto leaf_step = [&](uint32_t cur) {
+      const uint32_t l = k - 1;
+      const uint32_t u = uni(pl->order[l]);
+      const uint32_t len = uni(S.len[l]);
+      const uint64_t drv = uni64(S.drv[l]);
+      const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
+      uint32_t e[LEAF_UNROLL], x[LEAF_UNROLL];
+      bool ok[LEAF_UNROLL];
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) {
+        const uint32_t idx = cur + (uint32_t)(j * GM_WAVE + lane);
+        ok[j] = idx < len;
+        e[j] = ok[j] ? col[drv + idx] : 0u;
+        x[j] = (ok[j] && need_x) ? ext[drv + idx] : 0u;
+        if (ok[j]) {
+          st_bytes += need_x ? 8 : 4;
+          ++st_scan;
+        }
+      }
+      for (uint32_t jj = 0; jj < l; ++jj) {
+        const uint32_t fv = uni(S.f[pl->order[jj]]);
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
+      }
+      const uint32_t fdrv = uni(S.f[S.drvw[l]]);
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j)
+        if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, fdrv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+      const uint32_t on = uni(S.oth_n[l]);
+      const uint32_t ob = uni(pl->bofs[l]);
+      for (uint32_t i = 0; i < on; ++i) {
+        bool anyok = false;
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) anyok = anyok || ok[j];
+        if (!__ballot(anyok)) break;
+        const uint64_t base = S.oth_base[ob + i];
+        const uint32_t olen = uni(S.oth_len[ob + i]);
+        uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          lo[j] = 0;
+          cnt[j] = ok[j] ? olen : 0u;
+        }
+        for (;;) {
+          uint32_t v[LEAF_UNROLL];
+          bool any = false;
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            v[j] = cnt[j] ? (col[base + lo[j] + (cnt[j] >> 1)] & GM_IDMASK) : 0u;
+            if (cnt[j]) st_bytes += 4;
+          }
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            if (cnt[j]) {
+              any = true;
+              const uint32_t half = cnt[j] >> 1;
+              if (v[j] < (e[j] & GM_IDMASK)) {
+                lo[j] += half + 1;
+                cnt[j] -= half + 1;
+              } else {
+                cnt[j] = half;
+              }
+            }
+          }
+          if (!__ballot(any)) break;
+        }
+        const uint32_t wv = uni(S.f[S.oth_w[ob + i]]);
+        uint32_t e2[LEAF_UNROLL];
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const bool in = ok[j] && lo[j] < olen;
+          e2[j] = in ? col[base + lo[j]] : 0u;
+          if (ok[j]) {
+            if (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK)) ok[j] = false;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j)
+          if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+      }
+      const uint64_t hpre = uni64(S.hpre);
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) {
+        const uint64_t m = __ballot(ok[j]);
+        if (m) emit(P, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
+      }
+    };
+
     auto try_donate = [&](uint32_t lcur) {
       const uint64_t t0 = __builtin_readcyclecounter();
       try_donate_impl(lcur);
@@ -547,10 +640,15 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
         uint64_t m = uni64(S.mask[l]);
         if (m == 0) {
           if (P.donate) {
-            const uint64_t now = wall_clock64();
-            if (now - last_poll >= POLL_TICKS) {
+            const uint64_t now = __builtin_readcyclecounter();
+            if (now - last_poll >= POLL_CYCLES) {
               last_poll = now;
-              if (ld_coherent(&P.idle_rep[slot & 63]) != 0) try_donate(l);
+              // gate: with c idle waves, about 8c of the busy waves try per period
+              const uint32_t c = ld_coherent(&P.idle_rep[slot & 63]);
+              if (c != 0 && c < 0x80000000u) {
+                const uint32_t roll = (uint32_t)gm_mix64(((uint64_t)slot << 32) ^ now) & 1023u;
+                if (roll < (c >= 128 ? 1024u : c * 8u)) try_donate(l);
+              }
             }
           }
           const uint32_t cur = uni(S.cur[l]);
@@ -559,25 +657,18 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
             --l;
             continue;
           }
+          const uint64_t t_ev = __builtin_readcyclecounter();
+          if (l == k - 1) {
+            S.cur[l] = cur + LEAF_UNROLL * GM_WAVE;
+            leaf_step(cur);
+            cy_leaf += __builtin_readcyclecounter() - t_ev;
+            continue;
+          }
           S.cur[l] = cur + GM_WAVE;
           S.chunk[l] = cur;
           uint32_t c, eidx;
           bool ok;
-          const uint64_t t_ev = __builtin_readcyclecounter();
           m = eval_chunk(l, cur, c, eidx, ok);
-          if (l == k - 1) {
-            if (m) {
-              const uint32_t u = uni(pl->order[l]);
-              uint32_t cx = 0;
-              if (ok && (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE))) {
-                cx = ext[uni64(S.drv[l]) + eidx];
-                st_bytes += 4;
-              }
-              emit(P, S, A, k, u, ok, m, cx, uni64(S.hpre), q, sign, ord, lane, lt, st_bytes);
-            }
-            cy_leaf += __builtin_readcyclecounter() - t_ev;
-            continue;
-          }
           cy_inner += __builtin_readcyclecounter() - t_ev;
           S.mask[l] = m;
           if (m == 0) continue;

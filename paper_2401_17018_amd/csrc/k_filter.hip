@@ -102,6 +102,29 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
   }
 }
 
+// Label index (thread per (row, indexed label)): the subrange [start,
+// start + len) of the row holding neighbours with that label.  Rows are
+// sorted by label-grouped ids, so this is two binary searches.
+__global__ void k_label_index(GmGraphDev G, const uint32_t* __restrict__ verts, uint32_t nv,
+                              const uint32_t* __restrict__ slot_labels, uint32_t n_slots,
+                              unsigned long long* __restrict__ lix) {
+  const uint64_t total = (uint64_t)nv * n_slots;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = (uint32_t)(w / n_slots), sl = (uint32_t)(w % n_slots);
+    const uint32_t v = verts ? verts[i] : i;
+    const uint32_t lab = slot_labels[sl];
+    uint32_t s0 = 0, s1 = 0;
+    if (lab < G.label_slots) {
+      const uint64_t off = G.row_off[v];
+      const uint32_t len = G.row_len[v];
+      s0 = lb_masked(G.col, off, len, G.label_start[lab]);
+      s1 = s0 + lb_masked(G.col, off + s0, len - s0, G.label_start[lab + 1]);
+    }
+    lix[(uint64_t)v * n_slots + sl] = (unsigned long long)s0 | ((unsigned long long)(s1 - s0) << 32);
+  }
+}
+
 // The search starts with one unfinished work item per seed.
 __global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds; }
 
@@ -124,6 +147,12 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint3
 }
 
 void launch_pending_init(GmCounters* ctr, hipStream_t s) { k_pending_init<<<1, 1, 0, s>>>(ctr); }
+
+void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
+                        uint32_t n_slots, unsigned long long* lix, hipStream_t s) {
+  if (!nv || !n_slots) return;
+  k_label_index<<<grid_for((uint64_t)nv * n_slots, 256), 256, 0, s>>>(G, verts, nv, slot_labels, n_slots, lix);
+}
 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,

@@ -42,12 +42,12 @@ struct GmCounters {
   unsigned long long bytes_update;
   unsigned long long cyc[6];      // idle, init, inner, leaf, hand-over cycles; tasks received
   unsigned long long pending;     // work items taken or handed over and not finished
-  unsigned int idle_count;        // waves advertised in the idle bitmap
-  unsigned int seeds_done;        // set once a wave found the seed queue empty
 };
 
 struct GmDfsParams {
   GmGraphDev G;
+  const unsigned long long* lix;  // [n][lix_slots]: label subrange of each row, start | len << 32
+  uint32_t lix_slots;
   const GmPlan* plans;
   const GmQueryDev* queries;
   const uint16_t* cand;           // [nq][n]
@@ -65,8 +65,8 @@ struct GmDfsParams {
   // work hand-over between waves (one mailbox per wave slot)
   uint32_t* mbox;                 // [n_slots][32] task records
   uint32_t* mflag;                // [n_slots] 1 = a task waits in the mailbox
-  unsigned long long* idle_bits;  // [ceil(n_slots / 64)]
-  uint32_t* idle_rep;             // [64] replicated count of advertised idle waves
+  unsigned long long* idle_bits;  // [ceil(n_slots / 64)] bit set = the wave waits for work
+  uint32_t* idle_rep;             // [64] replicated count of idle waves (a polling hint)
   uint32_t n_slots;
   uint32_t donate;                // 0 = no hand-over (each wave keeps its seed)
 };
@@ -127,6 +127,9 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint3
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s);
 void launch_pending_init(GmCounters* ctr, hipStream_t s);
+// label index: for rows `verts` (or all rows), the subrange of each indexed label
+void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
+                        uint32_t n_slots, unsigned long long* lix, hipStream_t s);
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,

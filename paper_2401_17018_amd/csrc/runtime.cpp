@@ -84,6 +84,8 @@ struct gamma_ctx {
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
+  DevBuf lix, lix_lab;
+  std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
 
   // host side results
   void* h_pinned = nullptr;
@@ -102,7 +104,7 @@ struct gamma_ctx {
 
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
-                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep,
+                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab,
                       &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
@@ -216,6 +218,20 @@ struct gamma_ctx {
   void upload_plans() {
     std::vector<GmPlan> all_plans;
     std::vector<GmQueryDev> qd;
+    lix_labels.clear();
+    for (auto& q : queries)
+      for (uint32_t l : q.labels) lix_labels.push_back(l);
+    std::sort(lix_labels.begin(), lix_labels.end());
+    lix_labels.erase(std::unique(lix_labels.begin(), lix_labels.end()), lix_labels.end());
+    for (auto& q : queries)
+      for (auto& p : q.plans)
+        for (uint32_t l = 0; l < q.k; ++l)
+          p.lslot[l] = (uint8_t)(std::lower_bound(lix_labels.begin(), lix_labels.end(), (uint32_t)p.lab[l]) -
+                                 lix_labels.begin());
+    if (!lix_labels.empty()) {
+      uint32_t* dl = ensure<uint32_t>(lix_lab, lix_labels.size());
+      chk(hipMemcpyAsync(dl, lix_labels.data(), lix_labels.size() * 4, hipMemcpyHostToDevice, stream), "h2d");
+    }
     for (auto& q : queries) {
       GmQueryDev d{};
       d.k = q.k;
@@ -235,6 +251,21 @@ struct gamma_ctx {
       chk(hipMemcpyAsync(dq, qd.data(), qd.size() * sizeof(GmQueryDev), hipMemcpyHostToDevice, stream),
           "h2d");
     chk(hipStreamSynchronize(stream), "sync");
+  }
+
+  // Label index of every row for the current label-index slots.
+  void full_label_index() {
+    if (!has_graph || lix_labels.empty()) return;
+    unsigned long long* L = (unsigned long long*)ensure<uint64_t>(lix, (size_t)n * lix_labels.size());
+    gm::launch_label_index(G(), nullptr, n, (const uint32_t*)lix_lab.p, (uint32_t)lix_labels.size(), L, stream);
+    chk(hipGetLastError(), "label index launch");
+    chk(hipStreamSynchronize(stream), "sync");
+  }
+
+  void touched_label_index(const uint32_t* verts, uint32_t nv) {
+    if (lix_labels.empty()) return;
+    gm::launch_label_index(G(), verts, nv, (const uint32_t*)lix_lab.p, (uint32_t)lix_labels.size(),
+                           (unsigned long long*)lix.p, stream);
   }
 
   // Candidate table for every query (or one) over all vertices.
@@ -478,6 +509,8 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
       C.rebuild_filter_tables();
       C.release(C.cand);
       C.full_filter(0xFFFFFFFFu);
+      C.release(C.lix);
+      C.full_label_index();
     }
     return GAMMA_OK;
   });
@@ -504,6 +537,7 @@ gamma_status gamma_register_query(gamma_ctx* c, uint32_t k, const uint32_t* qlab
       if (c->has_graph) {
         c->rebuild_filter_tables();
         c->full_filter(qi);
+        c->full_label_index();
       }
     } catch (const StatusError&) {
       c->queries.pop_back();
@@ -652,6 +686,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     G = C.G();
     gm::launch_merge(dk, rsc, tch, rs_, re_, r1, n_touched, r1_total, base1, base2, ib, G, s);
     gm::launch_rows_set(tch, rs_, re_, rsc, r1, n_touched, base1, base2, G, r2o, r2l, s);
+    C.touched_label_index(tch, n_touched);
     C.arena_top += r1_total + r2_total;
     chk(hipEventRecord(C.ev[2], s), "event");
 
@@ -690,6 +725,8 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     if (nq && n_canon) {
       GmDfsParams P;
       P.G = G;
+      P.lix = (const unsigned long long*)C.lix.p;
+      P.lix_slots = (uint32_t)C.lix_labels.size();
       P.plans = (const GmPlan*)C.plans.p;
       P.queries = (const GmQueryDev*)C.qdev.p;
       P.cand = (const uint16_t*)C.cand.p;
@@ -723,6 +760,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
 
     // ---------------------------------------------------------- commit G', refresh filter on G'
     gm::launch_rows_commit(tch, r2o, r2l, n_touched, G, s);
+    C.touched_label_index(tch, n_touched);
     if (nq)
       gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
                         (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
