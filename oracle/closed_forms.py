@@ -11,9 +11,10 @@ These pin the oracle with facts that do not come from running a matcher:
     with triangles counted by the textbook node iterator;
   * label-preserving automorphisms of Q act freely on the match set, so every
     result is closed under them and its size is a multiple of |Aut_L(Q)|.
-The multiset hash is the SplitMix64 finaliser (Vigna, public domain) folded
-over the tuple; it lets results be compared at sizes where the tuples are not
-materialised.
+The multiset hash (a checksum of this project, not part of the paper) sums
+position-salted SplitMix64-finaliser hashes of the tuple's elements (Vigna,
+public domain constants) under one final finaliser; it lets results be
+compared at sizes where the tuples are not materialised.
 """
 from __future__ import annotations
 
@@ -37,11 +38,11 @@ def _mix_py(z: int) -> int:
 
 
 def tuple_hash(qid: int, sign: int, f) -> int:
-    """h0 = mix(qid << 1 | sign); h_{j+1} = mix(h_j ^ (f_j + GOLDEN * (j + 1)))."""
-    h = _mix_py((qid << 1) | (1 if sign else 0))
+    """h = mix(mix(qid << 1 | sign) + sum_j mix(f_j + GOLDEN * (j + 1))), sums mod 2^64."""
+    s = _mix_py((qid << 1) | (1 if sign else 0))
     for j, v in enumerate(f):
-        h = _mix_py(h ^ ((int(v) + GOLDEN * (j + 1)) & M64))
-    return h
+        s = (s + _mix_py((int(v) + GOLDEN * (j + 1)) & M64)) & M64
+    return _mix_py(s)
 
 
 def _mix_np(z: np.ndarray) -> np.ndarray:
@@ -59,9 +60,10 @@ def multiset_hash(tuples: np.ndarray, qid: int, sign: int) -> Tuple[int, int, in
     if t.ndim != 2 or t.shape[0] == 0:
         return 0, 0, 0
     with np.errstate(over="ignore"):
-        h = np.full(t.shape[0], _mix_py((qid << 1) | (1 if sign else 0)), dtype=np.uint64)
+        acc = np.full(t.shape[0], _mix_py((qid << 1) | (1 if sign else 0)), dtype=np.uint64)
         for j in range(t.shape[1]):
-            h = _mix_np(h ^ (t[:, j] + np.uint64((GOLDEN * (j + 1)) & M64)))
+            acc = acc + _mix_np(t[:, j] + np.uint64((GOLDEN * (j + 1)) & M64))
+        h = _mix_np(acc)
         s = int(np.sum(h, dtype=np.uint64))
     x = int(np.bitwise_xor.reduce(h))
     return int(t.shape[0]), s, x

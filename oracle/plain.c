@@ -41,9 +41,12 @@
  *   graph whose matches a deletion destroys).
  *
  * Output per pass: the tuples (f(0), ..., f(k-1)) with their seed ord, and
- * count / sum / xor of a per-tuple SplitMix64-finaliser hash:
- *   h0 = mix(qid << 1 | sign), h_{j+1} = mix(h_j ^ (f(j) + G * (j + 1))),
- *   G = 0x9E3779B97F4A7C15, sign = 1 for insertions and 0 for deletions.
+ * count / sum / xor of a per-tuple checksum built from the SplitMix64
+ * finaliser `mix` (a checksum of this project, not part of the paper):
+ *   h = mix( mix(qid << 1 | sign) + sum_j mix(f(j) + G * (j + 1)) ),
+ *   sums mod 2^64, G = 0x9E3779B97F4A7C15, sign = 1 for insertions and 0 for
+ *   deletions.  Position salts make it order-sensitive; the outer mix makes
+ *   it non-linear in the tuple.
  *
  * A `mutant` argument plants a known mistake (tests use it to show that the
  * pins catch each one); 0 is the correct oracle.
@@ -95,9 +98,9 @@ static uint64_t mix(uint64_t z) {
 }
 
 static uint64_t tuple_hash(uint32_t qid, int sign, const uint32_t* f, uint32_t k) {
-  uint64_t h = mix(((uint64_t)qid << 1) | (uint64_t)(sign ? 1 : 0));
-  for (uint32_t j = 0; j < k; ++j) h = mix(h ^ ((uint64_t)f[j] + 0x9E3779B97F4A7C15ull * (j + 1)));
-  return h;
+  uint64_t s = mix(((uint64_t)qid << 1) | (uint64_t)(sign ? 1 : 0));
+  for (uint32_t j = 0; j < k; ++j) s += mix((uint64_t)f[j] + 0x9E3779B97F4A7C15ull * (j + 1));
+  return mix(s);
 }
 
 /* ---------------------------------------------------------------- helpers */
