@@ -59,7 +59,7 @@ struct WaveState {
   uint64_t mask[GM_MAX_K]; // survivors of the current chunk not descended into yet
   uint32_t drvw[GM_MAX_K]; // query vertex whose list drives level l
   uint32_t oth_n[GM_MAX_K];
-  uint64_t hpre;           // hash state over query positions before the last vertex
+  uint64_t hpre;           // checksum salt + element terms of every position but the last vertex
   uint64_t oth_base[MAX_OTH];
   uint32_t oth_len[MAX_OTH];
   uint32_t oth_w[MAX_OTH];
@@ -168,8 +168,10 @@ __device__ inline bool visible(const GmBatchHash& H, uint32_t a, uint32_t c, uin
   return false;
 }
 
-__device__ inline uint64_t hash_step(uint64_t h, uint32_t v, uint32_t j) {
-  return gm_mix64(h ^ ((uint64_t)v + GM_GOLDEN * (uint64_t)(j + 1)));
+// Tuple checksum: h = mix(mix(q << 1 | sign) + sum_j mix(f_j + G (j + 1))).
+// Element term of position j:
+__device__ inline uint64_t elem_hash(uint32_t v, uint32_t j) {
+  return gm_mix64((uint64_t)v + GM_GOLDEN * (uint64_t)(j + 1));
 }
 
 struct Acc {
@@ -198,8 +200,7 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t
   uint64_t h = 0;
   if (P.flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
     if (ok) {
-      h = hash_step(hpre, cx, u);
-      for (uint32_t j = u + 1; j < k; ++j) h = hash_step(h, S.fx[j], j);
+      h = gm_mix64(hpre + elem_hash(cx, u));  // hpre: salt + terms of every other position
       A.sum += h;
       A.xr ^= h;
     }
@@ -334,9 +335,8 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
 
     if (k == 2) {
       // the seed itself is the whole match
-      uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
-      h = hash_step(h, S.fx[0], 0);
-      emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], h, q, sign, ord, lane, lt, st_bytes);
+      const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], 0);
+      emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
       if (P.donate) {
         unsigned long long left = 1;
         if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
@@ -391,7 +391,8 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       if (l == k - 1) {
         const uint32_t u = uni(pl->order[l]);
         uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
-        for (uint32_t j = 0; j < u; ++j) h = hash_step(h, S.fx[j], j);
+        for (uint32_t j = 0; j < k; ++j)
+          if (j != u) h += elem_hash(S.fx[j], j);
         S.hpre = h;
       }
       return true;
