@@ -56,7 +56,7 @@ typedef enum gamma_status {
   GAMMA_ENOMEM = -3,        /* device or host allocation failed (nothing mutated) */
   GAMMA_EUNSUPPORTED = -4,  /* outside the supported envelope (k > 16, disconnected query, ...) */
   GAMMA_ESTATE = -5,        /* call order (e.g. apply_batch before load_graph) */
-  GAMMA_ETIMEDOUT = -6,     /* reserved: deadline exceeded, batch not committed */
+  GAMMA_ETIMEDOUT = -6,     /* search deadline exceeded; batch not committed (graph unchanged) */
   GAMMA_EDEVICE = -7        /* HIP runtime error; the context is poisoned */
 } gamma_status;
 
@@ -70,7 +70,9 @@ typedef struct gamma_options {
   uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 8) */
   uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
   uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
-  uint32_t reserved[8];
+  uint32_t deadline_ms;      /* search deadline per batch (0 = none); past it the batch
+                                returns GAMMA_ETIMEDOUT and is not committed */
+  uint32_t reserved[7];
 } gamma_options;
 
 /* Flags of gamma_apply_batch. */
@@ -117,6 +119,7 @@ typedef struct gamma_batch_stats {
   uint64_t cyc_leaf;       /* evaluating and emitting last-level chunks */
   uint64_t cyc_handover;   /* handing work to idle waves */
   uint64_t tasks_received; /* work items received from other waves */
+  uint64_t seeds_started;  /* seeds taken by the search (all of n_seeds unless timed out) */
 } gamma_batch_stats;
 
 typedef struct gamma_batch_result {
@@ -194,7 +197,11 @@ gamma_status gamma_register_query(gamma_ctx* ctx, uint32_t k, const uint32_t* ql
  * Canonical semantics: duplicates collapse; +e with e in E and -e with e not
  * in E are skipped as no-ops; a self loop or an id >= n gives EINVAL; +e
  * together with -e gives ECONFLICT.  Either error leaves the graph unchanged.
- * Returns OK or TRUNCATED (tuple capacity reached; counts and hashes exact). */
+ * Returns OK or TRUNCATED (tuple capacity reached; counts and hashes exact).
+ * With a deadline (gamma_options.deadline_ms) the search stops cooperatively
+ * once it passes; the call then returns GAMMA_ETIMEDOUT, the graph keeps its
+ * state from before the batch, and `out` holds the partial statistics
+ * (stats.seeds_started tells how far the search got). */
 gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);

@@ -97,7 +97,7 @@ class Context:
     """A device context holding one dynamic data graph and its standing queries."""
 
     def __init__(self, device: int = 0, stream=None, tuple_capacity: int = 0, waves_per_cu: int = 0,
-                 steal: Optional[bool] = None):
+                 steal: Optional[bool] = None, deadline_ms: int = 0):
         self._lib = capi.load_library()
         opt = capi.Options()
         opt.device = device
@@ -108,6 +108,7 @@ class Context:
         if steal is not None:
             opt.steal = 1 if steal else 0
             opt.steal_set = 1
+        opt.deadline_ms = int(deadline_ms)
         self._ptr = ctypes.c_void_p()
         st = self._lib.gamma_create(ctypes.byref(opt), ctypes.byref(self._ptr))
         if st < 0:
@@ -174,6 +175,12 @@ class Context:
         res = capi.BatchResult()
         st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
                                          o if n_upd else None, w1, flags, ctypes.byref(res))
+        if st == capi.GAMMA_ETIMEDOUT:
+            err = GammaError(st, "apply_batch: %s" % (self._lib.gamma_last_error(self._ptr) or b"").decode())
+            err.stats = {name: getattr(res.stats, name) for name, _ in capi.BatchStats._fields_
+                         if not name.startswith("reserved")}
+            err.counts = [[res.queries[i].count[sg] for sg in range(2)] for i in range(int(res.n_queries))]
+            raise err
         _check(self._lib, self._ptr, st, "apply_batch")
         nq = int(res.n_queries)
         counts = np.zeros((nq, 2), dtype=np.uint64)

@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
         ("waves_per_cu", ctypes.c_uint32),
         ("steal", ctypes.c_uint32),
         ("steal_set", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 8),
+        ("deadline_ms", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 7),
     ]
 
 
@@ -81,6 +82,7 @@ class BatchStats(ctypes.Structure):
         ("cyc_leaf", ctypes.c_uint64),
         ("cyc_handover", ctypes.c_uint64),
         ("tasks_received", ctypes.c_uint64),
+        ("seeds_started", ctypes.c_uint64),
     ]
 
 

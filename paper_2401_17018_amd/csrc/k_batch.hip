@@ -260,6 +260,28 @@ __global__ void k_rows_commit(const uint32_t* __restrict__ touched, const uint64
   }
 }
 
+// Commit the G' rows, or put the saved rows back when the search was aborted.
+__global__ void k_rows_finish(const uint32_t* __restrict__ touched, const uint64_t* __restrict__ r2_off,
+                              const uint32_t* __restrict__ r2_len, const uint64_t* __restrict__ r0_off,
+                              const uint32_t* __restrict__ r0_len, uint32_t n_touched, GmGraphDev G,
+                              const GmCounters* __restrict__ ctr) {
+  const bool back = ctr->aborted != 0;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_touched; t += gridDim.x * blockDim.x) {
+    const uint32_t v = touched[t];
+    G.row_off[v] = back ? r0_off[t] : r2_off[t];
+    G.row_len[v] = back ? r0_len[t] : r2_len[t];
+  }
+}
+
+__global__ void k_rows_save(const uint32_t* __restrict__ touched, uint32_t n_touched, GmGraphDev G,
+                            uint64_t* __restrict__ r0_off, uint32_t* __restrict__ r0_len) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_touched; t += gridDim.x * blockDim.x) {
+    const uint32_t v = touched[t];
+    r0_off[t] = G.row_off[v];
+    r0_len[t] = G.row_len[v];
+  }
+}
+
 unsigned grid_for(uint64_t work, unsigned per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -327,6 +349,20 @@ void launch_rows_set(const uint32_t* touched, const uint32_t* run_start, const u
   if (!n_touched) return;
   k_rows_set<<<grid_for(n_touched, 256), 256, 0, s>>>(touched, run_start, run_end, runscan, r1off,
                                                      n_touched, base1, base2, G, r2_off, r2_len);
+}
+
+void launch_rows_finish(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
+                        const uint64_t* r0_off, const uint32_t* r0_len, uint32_t n_touched, GmGraphDev G,
+                        const GmCounters* ctr, hipStream_t s) {
+  if (!n_touched) return;
+  k_rows_finish<<<grid_for(n_touched, 256), 256, 0, s>>>(touched, r2_off, r2_len, r0_off, r0_len, n_touched,
+                                                         G, ctr);
+}
+
+void launch_rows_save(const uint32_t* touched, uint32_t n_touched, GmGraphDev G, uint64_t* r0_off,
+                      uint32_t* r0_len, hipStream_t s) {
+  if (!n_touched) return;
+  k_rows_save<<<grid_for(n_touched, 256), 256, 0, s>>>(touched, n_touched, G, r0_off, r0_len);
 }
 
 void launch_rows_commit(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,

@@ -47,7 +47,10 @@ constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
 constexpr uint64_t POLL_CYCLES = 6000;               // shader-clock cycles between polls (~2.5 us)
 constexpr uint32_t LEAF_MIN_SPLIT = 8 * GM_WAVE;     // smallest last-level range worth handing over
 constexpr uint32_t INNER_MIN_SPLIT = 2 * GM_WAVE;
-constexpr int LEAF_UNROLL = 4;                       // last-level chunks examined per step
+#ifndef GM_LEAF_UNROLL
+#define GM_LEAF_UNROLL 4
+#endif
+constexpr int LEAF_UNROLL = GM_LEAF_UNROLL;          // last-level chunks examined per step
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
@@ -238,7 +241,13 @@ __device__ inline void broadcast_stop(const GmDfsParams& P, int lane) {
     __hip_atomic_store(&P.mflag[s], MSG_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
+#ifdef GM_DFS_WAVES_PER_EU
+#define GM_DFS_ATTR __attribute__((amdgpu_waves_per_eu(GM_DFS_WAVES_PER_EU)))
+#else
+#define GM_DFS_ATTR
+#endif
+
+__global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) {
   __shared__ WaveState WS[DFS_WAVES];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -258,6 +267,8 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
   if (n_seeds == 0) return;  // nothing to search (and nobody would send the stop message)
   bool seeds_left = true;
   uint64_t last_poll = __builtin_readcyclecounter();
+  const uint64_t t_start = wall_clock64();
+  bool abort_now = false;
 
   for (;;) {
     // ------------------------------------------------------------ obtain work
@@ -265,6 +276,10 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
     uint32_t tword = 0;  // handed-over work: lane w holds word w of the task record
     bool handed = false;
     if (seeds_left) {
+      if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) {
+        if (lane == 0) atomicExch(&P.ctr->aborted, 1u);
+        break;
+      }
       unsigned long long t = 0;
       if (lane == 0) t = atomicAdd(&P.ctr->seed_head, 1ull);
       t = shfl64(t, 0);
@@ -294,14 +309,22 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       int nap = 1;
       const uint64_t t_idle0 = __builtin_readcyclecounter();
       for (;;) {
-        if (lane == 0) msg = ld_coherent(&P.mflag[slot]);
+        uint32_t ab = 0;
+        if (lane == 0) {
+          msg = ld_coherent(&P.mflag[slot]);
+          ab = ld_coherent(&P.ctr->aborted);
+        }
         msg = uni(__shfl(msg, 0, GM_WAVE));
+        if (uni(__shfl(ab, 0, GM_WAVE))) {
+          abort_now = true;
+          break;
+        }
         if (msg) break;
         for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(32);
         nap = nap < 16 ? nap * 2 : 16;
       }
       cy_idle += __builtin_readcyclecounter() - t_idle0;
-      if (msg == MSG_STOP) break;
+      if (abort_now || msg == MSG_STOP) break;
       ++n_recv;
       // MSG_TASK: the donor cleared our bit and lowered the idle count;
       // its release store on the flag orders the task record before it
@@ -640,10 +663,21 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
       for (;;) {
         uint64_t m = uni64(S.mask[l]);
         if (m == 0) {
-          if (P.donate) {
-            const uint64_t now = __builtin_readcyclecounter();
-            if (now - last_poll >= POLL_CYCLES) {
-              last_poll = now;
+          const uint64_t now = __builtin_readcyclecounter();
+          if (now - last_poll >= POLL_CYCLES) {
+            last_poll = now;
+            // cooperative deadline: the first wave past it raises the abort
+            // word; every wave checks the word here and leaves
+            uint32_t ab = 0;
+            if (lane == 0) {
+              if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) atomicExch(&P.ctr->aborted, 1u);
+              ab = ld_coherent(&P.ctr->aborted);
+            }
+            if (uni(__shfl(ab, 0, GM_WAVE))) {
+              abort_now = true;
+              break;
+            }
+            if (P.donate) {
               // gate: with c idle waves, about 8c of the busy waves try per period
               const uint32_t c = ld_coherent(&P.idle_rep[slot & 63]);
               if (c != 0 && c < 0x80000000u) {
@@ -685,6 +719,7 @@ __global__ __launch_bounds__(DFS_THREADS) void k_dfs(GmDfsParams P) {
         if (init_level(l + 1, true)) ++l;
       }
     }
+    if (abort_now) break;
     // ---- work item finished
     if (P.donate) {
       unsigned long long left = 1;

@@ -42,6 +42,8 @@ struct GmCounters {
   unsigned long long bytes_update;
   unsigned long long cyc[6];      // idle, init, inner, leaf, hand-over cycles; tasks received
   unsigned long long pending;     // work items taken or handed over and not finished
+  unsigned int aborted;           // set when a wave passed the deadline; every wave then exits
+  unsigned int pad1;
 };
 
 struct GmDfsParams {
@@ -69,6 +71,7 @@ struct GmDfsParams {
   uint32_t* idle_rep;             // [64] replicated count of idle waves (a polling hint)
   uint32_t n_slots;
   uint32_t donate;                // 0 = no hand-over (each wave keeps its seed)
+  uint64_t deadline_ticks;        // wall-clock ticks a wave may search (0 = no deadline)
 };
 
 namespace gm {
@@ -121,6 +124,11 @@ void launch_rows_set(const uint32_t* touched, const uint32_t* run_start, const u
                      uint32_t* r2_len, hipStream_t s);
 void launch_rows_commit(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
                         uint32_t n_touched, GmGraphDev G, hipStream_t s);
+void launch_rows_finish(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
+                        const uint64_t* r0_off, const uint32_t* r0_len, uint32_t n_touched, GmGraphDev G,
+                        const GmCounters* ctr, hipStream_t s);
+void launch_rows_save(const uint32_t* touched, uint32_t n_touched, GmGraphDev G, uint64_t* r0_off,
+                      uint32_t* r0_len, hipStream_t s);
 
 // filter and seeds (k_filter.hip)
 void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,

@@ -84,7 +84,8 @@ struct gamma_ctx {
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
-  DevBuf lix, lix_lab;
+  DevBuf lix, lix_lab, r0_off, r0_len;
+  uint32_t wall_khz = 100000;
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
 
   // host side results
@@ -104,7 +105,7 @@ struct gamma_ctx {
 
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
-                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab,
+                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len,
                       &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
@@ -373,6 +374,9 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cu > 0)
     c->n_cu = cu;
+  int wk = 0;
+  if (hipDeviceGetAttribute(&wk, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && wk > 0)
+    c->wall_khz = (uint32_t)wk;
   for (auto& e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       delete c;
@@ -685,6 +689,9 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     uint32_t* r2l = C.ensure<uint32_t>(C.r2_len, std::max<uint32_t>(n_touched, 1));
     G = C.G();
     gm::launch_merge(dk, rsc, tch, rs_, re_, r1, n_touched, r1_total, base1, base2, ib, G, s);
+    uint64_t* r0o = C.ensure<uint64_t>(C.r0_off, std::max<uint32_t>(n_touched, 1));
+    uint32_t* r0l = C.ensure<uint32_t>(C.r0_len, std::max<uint32_t>(n_touched, 1));
+    gm::launch_rows_save(tch, n_touched, G, r0o, r0l, s);
     gm::launch_rows_set(tch, rs_, re_, rsc, r1, n_touched, base1, base2, G, r2o, r2l, s);
     C.touched_label_index(tch, n_touched);
     C.arena_top += r1_total + r2_total;
@@ -750,6 +757,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 64);
       P.n_slots = slots;
       P.donate = (C.opt.steal_set && !C.opt.steal) ? 0u : 1u;
+      P.deadline_ticks = (uint64_t)C.opt.deadline_ms * C.wall_khz;
       gm::fill_u32(P.mflag, 0, slots, s);
       gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
       gm::fill_u32(P.idle_rep, 0, 64, s);
@@ -759,13 +767,12 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     chk(hipEventRecord(C.ev[5], s), "event");
 
     // ---------------------------------------------------------- commit G', refresh filter on G'
-    gm::launch_rows_commit(tch, r2o, r2l, n_touched, G, s);
+    gm::launch_rows_finish(tch, r2o, r2l, r0o, r0l, n_touched, G, ctr, s);
     C.touched_label_index(tch, n_touched);
     if (nq)
       gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
                         (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
                         (uint16_t*)C.cand.p, 0xFFFFFFFFu, s);
-    C.live = C.live + 2ull * n_insert - 2ull * n_delete;
     chk(hipEventRecord(C.ev[6], s), "event");
 
     // ---------------------------------------------------------- results to host
@@ -858,6 +865,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     st.cyc_leaf = h_ctr->cyc[3];
     st.cyc_handover = h_ctr->cyc[4];
     st.tasks_received = h_ctr->cyc[5];
+    st.seeds_started = std::min<uint64_t>(h_ctr->seed_head, h_ctr->n_seeds);
     st.bytes_alg_dfs = h_ctr->bytes_alg;
     // merge: read old rows, write R1 and R2; commit: row pointers only
     st.bytes_alg_update = (r1_total - 2ull * n_insert) * 4 + r1_total * 4 + r2_total * 4 + (uint64_t)n_upd * 9;
@@ -875,6 +883,12 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     st.ms_commit = el(5, 6);
     ms = el(0, 7);
     st.ms_total = ms;
+    if (h_ctr->aborted) {
+      // rows were put back on the device: the graph is as before the batch
+      C.has_result = false;
+      return fail(c, GAMMA_ETIMEDOUT, "apply_batch: search deadline exceeded; batch not committed");
+    }
+    C.live = C.live + 2ull * n_insert - 2ull * n_delete;
     C.has_result = true;
     C.last_tuples = out->n_tuples;
     C.last_twidth = tw;

@@ -287,3 +287,24 @@ def test_work_handover_on_off_identical(seed):
     assert np.array_equal(off.upd_count, on.upd_count)
     assert on.stats["steals"] > 0 and off.stats["steals"] == 0
     check_against_o2(on, g, q, b, check_tuples=not on.truncated)
+
+
+def test_deadline_aborts_and_leaves_graph_unchanged():
+    """A search past its deadline stops cooperatively (every wave polls the
+    abort word), returns ETIMEDOUT and leaves the graph as before the batch."""
+    lo, hi = W.rmat_edges(14, 200000, 9)
+    rp, col = W.csr_from_edges(1 << 14, lo, hi)
+    g = W.Graph(1 << 14, rp, col, np.zeros(1 << 14, np.uint32))
+    q = W.query_from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)], (0,) * 6)
+    b = _mixed_batch(g, 3, 2000, 500)
+    with make_ctx(cap=0, deadline_ms=1) as ctx:
+        ctx.load_graph(g.row_ptr, g.col, g.labels)
+        ctx.register_query(q.k, q.labels, q.edges)
+        with pytest.raises(GammaError) as ei:
+            ctx.apply_batch(b.src, b.dst, b.op)
+        assert ei.value.status == capi.GAMMA_ETIMEDOUT
+        assert ei.value.stats["seeds_started"] <= ei.value.stats["n_seeds"]
+        erp, ecol, _ = ctx.export_graph()
+        assert np.array_equal(erp, g.row_ptr) and np.array_equal(ecol, g.col)
+        res = ctx.apply_batch(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint8))
+        assert res.counts.sum() == 0
