@@ -11,7 +11,12 @@ Prints one JSON line:
             launch / its average duration (HIP events on the library stream)
   cpu_baseline  the CPU oracle (O2) on a bounded sample of the same batch
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|large|tiny]
+With --workload batched (64 standing queries on the mid graph) the search
+is first tuned on a calibration batch (dry runs), then every timed batch is
+searched twice: with one search launch per query (a dry run) and with all
+queries in one launch (applied); both rates are reported.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|large|tiny|batched]
 """
 from __future__ import annotations
 
@@ -25,6 +30,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("k_dfs.hip", "dev_common.h", "kernels.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2401_17018_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str):
+    """HBM-side bytes per search launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by a copy kernel's
+    reading), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_dfs_%s_hbm-counters.md" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if rec.get("source_sha16") != kernel_source_hash():
+        return None
+    return float(rec["traffic_bytes"])
 
 
 def percentile(xs, p):
@@ -70,11 +102,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large"])
+    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large", "batched"])
+    ap.add_argument("--tune-points", type=int, default=24, help="autotuner evaluations (batched workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steal", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration_mib:
+        # a plain copy kernel of known size: HBM counters read for it give the
+        # bytes-per-count factor used to turn FETCH_SIZE / WRITE_SIZE into bytes
+        import torch
+        n = args.copy_calibration_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -86,6 +134,8 @@ def main():
 
     n_batches = args.warmup + args.steps
     t0 = time.time()
+    if args.workload == "batched":
+        return run_batched(args)
     if args.workload == "mid":
         w = W.mid(n_batches=n_batches)
     elif args.workload == "large":
@@ -171,7 +221,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counter_traffic(w.name),
             "bytes_alg_per_launch": avg_bytes,
             "avg_launch_ms": avg_dfs_s * 1e3,
         },
@@ -179,6 +229,103 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+def run_batched(args):
+    """64 standing queries: one search launch for all of them against one
+    launch per query, on the same batches, after autotuning on a separate
+    calibration batch."""
+    import numpy as np
+    import workloads as W
+    from paper_2401_17018_amd import Context
+
+    n_batches = 1 + args.warmup + args.steps  # batch 0 calibrates the tuner
+    t0 = time.time()
+    w = W.batched_queries(n_batches=n_batches)
+    print("[bench] workload %s generated in %.1fs: n=%d m=%d queries=%d" % (
+        w.name, time.time() - t0, w.graph.n, w.graph.m, len(w.queries)), file=sys.stderr, flush=True)
+    ctx = Context(device=0)
+    ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
+    for q in w.queries:
+        ctx.register_query(q.k, q.labels, q.edges)
+    cb = w.batches[0]
+    t0 = time.time()
+    tune = ctx.autotune(cb.src, cb.dst, cb.op, max_points=args.tune_points, reps=1)
+    print("[bench] autotune %.1fs: %s (%.1f ms, start point %.1f ms)" % (
+        time.time() - t0, tune["tuning"], tune["best_ms"], tune["base_ms"]), file=sys.stderr, flush=True)
+    one = dict(tune["tuning"], query_launch=1)
+    per = dict(tune["tuning"], query_launch=2)
+
+    def timed(b, tuning, dry):
+        ctx.set_tuning(**tuning)
+        t1 = time.perf_counter()
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, dry_run=dry)
+        return (time.perf_counter() - t1) * 1e3, r
+
+    for i in range(args.warmup):
+        b = w.batches[1 + i]
+        timed(b, per, True)
+        timed(b, one, False)
+    lat1, latp, upd, mat, stats = [], [], 0, 0, []
+    for i in range(args.steps):
+        b = w.batches[1 + args.warmup + i]
+        tp, rp = timed(b, per, True)
+        t1, r1 = timed(b, one, False)
+        if not (np.array_equal(rp.counts, r1.counts) and np.array_equal(rp.hash_sum, r1.hash_sum)):
+            raise SystemExit("per-query and single-launch results differ")
+        lat1.append(t1)
+        latp.append(tp)
+        upd += r1.stats["n_canonical"]
+        mat += int(r1.counts.sum())
+        stats.append(r1.stats)
+        print("[bench] step %d: one launch %.1f ms, per-query launches %.1f ms, %d matches" % (
+            i, t1, tp, int(r1.counts.sum())), file=sys.stderr, flush=True)
+    ctx.close()
+    s1, sp = sum(lat1) / 1e3, sum(latp) / 1e3
+    avg_dfs_s = sum(s["ms_dfs"] for s in stats) / len(stats) / 1e3
+    avg_bytes = sum(s["bytes_alg_dfs"] for s in stats) / len(stats)
+    achieved = avg_bytes / avg_dfs_s / 1e9 if avg_dfs_s > 0 else 0.0
+    out = {
+        "metric": "incremental matches/s and updates/s on 1 MI355X; p50/p99 batch latency",
+        "value": mat / s1,
+        "unit": "matches/s",
+        "updates_per_s": upd / s1,
+        "p50_ms": percentile(lat1, 50),
+        "p99_ms": percentile(lat1, 99),
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": s1 * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded R-MAT graph, random-walk queries, generated update stream)",
+        "config": {
+            "workload": w.name,
+            "vertices": w.graph.n,
+            "edges": w.graph.m,
+            "queries": len(w.queries),
+            "query_k": [q.k for q in w.queries],
+            "batch_updates": len(w.batches[1]),
+            "mode": "counts + hash (every match enumerated)",
+            "tuning": one,
+        },
+        "per_query_launch": {
+            "updates_per_s": upd / sp,
+            "matches_per_s": mat / sp,
+            "p50_ms": percentile(latp, 50),
+            "p99_ms": percentile(latp, 99),
+            "speedup_of_one_launch": sp / s1,
+        },
+        "autotune": {k: tune[k] for k in ("best_ms", "base_ms", "max_points", "reps")},
+        "roofline": {
+            "bound": "hbm", "kernel": "k_dfs", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(w.name), "bytes_alg_per_launch": avg_bytes,
+            "avg_launch_ms": avg_dfs_s * 1e3,
+        },
+    }
     print(json.dumps(out))
 
 

@@ -67,7 +67,8 @@ typedef struct gamma_options {
   int32_t device;            /* HIP device ordinal */
   void* stream;              /* hipStream_t to run on; NULL = library-created stream */
   uint64_t tuple_capacity;   /* max tuple records stored per batch (0 = no tuple buffer) */
-  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 8) */
+  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 16, of which as many
+                                as the kernel's register use allows are resident) */
   uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
   uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
   uint32_t deadline_ms;      /* search deadline per batch (0 = none); past it the batch
@@ -82,8 +83,22 @@ enum {
   GAMMA_F_TUPLES = 1u << 2,         /* store match tuples (up to tuple_capacity records) */
   GAMMA_F_SEED_ATTR = 1u << 3,      /* store the seed ord of each tuple record */
   GAMMA_F_PER_UPDATE = 1u << 4,     /* count / hash per canonical batch edge (attribution) */
-  GAMMA_F_CANONICAL = 1u << 5       /* return the canonical batch on the host */
+  GAMMA_F_CANONICAL = 1u << 5,      /* return the canonical batch on the host */
+  GAMMA_F_DRY_RUN = 1u << 6         /* search the batch but do not commit it: results and
+                                       statistics as for a normal call, graph unchanged */
 };
+
+/* Search tunables.  They change how the work is spread over the chip, never
+ * the result.  In gamma_set_tuning a zero field keeps the current value. */
+typedef struct gamma_tuning {
+  uint32_t waves_per_cu;  /* persistent search waves per CU, 1..32 */
+  uint32_t steal;         /* 1 = chip-wide work hand-over (Sec. V-A), 2 = none */
+  uint32_t poll_cycles;   /* shader cycles between a busy wave's hand-over polls, 500..10^6 */
+  uint32_t split_inner;   /* smallest inner-level candidate range handed over, 2..2^20 */
+  uint32_t split_leaf;    /* smallest last-level candidate range handed over, 2..2^20 */
+  uint32_t query_launch;  /* 1 = every query's seeds in one search launch, 2 = one launch per query */
+  uint32_t reserved[2];
+} gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),
  * index 0 = deletion results (-). */
@@ -205,6 +220,26 @@ gamma_status gamma_register_query(gamma_ctx* ctx, uint32_t k, const uint32_t* ql
 gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);
+
+/* Current search tunables (every field filled).  Errors: EINVAL (NULL). */
+gamma_status gamma_get_tuning(const gamma_ctx* ctx, gamma_tuning* out);
+
+/* Set search tunables; zero fields keep their value.  Errors: EINVAL (a
+ * value outside the ranges in gamma_tuning; nothing changed). */
+gamma_status gamma_set_tuning(gamma_ctx* ctx, const gamma_tuning* in);
+
+/* Tune the search for the current graph and queries on a calibration batch.
+ * Every evaluation is a dry run (GAMMA_F_DRY_RUN with `flags`) of the batch,
+ * timed as the median device time of `reps` runs (1..9).  Coordinate
+ * search from the current tunables over query_launch, steal, waves_per_cu,
+ * poll_cycles, split_leaf and split_inner, at most max_points evaluations
+ * (1..64).  The fastest point is applied and written to *best; *best_ms and
+ * *base_ms (may be NULL) receive its time and the starting point's.  The
+ * graph is unchanged.  Errors: those of gamma_apply_batch (ETIMEDOUT from a
+ * deadline ends the search early and keeps the best point so far), EINVAL. */
+gamma_status gamma_autotune(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                            const uint8_t* op, gamma_mem where, uint32_t flags, uint32_t max_points,
+                            uint32_t reps, gamma_tuning* best, double* best_ms, double* base_ms);
 
 /* Copy up to max_records tuple records of the last batch into caller
  * buffers (any may be NULL) on the context stream; `where` is the memory

@@ -16,14 +16,17 @@ memory and streams only.
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
 
 from . import capi
-from .capi import (F_CANONICAL, F_COUNT, F_HASH, F_PER_UPDATE, F_SEED_ATTR, F_TUPLES, GAMMA_MEM_DEVICE,
-                   GAMMA_MEM_HOST)
+from .capi import (F_CANONICAL, F_COUNT, F_DRY_RUN, F_HASH, F_PER_UPDATE, F_SEED_ATTR, F_TUPLES,
+                   GAMMA_MEM_DEVICE, GAMMA_MEM_HOST)
 
 __all__ = ["Context", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch"]
 
@@ -115,6 +118,7 @@ class Context:
             raise GammaError(st, "gamma_create: %s" % self._lib.gamma_status_string(st).decode())
         self.tuple_capacity = int(tuple_capacity)
         self.query_k: List[int] = []
+        self._sig = hashlib.sha256()  # graph and query shapes, for the tuning cache key
 
     def close(self):
         if getattr(self, "_ptr", None):
@@ -145,6 +149,9 @@ class Context:
         nnz = int(k2.shape[0])
         _check(self._lib, self._ptr, self._lib.gamma_load_graph(self._ptr, n, nnz, rp, cl if nnz else None, lb, w1),
                "load_graph")
+        self._sig = hashlib.sha256(b"graph n=%d nnz=%d" % (n, nnz))
+        for q in getattr(self, "_queries", []):
+            self._sig.update(q)
 
     def register_query(self, k: int, labels, edges) -> int:
         ql = np.ascontiguousarray(np.asarray(labels), dtype=np.uint32)
@@ -156,10 +163,14 @@ class Context:
                                               ctypes.byref(qid)),
                "register_query")
         self.query_k.append(int(k))
+        qsig = b"query k=%d " % int(k) + ql.tobytes() + qe.tobytes()
+        self._queries = getattr(self, "_queries", []) + [qsig]
+        self._sig.update(qsig)
         return int(qid.value)
 
     def apply_batch(self, src, dst, op, hash: bool = True, tuples: bool = False, seed_attr: bool = False,
-                    per_update: bool = False, canonical: bool = False) -> BatchOutput:
+                    per_update: bool = False, canonical: bool = False, dry_run: bool = False) -> BatchOutput:
+        """Apply one batch (dry_run: search it without committing it)."""
         s, k1, w1 = _arg(src, np.uint32)
         d, k2, w2 = _arg(dst, np.uint32)
         o, k3, w3 = _arg(op, np.uint8)
@@ -172,6 +183,7 @@ class Context:
         flags |= F_SEED_ATTR if seed_attr else 0
         flags |= F_PER_UPDATE if per_update else 0
         flags |= F_CANONICAL if canonical else 0
+        flags |= F_DRY_RUN if dry_run else 0
         res = capi.BatchResult()
         st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
                                          o if n_upd else None, w1, flags, ctypes.byref(res))
@@ -226,6 +238,65 @@ class Context:
         stt = res.stats
         out.stats = {name: getattr(stt, name) for name, _ in capi.BatchStats._fields_ if not name.startswith("reserved")}
         return out
+
+    # ------------------------------------------------------------ tuning
+
+    def get_tuning(self) -> dict:
+        t = capi.Tuning()
+        _check(self._lib, self._ptr, self._lib.gamma_get_tuning(self._ptr, ctypes.byref(t)), "get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **kw) -> dict:
+        """Set search tunables (waves_per_cu, steal 1/2, poll_cycles, split_inner,
+        split_leaf, query_launch 1/2); unnamed ones keep their value."""
+        t = capi.Tuning()
+        for name, v in kw.items():
+            if name not in capi.Tuning.FIELDS:
+                raise ValueError("unknown tunable %r" % name)
+            setattr(t, name, int(v))
+        _check(self._lib, self._ptr, self._lib.gamma_set_tuning(self._ptr, ctypes.byref(t)), "set_tuning")
+        return self.get_tuning()
+
+    def tuning_key(self, n_updates: int) -> str:
+        """Cache key: graph size, registered queries and the batch size's power of two."""
+        return "%s:b%d" % (self._sig.hexdigest()[:24], max(int(n_updates), 1).bit_length())
+
+    def autotune(self, src, dst, op, hash: bool = True, max_points: int = 40, reps: int = 3,
+                 cache: Optional[str] = None) -> dict:
+        """Tune the search on a calibration batch (dry runs, graph unchanged)
+        and apply the best point.  With `cache` (a JSON file) a point stored
+        for the same graph, queries and batch-size class is reused."""
+        key = self.tuning_key(len(np.asarray(src)) if not _is_torch(src) else int(src.shape[0]))
+        db = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                db = json.load(f)
+            if key in db:
+                self.set_tuning(**db[key]["tuning"])
+                return dict(db[key], key=key, from_cache=True)
+        s, k1, w1 = _arg(src, np.uint32)
+        d, k2, w2 = _arg(dst, np.uint32)
+        o, k3, w3 = _arg(op, np.uint8)
+        if len({w1, w2, w3}) != 1:
+            raise ValueError("src, dst and op must all be host arrays or all device tensors")
+        n_upd = int(k1.shape[0])
+        best = capi.Tuning()
+        best_ms, base_ms = ctypes.c_double(), ctypes.c_double()
+        flags = F_COUNT | (F_HASH if hash else 0)
+        _check(self._lib, self._ptr,
+               self._lib.gamma_autotune(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                        o if n_upd else None, w1, flags, int(max_points), int(reps),
+                                        ctypes.byref(best), ctypes.byref(best_ms), ctypes.byref(base_ms)),
+               "autotune")
+        entry = {"tuning": best.as_dict(), "best_ms": best_ms.value, "base_ms": base_ms.value,
+                 "max_points": int(max_points), "reps": int(reps), "n_updates": n_upd}
+        if cache:
+            db[key] = entry
+            tmp = "%s.tmp%d" % (cache, os.getpid())
+            with open(tmp, "w") as f:
+                json.dump(db, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(entry, key=key, from_cache=False)
 
     def export_graph(self):
         n = ctypes.c_uint32()

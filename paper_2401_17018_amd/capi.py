@@ -18,11 +18,12 @@ GAMMA_ESTATE, GAMMA_ETIMEDOUT, GAMMA_EDEVICE = -5, -6, -7
 
 GAMMA_MEM_HOST, GAMMA_MEM_DEVICE = 0, 1
 
-F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL = 1, 2, 4, 8, 16, 32
+F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL, F_DRY_RUN = 1, 2, 4, 8, 16, 32, 64
 
 # every function declared in include/gamma.h
 EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
+    "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
     "gamma_validate_query", "gamma_validate_batch", "gamma_status_string", "gamma_last_error",
     "gamma_version",
@@ -40,6 +41,23 @@ class Options(ctypes.Structure):
         ("deadline_ms", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32 * 7),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("waves_per_cu", ctypes.c_uint32),
+        ("steal", ctypes.c_uint32),
+        ("poll_cycles", ctypes.c_uint32),
+        ("split_inner", ctypes.c_uint32),
+        ("split_leaf", ctypes.c_uint32),
+        ("query_launch", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 2),
+    ]
+
+    FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch")
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f in self.FIELDS}
 
 
 class QueryResult(ctypes.Structure):
@@ -133,6 +151,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_register_query.argtypes = [P, u32, P, u32, P, ctypes.POINTER(u32)]
     lib.gamma_apply_batch.restype = st
     lib.gamma_apply_batch.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, ctypes.POINTER(BatchResult)]
+    lib.gamma_get_tuning.restype = st
+    lib.gamma_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gamma_set_tuning.restype = st
+    lib.gamma_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gamma_autotune.restype = st
+    lib.gamma_autotune.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, u32, u32, ctypes.POINTER(Tuning),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     lib.gamma_copy_tuples.restype = st
     lib.gamma_copy_tuples.argtypes = [P, P, P, P, u64, ctypes.c_int]
     lib.gamma_result_release.restype = st

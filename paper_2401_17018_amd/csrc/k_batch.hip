@@ -264,8 +264,8 @@ __global__ void k_rows_commit(const uint32_t* __restrict__ touched, const uint64
 __global__ void k_rows_finish(const uint32_t* __restrict__ touched, const uint64_t* __restrict__ r2_off,
                               const uint32_t* __restrict__ r2_len, const uint64_t* __restrict__ r0_off,
                               const uint32_t* __restrict__ r0_len, uint32_t n_touched, GmGraphDev G,
-                              const GmCounters* __restrict__ ctr) {
-  const bool back = ctr->aborted != 0;
+                              const GmCounters* __restrict__ ctr, uint32_t restore) {
+  const bool back = restore || ctr->aborted != 0;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_touched; t += gridDim.x * blockDim.x) {
     const uint32_t v = touched[t];
     G.row_off[v] = back ? r0_off[t] : r2_off[t];
@@ -353,10 +353,10 @@ void launch_rows_set(const uint32_t* touched, const uint32_t* run_start, const u
 
 void launch_rows_finish(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
                         const uint64_t* r0_off, const uint32_t* r0_len, uint32_t n_touched, GmGraphDev G,
-                        const GmCounters* ctr, hipStream_t s) {
+                        const GmCounters* ctr, uint32_t restore, hipStream_t s) {
   if (!n_touched) return;
   k_rows_finish<<<grid_for(n_touched, 256), 256, 0, s>>>(touched, r2_off, r2_len, r0_off, r0_len, n_touched,
-                                                         G, ctr);
+                                                         G, ctr, restore);
 }
 
 void launch_rows_save(const uint32_t* touched, uint32_t n_touched, GmGraphDev G, uint64_t* r0_off,

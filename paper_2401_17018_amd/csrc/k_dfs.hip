@@ -44,9 +44,16 @@ constexpr int DFS_WAVES = DFS_THREADS / GM_WAVE;
 constexpr int MAX_OTH = 120;  // >= |E(Q)| - 1 for any simple query with k <= 16
 constexpr int TASK_WORDS = 32;
 constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
-constexpr uint64_t POLL_CYCLES = 6000;               // shader-clock cycles between polls (~2.5 us)
-constexpr uint32_t LEAF_MIN_SPLIT = 8 * GM_WAVE;     // smallest last-level range worth handing over
-constexpr uint32_t INNER_MIN_SPLIT = 2 * GM_WAVE;
+#ifndef GM_DFS_PROFILE
+#define GM_DFS_PROFILE 0
+#endif
+// GM_DFS_COUNT=1 (instrumented builds only; exclusive with GM_DFS_PROFILE)
+// reuses the five cycle tallies as last-level counters: steps, binary-search
+// load instructions, lanes entering a list probe, lanes at step start, and
+// the summed lengths of the probed lists.
+#ifndef GM_DFS_COUNT
+#define GM_DFS_COUNT 0
+#endif
 #ifndef GM_LEAF_UNROLL
 #define GM_LEAF_UNROLL 4
 #endif
@@ -63,14 +70,36 @@ struct WaveState {
   uint32_t drvw[GM_MAX_K]; // query vertex whose list drives level l
   uint32_t oth_n[GM_MAX_K];
   uint64_t hpre;           // checksum salt + element terms of every position but the last vertex
+  uint64_t tally[8];       // idle, init, inner, leaf, hand-over cycles; tasks received; hand-overs; nodes
   uint64_t oth_base[MAX_OTH];
   uint32_t oth_len[MAX_OTH];
   uint32_t oth_w[MAX_OTH];
+  // Last-level set-up, prepared at the level before it (k >= 4).  The lists
+  // of the last vertex's matched neighbours other than order[k-2] do not
+  // change while level k-2 is searched ("static"); the survivors of the
+  // current level-(k-2) chunk carry their own row's subrange ("pf_*").
+  uint64_t st_base[GM_MAX_K];
+  uint32_t st_len[GM_MAX_K];
+  uint32_t st_w[GM_MAX_K];
+  uint32_t st_n;
+  uint64_t st_h;           // checksum salt + element terms of order[0 .. k-3]
+  uint32_t pf_c[GM_WAVE];  // survivor's internal id
+  uint32_t pf_x[GM_WAVE];  // its external id
+  uint32_t pf_len[GM_WAVE];
+  uint64_t pf_base[GM_WAVE];
+  uint64_t pf_h[GM_WAVE];  // its element term
 };
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline uint64_t uni64(uint64_t x) {
   return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+// value of lane i (i uniform)
+__device__ inline uint32_t lane_val(uint32_t x, uint32_t i) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)i);
+}
+__device__ inline uint64_t lane_val64(uint64_t x, uint32_t i) {
+  return ((uint64_t)lane_val((uint32_t)(x >> 32), i) << 32) | lane_val((uint32_t)x, i);
 }
 
 __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
@@ -261,13 +290,38 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
   const uint32_t bpx = (gridDim.x + 7) / 8;
   const uint32_t slot = ((blockIdx.x & 7) * bpx + (blockIdx.x >> 3)) * DFS_WAVES + wid;
   Acc A{0, 0, 0, 0xFFFFFFFFu};
-  uint64_t st_nodes = 0, st_scan = 0, st_bytes = 0, st_steals = 0;
-  uint64_t cy_idle = 0, cy_init = 0, cy_inner = 0, cy_leaf = 0, cy_hand = 0, n_recv = 0;
+  uint64_t st_scan = 0, st_bytes = 0;
+  // per-wave tallies live in LDS (keeps scalar registers free).  The cycle
+  // split (slots 0-4) is only collected in builds with GM_DFS_PROFILE=1.
+  if (lane < 8) S.tally[lane] = 0;
+#define TALLY_ALWAYS(i, v)            \
+  do {                                \
+    if (lane == 0) S.tally[i] += (v); \
+  } while (0)
+#if GM_DFS_COUNT
+#define CNT(i, v) TALLY_ALWAYS(i, v)
+#else
+#define CNT(i, v) \
+  do {            \
+  } while (0)
+#endif
+#if GM_DFS_PROFILE
+#define TALLY(i, v) TALLY_ALWAYS(i, v)
+#define CYCLES() __builtin_readcyclecounter()
+#else
+#define TALLY(i, v) \
+  do {              \
+  } while (0)
+#define CYCLES() 0ull
+#endif
+  // this launch searches seeds [seed_begin, n_seeds); the seed window kernel
+  // set seed_head = seed_begin and the deadline origin before it
   const unsigned long long n_seeds = P.ctr->n_seeds;
-  if (n_seeds == 0) return;  // nothing to search (and nobody would send the stop message)
+  if (n_seeds == P.ctr->seed_begin || P.ctr->aborted) return;  // nothing to do (nobody would send the stop message)
   bool seeds_left = true;
   uint64_t last_poll = __builtin_readcyclecounter();
-  const uint64_t t_start = wall_clock64();
+  const uint64_t t_start = P.ctr->t_start;
+  const uint64_t poll_cycles = P.poll_cycles;
   bool abort_now = false;
 
   for (;;) {
@@ -307,7 +361,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if (lane == 0) atomicOr(&P.idle_bits[slot >> 6], 1ull << (slot & 63));
       uint32_t msg = 0;
       int nap = 1;
-      const uint64_t t_idle0 = __builtin_readcyclecounter();
+      const uint64_t t_idle0 = CYCLES();
       for (;;) {
         uint32_t ab = 0;
         if (lane == 0) {
@@ -323,9 +377,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         for (int i = 0; i < nap; ++i) __builtin_amdgcn_s_sleep(32);
         nap = nap < 16 ? nap * 2 : 16;
       }
-      cy_idle += __builtin_readcyclecounter() - t_idle0;
+      TALLY(0, CYCLES() - t_idle0);
       if (abort_now || msg == MSG_STOP) break;
-      ++n_recv;
+      TALLY_ALWAYS(5, 1);
       // MSG_TASK: the donor cleared our bit and lowered the idle count;
       // its release store on the flag orders the task record before it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -368,49 +422,88 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       continue;
     }
 
-    // ---- level initialisation: candidate subrange of order[l]
-    auto init_level_impl = [&](uint32_t l, bool count) -> bool {
-      const uint32_t lab = uni(pl->lab[l]);
-      if (lab >= P.G.label_slots) return false;
-      const uint32_t lo_id = uni(P.G.label_start[lab]);
-      const uint32_t hi_id = uni(P.G.label_start[lab + 1]);
-      st_bytes += 8;
-      if (lo_id >= hi_id) return false;
-      const uint32_t ob = uni(pl->bofs[l]);
-      const uint32_t ls = uni(pl->lslot[l]);
-      uint32_t cnt = 0, best = 0xFFFFFFFFu, besti = 0;
-      for (uint32_t bm = uni(pl->back[l]); bm; bm &= bm - 1) {
-        const uint32_t w = (uint32_t)__ffs(bm) - 1;
-        const uint32_t v = uni(S.f[w]);
-        // label subrange of v's row from the label index (row offset and
-        // index entry are independent loads)
-        const uint64_t off = uni64(P.G.row_off[v]);
-        const uint64_t li = uni64(P.lix[(uint64_t)v * P.lix_slots + ls]);
-        st_bytes += 16;
-        const uint32_t s0 = (uint32_t)li;
-        const uint32_t sub = (uint32_t)(li >> 32);
-        if (sub == 0) return false;
-        S.oth_base[ob + cnt] = off + s0;
-        S.oth_len[ob + cnt] = sub;
-        S.oth_w[ob + cnt] = w;
-        if (sub < best) {
-          best = sub;
-          besti = cnt;
+    // ---- level set-up.  The candidates of order[l] lie in the label
+    // subrange (label index) of every matched neighbour's row: the shortest
+    // list drives the level, the others are probed.  Lane i < nb holds list
+    // i as (w = query vertex, base = arena index of the subrange, sub = its
+    // length).
+    const uint32_t pf_lvl = k >= 4 ? k - 2 : 0xFFFFFFFFu;
+    auto finish_level = [&](uint32_t l, uint32_t nb, bool act, uint32_t w, uint64_t base, uint32_t sub) {
+      uint32_t best = 0xFFFFFFFFu, besti = 0;
+      for (uint32_t i = 0; i < nb; ++i) {
+        const uint32_t si = lane_val(sub, i);
+        if (si < best) {
+          best = si;
+          besti = i;
         }
-        ++cnt;
       }
-      S.drv[l] = S.oth_base[ob + besti];
+      const uint32_t ob = uni(pl->bofs[l]);
+      // every list but the driver is probed; the last list takes the driver's place
+      if (act && (uint32_t)lane != besti) {
+        const uint32_t at = ob + ((uint32_t)lane == nb - 1 ? besti : (uint32_t)lane);
+        S.oth_base[at] = base;
+        S.oth_len[at] = sub;
+        S.oth_w[at] = w;
+      }
+      S.drv[l] = lane_val64(base, besti);
       S.len[l] = best;
-      S.drvw[l] = S.oth_w[ob + besti];
-      if (besti != cnt - 1) {
-        S.oth_base[ob + besti] = S.oth_base[ob + cnt - 1];
-        S.oth_len[ob + besti] = S.oth_len[ob + cnt - 1];
-        S.oth_w[ob + besti] = S.oth_w[ob + cnt - 1];
-      }
-      S.oth_n[l] = cnt - 1;
+      S.drvw[l] = lane_val(w, besti);
+      S.oth_n[l] = nb - 1;
       S.cur[l] = 0;
       S.mask[l] = 0;
-      if (count && lane == 0) ++st_nodes;
+    };
+
+    // Lanes 0-31 fetch the lists of order[l] (one memory round trip for
+    // all of them); at level k-2 lanes 32-63 fetch, in the same round
+    // trip, the static lists of the last level.
+    auto init_level_impl = [&](uint32_t l, bool count) -> bool {
+      const uint32_t bm = uni(pl->back[l]);
+      const uint32_t nb = (uint32_t)__popc(bm);
+      const bool pre = l == pf_lvl;
+      uint32_t bm1 = 0, nb1 = 0, ls1 = 0;
+      if (pre) {
+        bm1 = uni(pl->back[k - 1]) & ~(1u << uni(pl->order[l]));
+        nb1 = (uint32_t)__popc(bm1);
+        ls1 = uni(pl->lslot[k - 1]);
+      }
+      const bool hi = lane >= 32;
+      const uint32_t my_i = (uint32_t)lane & 31u;
+      const uint32_t my_n = hi ? nb1 : nb;
+      uint32_t t = hi ? bm1 : bm;
+      const uint32_t nmax = nb > nb1 ? nb : nb1;
+      for (uint32_t i = 0; i < nmax; ++i)
+        if (i < my_i) t &= t - 1;  // drop the lower set bits: t's lowest bit is list my_i
+      const bool act = my_i < my_n;
+      uint32_t w = 0, sub = 0;
+      uint64_t base = 0;
+      if (act) {
+        w = (uint32_t)__ffs(t) - 1;
+        const uint32_t v = S.f[w];
+        const uint64_t off = P.G.row_off[v];
+        const uint64_t li = P.lix[(uint64_t)v * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
+        base = off + (uint32_t)li;
+        sub = (uint32_t)(li >> 32);
+      }
+      st_bytes += 16ull * (nb + nb1);
+      // an empty list leaves no candidate (for a static list of the last
+      // level: no candidate for any extension of this prefix)
+      if (__ballot(act && sub == 0)) return false;
+      if (pre) {
+        if (hi && act) {
+          S.st_base[my_i] = base;
+          S.st_len[my_i] = sub;
+          S.st_w[my_i] = w;
+        }
+        S.st_n = nb1;
+        uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
+        for (uint32_t j = 0; j < l; ++j) {
+          const uint32_t uj = uni(pl->order[j]);
+          h += elem_hash(uni(S.fx[uj]), uj);
+        }
+        S.st_h = h;
+      }
+      finish_level(l, nb, act && !hi, w, base, sub);
+      if (count) TALLY_ALWAYS(7, 1);
       if (l == k - 1) {
         const uint32_t u = uni(pl->order[l]);
         uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
@@ -421,10 +514,66 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       return true;
     };
 
+    // Descend from survivor `bit` of level k-2 into the last level using
+    // what that level prepared: no global memory access.
+    auto init_leaf_fast = [&](uint32_t bit) -> bool {
+      const uint32_t l = k - 1;
+      const uint32_t u = uni(pl->order[k - 2]);
+      S.f[u] = uni(S.pf_c[bit]);
+      S.fx[u] = uni(S.pf_x[bit]);
+      const uint32_t nb1 = uni(S.st_n);
+      const bool dyn = (uni(pl->back[l]) >> u) & 1u;
+      const uint32_t dlen = uni(S.pf_len[bit]);
+      if (dyn && dlen == 0) return false;
+      const uint32_t nb = nb1 + (dyn ? 1u : 0u);
+      uint32_t w = 0, sub = 0;
+      uint64_t base = 0;
+      if ((uint32_t)lane < nb1) {
+        w = S.st_w[lane];
+        base = S.st_base[lane];
+        sub = S.st_len[lane];
+      } else if ((uint32_t)lane == nb1) {
+        w = u;
+        base = uni64(S.pf_base[bit]);
+        sub = dlen;
+      }
+      finish_level(l, nb, (uint32_t)lane < nb, w, base, sub);
+      S.hpre = uni64(S.st_h) + uni64(S.pf_h[bit]);
+      TALLY_ALWAYS(7, 1);
+      return true;
+    };
+
+    // After a level-(k-2) chunk: every survivor lane records its external id,
+    // its element term and (when order[k-2] is a matched neighbour of the
+    // last vertex) its own row's subrange for the last vertex's label.
+    auto prefetch_leaf = [&](uint32_t l, uint32_t idx, uint32_t c, bool ok) {
+      const uint32_t u = uni(pl->order[l]);
+      const bool dyn = (uni(pl->back[k - 1]) >> u) & 1u;
+      const uint32_t ls1 = uni(pl->lslot[k - 1]);
+      if (ok) {
+        const uint32_t x = ext[uni64(S.drv[l]) + idx];
+        uint64_t base = 0;
+        uint32_t sub = 0;
+        if (dyn) {
+          const uint64_t off = P.G.row_off[c];
+          const uint64_t li = P.lix[(uint64_t)c * P.lix_slots + ls1];
+          base = off + (uint32_t)li;
+          sub = (uint32_t)(li >> 32);
+          st_bytes += 16;
+        }
+        st_bytes += 4;
+        S.pf_c[lane] = c;
+        S.pf_x[lane] = x;
+        S.pf_base[lane] = base;
+        S.pf_len[lane] = sub;
+        S.pf_h[lane] = elem_hash(x, u);
+      }
+    };
+
     auto init_level = [&](uint32_t l, bool count) -> bool {
-      const uint64_t t0 = __builtin_readcyclecounter();
+      const uint64_t t0 = CYCLES();
       const bool r = init_level_impl(l, count);
-      cy_init += __builtin_readcyclecounter() - t0;
+      TALLY(1, CYCLES() - t0);
       return r;
     };
 
@@ -479,7 +628,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       uint64_t give = 0;
       for (uint32_t x = base_l; x <= lcur; ++x) {
         const uint32_t cur = uni(S.cur[x]), len = uni(S.len[x]);
-        const uint32_t min_split = (x == k - 1) ? LEAF_MIN_SPLIT : INNER_MIN_SPLIT;
+        const uint32_t min_split = (x == k - 1) ? P.split_leaf : P.split_inner;
         if (len > cur && len - cur >= min_split) {
           lv = x;
           kind = 1;
@@ -547,7 +696,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if (lane < TASK_WORDS) P.mbox[(uint64_t)target * TASK_WORDS + lane] = w;
       if (lane == 0) {
         __hip_atomic_store(&P.mflag[target], MSG_TASK, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        ++st_steals;
+        S.tally[6] += 1;
       }
     };
 
@@ -559,20 +708,40 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint32_t u = uni(pl->order[l]);
       const uint32_t len = uni(S.len[l]);
       const uint64_t drv = uni64(S.drv[l]);
+      const uint32_t on = uni(S.oth_n[l]);
+      const uint32_t ob = uni(pl->bofs[l]);
       const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
       uint32_t e[LEAF_UNROLL], x[LEAF_UNROLL];
       bool ok[LEAF_UNROLL];
+      // branch-free: lanes past the end read the last entry (len >= 1) and
+      // are masked off afterwards
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j) {
         const uint32_t idx = cur + (uint32_t)(j * GM_WAVE + lane);
         ok[j] = idx < len;
-        e[j] = ok[j] ? col[drv + idx] : 0u;
-        x[j] = (ok[j] && need_x) ? ext[drv + idx] : 0u;
+        e[j] = col[drv + (ok[j] ? idx : len - 1)];
+      }
+      if (need_x) {
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint32_t idx = cur + (uint32_t)(j * GM_WAVE + lane);
+          x[j] = ext[drv + (ok[j] ? idx : len - 1)];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) x[j] = 0;
+      }
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j)
         if (ok[j]) {
           st_bytes += need_x ? 8 : 4;
           ++st_scan;
         }
-      }
+      CNT(0, 1);
+#if GM_DFS_COUNT
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) CNT(3, __popcll(__ballot(ok[j])));
+#endif
       for (uint32_t jj = 0; jj < l; ++jj) {
         const uint32_t fv = uni(S.f[pl->order[jj]]);
 #pragma unroll
@@ -582,8 +751,6 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j)
         if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, fdrv, e[j] & GM_IDMASK, ord, sign, st_bytes);
-      const uint32_t on = uni(S.oth_n[l]);
-      const uint32_t ob = uni(pl->bofs[l]);
       for (uint32_t i = 0; i < on; ++i) {
         bool anyok = false;
 #pragma unroll
@@ -591,48 +758,56 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (!__ballot(anyok)) break;
         const uint64_t base = S.oth_base[ob + i];
         const uint32_t olen = uni(S.oth_len[ob + i]);
-        uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
+#if GM_DFS_COUNT
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
-          lo[j] = 0;
-          cnt[j] = ok[j] ? olen : 0u;
-        }
-        for (;;) {
-          uint32_t v[LEAF_UNROLL];
-          bool any = false;
+        for (int j = 0; j < LEAF_UNROLL; ++j) CNT(2, __popcll(__ballot(ok[j])));
+#endif
+        CNT(4, olen);
+        {
+          uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
 #pragma unroll
           for (int j = 0; j < LEAF_UNROLL; ++j) {
-            v[j] = cnt[j] ? (col[base + lo[j] + (cnt[j] >> 1)] & GM_IDMASK) : 0u;
-            if (cnt[j]) st_bytes += 4;
+            lo[j] = 0;
+            cnt[j] = ok[j] ? olen : 0u;
           }
+          for (;;) {
+            uint32_t v[LEAF_UNROLL];
+            bool any = false;
 #pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
-            if (cnt[j]) {
-              any = true;
-              const uint32_t half = cnt[j] >> 1;
-              if (v[j] < (e[j] & GM_IDMASK)) {
-                lo[j] += half + 1;
-                cnt[j] -= half + 1;
-              } else {
-                cnt[j] = half;
+            for (int j = 0; j < LEAF_UNROLL; ++j) {
+              // clamped so a finished search still reads inside the list (olen >= 1)
+              const uint32_t at = lo[j] + (cnt[j] >> 1);
+              v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
+              if (cnt[j]) st_bytes += 4;
+            }
+            CNT(1, LEAF_UNROLL);
+#pragma unroll
+            for (int j = 0; j < LEAF_UNROLL; ++j) {
+              if (cnt[j]) {
+                any = true;
+                const uint32_t half = cnt[j] >> 1;
+                if (v[j] < (e[j] & GM_IDMASK)) {
+                  lo[j] += half + 1;
+                  cnt[j] -= half + 1;
+                } else {
+                  cnt[j] = half;
+                }
               }
             }
+            if (!__ballot(any)) break;
           }
-          if (!__ballot(any)) break;
-        }
-        const uint32_t wv = uni(S.f[S.oth_w[ob + i]]);
-        uint32_t e2[LEAF_UNROLL];
+          const uint32_t wv = uni(S.f[S.oth_w[ob + i]]);
+          uint32_t e2[LEAF_UNROLL];
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
-          const bool in = ok[j] && lo[j] < olen;
-          e2[j] = in ? col[base + lo[j]] : 0u;
-          if (ok[j]) {
-            if (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK)) ok[j] = false;
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            const bool in = lo[j] < olen;
+            e2[j] = col[base + (in ? lo[j] : olen - 1)];
+            if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
           }
-        }
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j)
-          if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+          for (int j = 0; j < LEAF_UNROLL; ++j)
+            if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+        }
       }
       const uint64_t hpre = uni64(S.hpre);
 #pragma unroll
@@ -643,12 +818,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     };
 
     auto try_donate = [&](uint32_t lcur) {
-      const uint64_t t0 = __builtin_readcyclecounter();
+      const uint64_t t0 = CYCLES();
       try_donate_impl(lcur);
-      cy_hand += __builtin_readcyclecounter() - t0;
+      TALLY(4, CYCLES() - t0);
     };
 
     uint32_t l = base_l;
+    bool pf_ok = false;  // level k-2's prefetch records belong to its current chunk
     if (!init_level(l, !handed)) {
       // an empty first level (a seed with no extension)
     } else {
@@ -664,7 +840,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         uint64_t m = uni64(S.mask[l]);
         if (m == 0) {
           const uint64_t now = __builtin_readcyclecounter();
-          if (now - last_poll >= POLL_CYCLES) {
+          if (now - last_poll >= poll_cycles) {
             last_poll = now;
             // cooperative deadline: the first wave past it raises the abort
             // word; every wave checks the word here and leaves
@@ -692,11 +868,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
             --l;
             continue;
           }
-          const uint64_t t_ev = __builtin_readcyclecounter();
+          const uint64_t t_ev = CYCLES();
           if (l == k - 1) {
             S.cur[l] = cur + LEAF_UNROLL * GM_WAVE;
             leaf_step(cur);
-            cy_leaf += __builtin_readcyclecounter() - t_ev;
+            TALLY(3, CYCLES() - t_ev);
             continue;
           }
           S.cur[l] = cur + GM_WAVE;
@@ -704,12 +880,23 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           uint32_t c, eidx;
           bool ok;
           m = eval_chunk(l, cur, c, eidx, ok);
-          cy_inner += __builtin_readcyclecounter() - t_ev;
+          if (l == pf_lvl) {
+            if (m) prefetch_leaf(l, eidx, c, ok);
+            pf_ok = true;
+          }
+          TALLY(2, CYCLES() - t_ev);
           S.mask[l] = m;
           if (m == 0) continue;
         }
         const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;
         S.mask[l] = m & (m - 1);
+        if (l == pf_lvl && pf_ok) {
+          const uint64_t t0 = CYCLES();
+          const bool r = init_leaf_fast(bit);
+          TALLY(1, CYCLES() - t0);
+          if (r) ++l;
+          continue;
+        }
         const uint64_t at = uni64(S.drv[l]) + uni(S.chunk[l]) + bit;
         const uint32_t c = uni(col[at] & GM_IDMASK);
         const uint32_t u = uni(pl->order[l]);
@@ -728,19 +915,16 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     }
   }
   flush_acc(P, A, lane);
-  const uint64_t sn = wave_sum64(st_nodes), ss = wave_sum64(st_scan), sb = wave_sum64(st_bytes);
-  const uint64_t sw = wave_sum64(st_steals);
+#undef TALLY
+#undef TALLY_ALWAYS
+#undef CYCLES
+  const uint64_t ss = wave_sum64(st_scan), sb = wave_sum64(st_bytes);
+  if (lane < 6) atomicAdd(&P.ctr->cyc[lane], (unsigned long long)S.tally[lane]);
   if (lane == 0) {
-    atomicAdd(&P.ctr->cyc[0], (unsigned long long)cy_idle);
-    atomicAdd(&P.ctr->cyc[1], (unsigned long long)cy_init);
-    atomicAdd(&P.ctr->cyc[2], (unsigned long long)cy_inner);
-    atomicAdd(&P.ctr->cyc[3], (unsigned long long)cy_leaf);
-    atomicAdd(&P.ctr->cyc[4], (unsigned long long)cy_hand);
-    atomicAdd(&P.ctr->cyc[5], (unsigned long long)n_recv);
-    atomicAdd(&P.ctr->dfs_nodes, (unsigned long long)sn);
+    atomicAdd(&P.ctr->steals, (unsigned long long)S.tally[6]);
+    atomicAdd(&P.ctr->dfs_nodes, (unsigned long long)S.tally[7]);
     atomicAdd(&P.ctr->cand_scanned, (unsigned long long)ss);
     atomicAdd(&P.ctr->bytes_alg, (unsigned long long)sb);
-    atomicAdd(&P.ctr->steals, (unsigned long long)sw);
   }
 }
 

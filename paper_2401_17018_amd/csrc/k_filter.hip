@@ -76,11 +76,12 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
                         const uint8_t* __restrict__ canon_sign, uint32_t n_canon,
                         const GmQueryDev* __restrict__ qs, uint32_t nq, const GmPlan* __restrict__ plans,
                         const uint16_t* __restrict__ cand, uint32_t n, GmSeed* __restrict__ seeds,
-                        uint64_t cap, GmCounters* ctr) {
-  const uint64_t total = (uint64_t)n_canon * nq;
+                        uint64_t cap, GmCounters* ctr, uint32_t only_q) {
+  const uint32_t nqs = only_q < nq ? 1u : nq;
+  const uint64_t total = (uint64_t)n_canon * nqs;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
        w += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t o = (uint32_t)(w / nq), q = (uint32_t)(w % nq);
+    const uint32_t o = (uint32_t)(w / nqs), q = only_q < nq ? only_q : (uint32_t)(w % nqs);
     const uint32_t a = canon_a[o], b = canon_b[o];
     const uint32_t ca = cand[(uint64_t)q * n + a], cb = cand[(uint64_t)q * n + b];
     if (!ca || !cb) continue;
@@ -125,8 +126,15 @@ __global__ void k_label_index(GmGraphDev G, const uint32_t* __restrict__ verts, 
   }
 }
 
-// The search starts with one unfinished work item per seed.
-__global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds; }
+// The search starts with one unfinished work item per seed of its window.
+__global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds - ctr->seed_begin; }
+
+// Seeds appended after this point form the next launch's window.
+__global__ void k_seed_window(GmCounters* ctr) {
+  ctr->seed_begin = ctr->n_seeds;
+  ctr->seed_head = ctr->n_seeds;
+  if (ctr->t_start == 0) ctr->t_start = wall_clock64();
+}
 
 unsigned grid_for(uint64_t work, unsigned per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
@@ -147,6 +155,7 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint3
 }
 
 void launch_pending_init(GmCounters* ctr, hipStream_t s) { k_pending_init<<<1, 1, 0, s>>>(ctr); }
+void launch_seed_window(GmCounters* ctr, hipStream_t s) { k_seed_window<<<1, 1, 0, s>>>(ctr); }
 
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
                         uint32_t n_slots, unsigned long long* lix, hipStream_t s) {
@@ -157,10 +166,11 @@ void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
-                  hipStream_t s) {
+                  uint32_t only_q, hipStream_t s) {
   if (!n_canon || !nq) return;
-  k_seeds<<<grid_for((uint64_t)n_canon * nq, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, n_canon,
-                                                                qs, nq, plans, cand, n, seeds, cap, ctr);
+  const uint64_t work = (uint64_t)n_canon * (only_q < nq ? 1u : nq);
+  k_seeds<<<grid_for(work, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, n_canon, qs, nq, plans, cand, n,
+                                              seeds, cap, ctr, only_q);
 }
 
 }  // namespace gm

@@ -44,6 +44,8 @@ struct GmCounters {
   unsigned long long pending;     // work items taken or handed over and not finished
   unsigned int aborted;           // set when a wave passed the deadline; every wave then exits
   unsigned int pad1;
+  unsigned long long seed_begin;  // first seed of the current search launch (seeds [seed_begin, n_seeds))
+  unsigned long long t_start;     // device wall clock when the batch's search began (deadline origin)
 };
 
 struct GmDfsParams {
@@ -72,6 +74,10 @@ struct GmDfsParams {
   uint32_t n_slots;
   uint32_t donate;                // 0 = no hand-over (each wave keeps its seed)
   uint64_t deadline_ticks;        // wall-clock ticks a wave may search (0 = no deadline)
+  uint32_t poll_cycles;           // shader cycles between a busy wave's hand-over polls
+  uint32_t split_inner;           // smallest inner-level range worth handing over
+  uint32_t split_leaf;            // smallest last-level range worth handing over
+  uint32_t pad2;
 };
 
 namespace gm {
@@ -126,7 +132,7 @@ void launch_rows_commit(const uint32_t* touched, const uint64_t* r2_off, const u
                         uint32_t n_touched, GmGraphDev G, hipStream_t s);
 void launch_rows_finish(const uint32_t* touched, const uint64_t* r2_off, const uint32_t* r2_len,
                         const uint64_t* r0_off, const uint32_t* r0_len, uint32_t n_touched, GmGraphDev G,
-                        const GmCounters* ctr, hipStream_t s);
+                        const GmCounters* ctr, uint32_t restore, hipStream_t s);  // restore: roll back
 void launch_rows_save(const uint32_t* touched, uint32_t n_touched, GmGraphDev G, uint64_t* r0_off,
                       uint32_t* r0_len, hipStream_t s);
 
@@ -135,13 +141,16 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint3
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s);
 void launch_pending_init(GmCounters* ctr, hipStream_t s);
+// opens the seed window of the next search launch: seed_begin = seed_head =
+// n_seeds; sets the deadline origin on the first call of a batch
+void launch_seed_window(GmCounters* ctr, hipStream_t s);
 // label index: for rows `verts` (or all rows), the subrange of each indexed label
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
                         uint32_t n_slots, unsigned long long* lix, hipStream_t s);
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
-                  hipStream_t s);
+                  uint32_t only_q, hipStream_t s);  // only_q = 0xFFFFFFFF: every query
 
 // search (k_dfs.hip)
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);

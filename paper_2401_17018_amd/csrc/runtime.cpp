@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gamma.h"
@@ -86,6 +87,7 @@ struct gamma_ctx {
   DevBuf mbox, mflag, idle_bits, idle_rep;
   DevBuf lix, lix_lab, r0_off, r0_len;
   uint32_t wall_khz = 100000;
+  gamma_tuning tun{};                // search tunables (never change results)
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
 
   // host side results
@@ -382,6 +384,12 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
       delete c;
       return GAMMA_EDEVICE;
     }
+  c->tun.waves_per_cu = c->opt.waves_per_cu ? std::min<uint32_t>(c->opt.waves_per_cu, 32) : 16;
+  c->tun.steal = (c->opt.steal_set && !c->opt.steal) ? 2 : 1;
+  c->tun.poll_cycles = 6000;  // ~2.5 us at 2.4 GHz
+  c->tun.split_inner = 128;
+  c->tun.split_leaf = 512;
+  c->tun.query_launch = 1;
   *out = c;
   return GAMMA_OK;
 }
@@ -705,11 +713,15 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     chk(hipEventRecord(C.ev[3], s), "event");
 
     // ---------------------------------------------------------- seeds
+    // (one launch per query: each query's seeds are generated right before
+    // its own search launch, so that time falls in the search phase)
     const uint64_t seed_cap = std::max<uint64_t>((uint64_t)n_canon * C.total_plans, 1);
     GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
-    if (nq)
+    const bool per_query = C.tun.query_launch == 2 && nq > 1;
+    gm::launch_seed_window(ctr, s);
+    if (nq && !per_query)
       gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
-                       (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, s);
+                       (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu, s);
     chk(hipEventRecord(C.ev[4], s), "event");
 
     // ---------------------------------------------------------- search
@@ -748,7 +760,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.tord = (uint32_t*)C.tord.p;
       P.tcap = tcap;
       P.upd_res = upd;
-      uint32_t wpc = C.opt.waves_per_cu ? C.opt.waves_per_cu : 16;
+      const uint32_t wpc = C.tun.waves_per_cu;
       unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / gm::dfs_waves_per_block());
       const uint32_t slots = gm::dfs_slots(blocks);
       P.mbox = C.ensure<uint32_t>(C.mbox, (size_t)slots * 32);
@@ -756,18 +768,31 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.idle_bits = (unsigned long long*)C.ensure<uint64_t>(C.idle_bits, (slots + 63) / 64);
       P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 64);
       P.n_slots = slots;
-      P.donate = (C.opt.steal_set && !C.opt.steal) ? 0u : 1u;
+      P.donate = C.tun.steal == 1 ? 1u : 0u;
       P.deadline_ticks = (uint64_t)C.opt.deadline_ms * C.wall_khz;
-      gm::fill_u32(P.mflag, 0, slots, s);
-      gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
-      gm::fill_u32(P.idle_rep, 0, 64, s);
-      gm::launch_pending_init(ctr, s);
-      gm::launch_dfs(P, blocks, s);
+      P.poll_cycles = C.tun.poll_cycles;
+      P.split_inner = C.tun.split_inner;
+      P.split_leaf = C.tun.split_leaf;
+      P.pad2 = 0;
+      for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
+        if (per_query) {
+          if (qi) gm::launch_seed_window(ctr, s);
+          gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
+                           (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi, s);
+        }
+        gm::fill_u32(P.mflag, 0, slots, s);
+        gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
+        gm::fill_u32(P.idle_rep, 0, 64, s);
+        gm::launch_pending_init(ctr, s);
+        gm::launch_dfs(P, blocks, s);
+      }
     }
     chk(hipEventRecord(C.ev[5], s), "event");
 
     // ---------------------------------------------------------- commit G', refresh filter on G'
-    gm::launch_rows_finish(tch, r2o, r2l, r0o, r0l, n_touched, G, ctr, s);
+    // a dry run (or a search past its deadline) puts the saved rows back
+    const bool dry = (flags & GAMMA_F_DRY_RUN) != 0;
+    gm::launch_rows_finish(tch, r2o, r2l, r0o, r0l, n_touched, G, ctr, dry ? 1u : 0u, s);
     C.touched_label_index(tch, n_touched);
     if (nq)
       gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
@@ -888,13 +913,126 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       C.has_result = false;
       return fail(c, GAMMA_ETIMEDOUT, "apply_batch: search deadline exceeded; batch not committed");
     }
-    C.live = C.live + 2ull * n_insert - 2ull * n_delete;
+    if (!dry) C.live = C.live + 2ull * n_insert - 2ull * n_delete;
     C.has_result = true;
     C.last_tuples = out->n_tuples;
     C.last_twidth = tw;
     C.last_has_ord = out->ord != nullptr;
     return out->n_tuples < out->n_tuples_found ? GAMMA_TRUNCATED : GAMMA_OK;
   });
+}
+
+gamma_status gamma_get_tuning(const gamma_ctx* c, gamma_tuning* out) {
+  if (!c || !out) return GAMMA_EINVAL;
+  *out = c->tun;
+  return GAMMA_OK;
+}
+
+namespace {
+bool tuning_ok(const gamma_tuning& t) {
+  return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && (t.steal == 1 || t.steal == 2) &&
+         t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
+         t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
+         (t.query_launch == 1 || t.query_launch == 2);
+}
+}  // namespace
+
+gamma_status gamma_set_tuning(gamma_ctx* c, const gamma_tuning* in) {
+  if (!c || !in) return GAMMA_EINVAL;
+  gamma_tuning t = c->tun;
+  if (in->waves_per_cu) t.waves_per_cu = in->waves_per_cu;
+  if (in->steal) t.steal = in->steal;
+  if (in->poll_cycles) t.poll_cycles = in->poll_cycles;
+  if (in->split_inner) t.split_inner = in->split_inner;
+  if (in->split_leaf) t.split_leaf = in->split_leaf;
+  if (in->query_launch) t.query_launch = in->query_launch;
+  if (!tuning_ok(t)) return fail(c, GAMMA_EINVAL, "set_tuning: value out of range");
+  c->tun = t;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                            const uint8_t* op, gamma_mem where, uint32_t flags, uint32_t max_points,
+                            uint32_t reps, gamma_tuning* best, double* best_ms, double* base_ms) {
+  if (!c || !best) return GAMMA_EINVAL;
+  if (max_points < 1 || max_points > 64 || reps < 1 || reps > 9)
+    return fail(c, GAMMA_EINVAL, "autotune: max_points must be 1..64 and reps 1..9");
+  flags = (flags | GAMMA_F_DRY_RUN) & ~(uint32_t)GAMMA_F_TUPLES;
+  std::vector<std::pair<gamma_tuning, double>> seen;
+  auto same = [](const gamma_tuning& a, const gamma_tuning& b) {
+    return a.waves_per_cu == b.waves_per_cu && a.steal == b.steal && a.poll_cycles == b.poll_cycles &&
+           a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch;
+  };
+  gamma_status err = GAMMA_OK;
+  // median device time of `reps` dry runs at tuning t (< 0: failed)
+  auto eval = [&](const gamma_tuning& t) -> double {
+    for (auto& p : seen)
+      if (same(p.first, t)) return p.second;
+    if ((uint32_t)seen.size() >= max_points || err != GAMMA_OK) return -1.0;
+    c->tun = t;
+    std::vector<double> ms;
+    for (uint32_t r = 0; r < reps; ++r) {
+      gamma_batch_result res;
+      const gamma_status st = gamma_apply_batch(c, n_upd, src, dst, op, where, flags, &res);
+      if (st < 0) {
+        err = st;
+        return -1.0;
+      }
+      ms.push_back(res.stats.ms_total);
+    }
+    std::sort(ms.begin(), ms.end());
+    const double m = ms[ms.size() / 2];
+    seen.push_back({t, m});
+    return m;
+  };
+  const gamma_tuning start = c->tun;
+  gamma_tuning cur = start;
+  double cur_ms = eval(cur);
+  if (cur_ms < 0) {
+    c->tun = start;
+    return err != GAMMA_OK ? err : GAMMA_EINVAL;
+  }
+  if (base_ms) *base_ms = cur_ms;
+  const uint32_t wpc_v[] = {4, 8, 12, 16, 24};
+  const uint32_t poll_v[] = {1500, 3000, 6000, 12000, 24000};
+  const uint32_t leaf_v[] = {128, 256, 512, 1024, 2048};
+  const uint32_t inner_v[] = {64, 128, 256, 512};
+  const bool many_q = c->queries.size() > 1;
+  for (int pass = 0; pass < 3; ++pass) {
+    bool moved = false;
+    // one dimension at a time: keep a value only if it is at least 1% faster
+    auto sweep = [&](uint32_t gamma_tuning::*f, const uint32_t* vals, int nv) {
+      for (int i = 0; i < nv; ++i) {
+        if (cur.*f == vals[i]) continue;
+        gamma_tuning t = cur;
+        t.*f = vals[i];
+        const double m = eval(t);
+        if (m >= 0 && m < 0.99 * cur_ms) {
+          cur = t;
+          cur_ms = m;
+          moved = true;
+        }
+      }
+    };
+    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2};
+    if (many_q) sweep(&gamma_tuning::query_launch, ql_v, 2);
+    sweep(&gamma_tuning::steal, steal_v, 2);
+    sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);
+    if (cur.steal == 1) {
+      sweep(&gamma_tuning::poll_cycles, poll_v, 5);
+      sweep(&gamma_tuning::split_leaf, leaf_v, 5);
+      sweep(&gamma_tuning::split_inner, inner_v, 4);
+    }
+    if (!moved || err != GAMMA_OK || (uint32_t)seen.size() >= max_points) break;
+  }
+  if (err != GAMMA_OK && err != GAMMA_ETIMEDOUT) {
+    c->tun = start;
+    return err;
+  }
+  c->tun = cur;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return GAMMA_OK;
 }
 
 gamma_status gamma_copy_tuples(gamma_ctx* c, uint32_t* tuples, uint32_t* meta, uint32_t* ord,

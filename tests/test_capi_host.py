@@ -50,6 +50,10 @@ def test_create_without_gpu_fails_cleanly(lib):
     assert st == capi.GAMMA_EDEVICE and not ptr.value
     # calls on a null context are rejected, not crashed
     assert lib.gamma_destroy(None) == capi.GAMMA_OK
+    t = capi.Tuning()
+    assert lib.gamma_get_tuning(None, ctypes.byref(t)) == capi.GAMMA_EINVAL
+    assert lib.gamma_set_tuning(None, ctypes.byref(t)) == capi.GAMMA_EINVAL
+    assert lib.gamma_autotune(None, 0, None, None, None, 0, 0, 8, 1, ctypes.byref(t), None, None) == capi.GAMMA_EINVAL
 
 
 def test_validate_graph(lib):

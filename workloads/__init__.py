@@ -9,8 +9,8 @@ Workload shapes follow the paper's experimental setup (Sec. VI-A): power-law
 data graphs with skewed label alphabets (Table II) stand in for its datasets,
 queries are extracted from the data graph by random walks and classed as
 Dense (average degree >= 3), Sparse (< 3) or Tree, and batches mix edge
-insertions with deletions.  The concrete sizes are the five configurations
-named at the top of the design doc.
+insertions with deletions.  The concrete sizes are those of tiny(), mid(),
+large() and batched_queries() below.
 
 Randomness is counter-based (SplitMix64 finaliser), so every array is a pure
 function of (seed, tag, counter) and independent of thread counts.
@@ -332,10 +332,12 @@ def keys_of(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
 
 
 class _Adj:
-    """Neighbour lookup over the CSR graph plus a set of inserted edges."""
+    """Neighbour lookup over the CSR graph plus a set of inserted edges,
+    optionally restricted to vertices whose label is >= min_label."""
 
-    def __init__(self, graph: Graph, ins_keys: np.ndarray):
+    def __init__(self, graph: Graph, ins_keys: np.ndarray, min_label: int = 0):
         self.g = graph
+        self.min_label = min_label
         self.extra = {}
         for key in ins_keys.tolist():
             a, b = key >> 32, key & 0xFFFFFFFF
@@ -347,6 +349,8 @@ class _Adj:
         e = self.extra.get(v)
         if e:
             r = np.union1d(r, np.array(e, dtype=np.uint32))
+        if self.min_label:
+            r = r[self.g.labels[r] >= self.min_label]
         return r
 
     def has(self, u: int, v: int) -> bool:
@@ -387,7 +391,7 @@ def _induced_edges(adj: _Adj, verts: Sequence[int]) -> List[Tuple[int, int]]:
 
 
 def extract_query(graph: Graph, ins_keys: np.ndarray, k: int, kind: str, seed: int,
-                  dense_ratio: float = 0.6, max_tries: int = 10000) -> Query:
+                  dense_ratio: float = 0.6, max_tries: int = 10000, min_label: int = 0) -> Query:
     """Extract a connected k-vertex query whose first edge maps to an inserted edge.
 
     kind = "induced": the walk's vertex set with every edge among them in G u I.
@@ -395,9 +399,17 @@ def extract_query(graph: Graph, ins_keys: np.ndarray, k: int, kind: str, seed: i
     kind = "tree":    the walk's discovery tree.
     kind = "dense":   greedy densifying growth; ceil(dense_ratio * C(k,2)) edges.
     The identity map onto the walk's vertices is a match in G' that uses an
-    inserted edge, so it belongs to the insertion result (the planted match)."""
-    adj = _Adj(graph, ins_keys)
+    inserted edge, so it belongs to the insertion result (the planted match).
+    With min_label > 0 the walk only visits vertices whose label is >=
+    min_label (labels are ranked by frequency, so these are the rarer ones)."""
+    adj = _Adj(graph, ins_keys, min_label)
     draws = Draws(seed, TAG_QUERY)
+    if min_label:
+        a_lab = graph.labels[(ins_keys >> np.uint64(32)).astype(np.int64)]
+        b_lab = graph.labels[(ins_keys & np.uint64(0xFFFFFFFF)).astype(np.int64)]
+        ins_keys = ins_keys[(a_lab >= min_label) & (b_lab >= min_label)]
+        if ins_keys.shape[0] == 0:
+            raise RuntimeError("no inserted edge between vertices of the allowed labels")
     n_ins = int(ins_keys.shape[0])
     best = None
     for attempt in range(max_tries):
@@ -511,7 +523,8 @@ def tiny(seed: int = 0) -> Workload:
 
 def rmat_stream(scale: int, m_graph: int, L: int, zipf_s: float, n_ins: int, n_del: int,
                 n_batches: int, queries_spec: Sequence[Tuple[int, str]], seed: int = 0,
-                pool_batches: Optional[int] = None, name: str = "", threads: int = 0) -> Workload:
+                pool_batches: Optional[int] = None, name: str = "", threads: int = 0,
+                query_min_label: int = 0) -> Workload:
     """R-MAT graph, a stream of mixed batches, and queries extracted on G u I_0."""
     pool_batches = pool_batches or n_batches
     if n_batches > pool_batches:
@@ -523,7 +536,8 @@ def rmat_stream(scale: int, m_graph: int, L: int, zipf_s: float, n_ins: int, n_d
     queries = []
     protect = set()
     for qi, (k, kind) in enumerate(queries_spec):
-        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)))
+        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)),
+                          min_label=query_min_label)
         queries.append(q)
         for (x, y) in q.edges.tolist():
             a, b = q.planted[x], q.planted[y]
@@ -547,21 +561,35 @@ def mid(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
                        pool_batches=max(64, n_batches), name="mid-rmat20", threads=threads)
 
 
+LARGE_QUERY_MIN_LABEL = 12  # Zipf(1.0) over 32 labels: each label >= 12 covers <= 1.9% of vertices
+
+
 def large(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
     """R-MAT scale 24, |E| = 16 * 2^24 (average degree 32 = 2^29 CSR
     entries), 32 Zipf(1.0) labels, two 8-vertex queries (sparse: tree + one
-    cycle; dense: 17 edges), batches of 90,000 insertions and 10,000 deletions."""
+    cycle; dense: 17 edges), batches of 90,000 insertions and 10,000 deletions.
+    The query walks visit only vertices of the rarer labels (>= 12): walks
+    through the most frequent labels give 8-vertex queries with more than
+    10^15 incremental matches per batch on this graph."""
     return rmat_stream(24, 16 << 24, 32, 1.0, 90000, 10000, n_batches, [(8, "sparse"), (8, "dense")],
-                       seed, pool_batches=max(16, n_batches), name="large-rmat24", threads=threads)
+                       seed, pool_batches=max(16, n_batches), name="large-rmat24", threads=threads,
+                       query_min_label=LARGE_QUERY_MIN_LABEL)
 
 
-def batched_queries(seed: int = 0, n_batches: int = 1, n_queries: int = 64, threads: int = 0) -> Workload:
+BATCHED_QUERY_MIN_LABEL = 8  # Zipf(1.2) over 16 labels: each label >= 8 covers <= 2.6% of vertices
+
+
+def batched_queries(seed: int = 0, n_batches: int = 1, n_queries: int = 64, threads: int = 0,
+                    query_min_label: int = BATCHED_QUERY_MIN_LABEL) -> Workload:
     """The mid graph with 64 standing queries of 4..12 vertices (even ids
-    sparse, odd ids dense) and one 10^4-update batch."""
+    sparse, odd ids dense) and batches of 8,000 insertions and 2,000
+    deletions.  The query walks visit only vertices of the rarer labels
+    (>= query_min_label), as for the large workload."""
     d = Draws(sub_seed(seed, TAG_QUERY + 1000), TAG_QUERY)
     spec = [(4 + d.below(9), "sparse" if i % 2 == 0 else "dense") for i in range(n_queries)]
     return rmat_stream(20, 8 << 20, 16, 1.2, 8000, 2000, n_batches, spec, seed,
-                       pool_batches=max(64, n_batches), name="batched-rmat20", threads=threads)
+                       pool_batches=max(64, n_batches), name="batched-rmat20", threads=threads,
+                       query_min_label=query_min_label)
 
 
 # --------------------------------------------------------------------------
