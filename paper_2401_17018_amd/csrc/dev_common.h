@@ -26,17 +26,18 @@
 // Matching plan of one directed query edge (x, y): the order in which the
 // query vertices are matched (order[0] = x, order[1] = y) and, per level l,
 // which already-matched query vertices are neighbours of order[l].
+// Every field is a full 32-bit word so that a kernel reading a plan through
+// the constant address space gets scalar loads.
 struct alignas(16) GmPlan {
-  uint8_t k;
-  uint8_t x, y;
-  uint8_t pad0;
-  uint32_t q;              // query index
-  uint8_t order[GM_MAX_K];
-  uint16_t back[GM_MAX_K]; // bitmask over query vertex ids
-  uint16_t lab[GM_MAX_K];  // label of order[l]
-  uint8_t pos[GM_MAX_K];   // pos[u] = level at which query vertex u is matched
-  uint8_t bofs[GM_MAX_K];  // first slot of level l's neighbour-list records
-  uint8_t lslot[GM_MAX_K]; // label-index slot of order[l]'s label
+  uint32_t k;
+  uint32_t x, y;
+  uint32_t q;               // query index
+  uint32_t order[GM_MAX_K];
+  uint32_t back[GM_MAX_K];  // bitmask over query vertex ids
+  uint32_t lab[GM_MAX_K];   // label of order[l]
+  uint32_t pos[GM_MAX_K];   // pos[u] = level at which query vertex u is matched
+  uint32_t bofs[GM_MAX_K];  // first slot of level l's neighbour-list records
+  uint32_t lslot[GM_MAX_K]; // label-index slot of order[l]'s label
 };
 
 // Per query: plan range and size.

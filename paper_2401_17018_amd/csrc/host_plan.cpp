@@ -88,13 +88,13 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
   for (auto& d : dirs) {
     GmPlan p;
     std::memset(&p, 0, sizeof(p));
-    p.k = (uint8_t)k;
-    p.x = (uint8_t)d.first;
-    p.y = (uint8_t)d.second;
+    p.k = k;
+    p.x = d.first;
+    p.y = d.second;
     p.q = qindex;
     uint32_t matched = (1u << d.first) | (1u << d.second);
-    p.order[0] = (uint8_t)d.first;
-    p.order[1] = (uint8_t)d.second;
+    p.order[0] = d.first;
+    p.order[1] = d.second;
     for (uint32_t l = 2; l < k; ++l) {
       int best = -1;
       for (uint32_t u = 0; u < k; ++u) {
@@ -119,17 +119,17 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
           continue;
         }
       }
-      p.order[l] = (uint8_t)best;
+      p.order[l] = (uint32_t)best;
       matched |= 1u << best;
     }
     uint32_t bofs = 0;
     uint32_t placed = 0;
     for (uint32_t l = 0; l < k; ++l) {
       uint32_t u = p.order[l];
-      p.pos[u] = (uint8_t)l;
-      p.lab[l] = (uint16_t)q.labels[u];
-      p.back[l] = (uint16_t)(l >= 2 ? (adjm[u] & placed) : 0);
-      p.bofs[l] = (uint8_t)bofs;
+      p.pos[u] = l;
+      p.lab[l] = q.labels[u];
+      p.back[l] = l >= 2 ? (adjm[u] & placed) : 0;
+      p.bofs[l] = bofs;
       if (l >= 2) bofs += __builtin_popcount(p.back[l]);
       placed |= 1u << u;
     }

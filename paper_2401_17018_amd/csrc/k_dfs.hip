@@ -44,6 +44,9 @@ constexpr int DFS_WAVES = DFS_THREADS / GM_WAVE;
 constexpr int MAX_OTH = 120;  // >= |E(Q)| - 1 for any simple query with k <= 16
 constexpr int TASK_WORDS = 32;
 constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
+// the idle count is kept in IDLE_REPS copies, one per 128-byte line; a wave
+// polls the copy of its XCD
+constexpr uint32_t IDLE_REPS = 8, IDLE_STRIDE = 32;
 #ifndef GM_DFS_PROFILE
 #define GM_DFS_PROFILE 0
 #endif
@@ -61,26 +64,27 @@ constexpr int LEAF_UNROLL = GM_LEAF_UNROLL;          // last-level chunks examin
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
+  uint32_t fo[GM_MAX_K];   // the same by matching position: fo[l] = f[order[l]]
   uint32_t fx[GM_MAX_K];   // external id of the same
   uint64_t drv[GM_MAX_K];  // arena index where level l's candidate subrange starts
   uint32_t len[GM_MAX_K];  // end of the range to examine at level l
   uint32_t cur[GM_MAX_K];  // next subrange entry to examine
   uint32_t chunk[GM_MAX_K];
   uint64_t mask[GM_MAX_K]; // survivors of the current chunk not descended into yet
-  uint32_t drvw[GM_MAX_K]; // query vertex whose list drives level l
+  uint32_t drvv[GM_MAX_K]; // data vertex whose row drives level l
   uint32_t oth_n[GM_MAX_K];
   uint64_t hpre;           // checksum salt + element terms of every position but the last vertex
   uint64_t tally[8];       // idle, init, inner, leaf, hand-over cycles; tasks received; hand-overs; nodes
   uint64_t oth_base[MAX_OTH];
   uint32_t oth_len[MAX_OTH];
-  uint32_t oth_w[MAX_OTH];
+  uint32_t oth_v[MAX_OTH];  // data vertex whose row holds each probed list
   // Last-level set-up, prepared at the level before it (k >= 4).  The lists
   // of the last vertex's matched neighbours other than order[k-2] do not
   // change while level k-2 is searched ("static"); the survivors of the
   // current level-(k-2) chunk carry their own row's subrange ("pf_*").
   uint64_t st_base[GM_MAX_K];
   uint32_t st_len[GM_MAX_K];
-  uint32_t st_w[GM_MAX_K];
+  uint32_t st_v[GM_MAX_K];
   uint32_t st_n;
   uint64_t st_h;           // checksum salt + element terms of order[0 .. k-3]
   uint32_t pf_c[GM_WAVE];  // survivor's internal id
@@ -89,6 +93,11 @@ struct WaveState {
   uint64_t pf_base[GM_WAVE];
   uint64_t pf_h[GM_WAVE];  // its element term
 };
+
+// Plans and query records are never written during a search: reading them
+// through the constant address space lets uniform reads use scalar loads.
+typedef const __attribute__((address_space(4))) GmPlan* CPlan;
+typedef const __attribute__((address_space(4))) GmQueryDev* CQuery;
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline uint64_t uni64(uint64_t x) {
@@ -105,11 +114,6 @@ __device__ inline uint64_t lane_val64(uint64_t x, uint32_t i) {
 __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
   int lo = __shfl_xor((int)(uint32_t)v, m, GM_WAVE);
   int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, GM_WAVE);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-__device__ inline uint64_t shfl64(uint64_t v, int src) {
-  int lo = __shfl((int)(uint32_t)v, src, GM_WAVE);
-  int hi = __shfl((int)(uint32_t)(v >> 32), src, GM_WAVE);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 __device__ inline uint64_t wave_sum64(uint64_t v) {
@@ -241,7 +245,7 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t
     const uint32_t nok = (uint32_t)__popcll(m);
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&P.ctr->tuples_found, (unsigned long long)nok);
-    base = shfl64(base, 0);
+    base = lane_val64(base, 0);
     const uint64_t pos = base + (uint64_t)__popcll(m & lt);
     if (ok && pos < P.tcap) {
       uint32_t* row = P.tuples + pos * P.twidth;
@@ -290,7 +294,8 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
   const uint32_t bpx = (gridDim.x + 7) / 8;
   const uint32_t slot = ((blockIdx.x & 7) * bpx + (blockIdx.x >> 3)) * DFS_WAVES + wid;
   Acc A{0, 0, 0, 0xFFFFFFFFu};
-  uint64_t st_scan = 0, st_bytes = 0;
+  uint64_t st_scan = 0, st_bytes = 0;  // per lane
+  uint64_t u_scan = 0, u_bytes = 0;    // wave-uniform (last level)
   // per-wave tallies live in LDS (keeps scalar registers free).  The cycle
   // split (slots 0-4) is only collected in builds with GM_DFS_PROFILE=1.
   if (lane < 8) S.tally[lane] = 0;
@@ -336,14 +341,14 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       unsigned long long t = 0;
       if (lane == 0) t = atomicAdd(&P.ctr->seed_head, 1ull);
-      t = shfl64(t, 0);
+      t = lane_val64(t, 0);
       if (t < n_seeds) {
         const GmSeed sd = P.seeds[t];
         q = uni(sd.qd >> 8);
         dq = uni(sd.qd & 255u);
         ord = uni(sd.os >> 1);
         sign = uni(sd.os & 1u);
-        const GmPlan* pl = P.plans + P.queries[q].plan_base + dq;
+        CPlan pl = (CPlan)P.plans + ((CQuery)P.queries)[q].plan_base + dq;
         const uint32_t x = uni(pl->x), y = uni(pl->y);
         S.f[x] = uni(sd.a);
         S.f[y] = uni(sd.b);
@@ -356,7 +361,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if (!P.donate) break;
       // advertise, then wait for a task or the stop message
       // count first (a claimer decrements after claiming), then set our bit
-      atomicAdd(&P.idle_rep[lane], 1u);
+      if ((uint32_t)lane < IDLE_REPS) atomicAdd(&P.idle_rep[lane * IDLE_STRIDE], 1u);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (lane == 0) atomicOr(&P.idle_bits[slot >> 6], 1ull << (slot & 63));
       uint32_t msg = 0;
@@ -368,8 +373,8 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           msg = ld_coherent(&P.mflag[slot]);
           ab = ld_coherent(&P.ctr->aborted);
         }
-        msg = uni(__shfl(msg, 0, GM_WAVE));
-        if (uni(__shfl(ab, 0, GM_WAVE))) {
+        msg = lane_val(msg, 0);
+        if (lane_val(ab, 0)) {
           abort_now = true;
           break;
         }
@@ -386,17 +391,17 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       tword = lane < TASK_WORDS ? P.mbox[(uint64_t)slot * TASK_WORDS + lane] : 0;
       if (lane == 0) __hip_atomic_store(&P.mflag[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t w = tword;
-      q = uni(__shfl((int)w, 0, GM_WAVE)) >> 8;
-      dq = uni(__shfl((int)w, 0, GM_WAVE)) & 255u;
-      const uint32_t os = uni(__shfl((int)w, 1, GM_WAVE));
+      q = lane_val(w, 0) >> 8;
+      dq = lane_val(w, 0) & 255u;
+      const uint32_t os = lane_val(w, 1);
       ord = os >> 1;
       sign = os & 1u;
-      base_l = uni(__shfl((int)w, 2, GM_WAVE));
+      base_l = lane_val(w, 2);
       if (lane >= 8 && lane < 8 + GM_MAX_K) S.f[lane - 8] = w;
       handed = true;
     }
 
-    const GmPlan* __restrict__ pl = P.plans + P.queries[q].plan_base + dq;
+    CPlan pl = (CPlan)P.plans + ((CQuery)P.queries)[q].plan_base + dq;
     const uint32_t k = uni(pl->k);
     const uint32_t key = (q << 1) | sign;
     if (key != A.key) {
@@ -406,7 +411,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // external ids of the matched prefix (positions < base_l)
     if ((uint32_t)lane < base_l) {
       const uint32_t u = pl->order[lane];
-      S.fx[u] = P.G.old_of_new[S.f[u]];
+      const uint32_t fu = S.f[u];
+      S.fo[lane] = fu;
+      S.fx[u] = P.G.old_of_new[fu];
     }
     st_bytes += 4ull * base_l;
 
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if (P.donate) {
         unsigned long long left = 1;
         if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
-        if (shfl64(left, 0) == 1) broadcast_stop(P, lane);
+        if (lane_val64(left, 0) == 1) broadcast_stop(P, lane);
       }
       continue;
     }
@@ -428,7 +435,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // i as (w = query vertex, base = arena index of the subrange, sub = its
     // length).
     const uint32_t pf_lvl = k >= 4 ? k - 2 : 0xFFFFFFFFu;
-    auto finish_level = [&](uint32_t l, uint32_t nb, bool act, uint32_t w, uint64_t base, uint32_t sub) {
+    auto finish_level = [&](uint32_t l, uint32_t nb, bool act, uint32_t v, uint64_t base, uint32_t sub) {
       uint32_t best = 0xFFFFFFFFu, besti = 0;
       for (uint32_t i = 0; i < nb; ++i) {
         const uint32_t si = lane_val(sub, i);
@@ -443,11 +450,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         const uint32_t at = ob + ((uint32_t)lane == nb - 1 ? besti : (uint32_t)lane);
         S.oth_base[at] = base;
         S.oth_len[at] = sub;
-        S.oth_w[at] = w;
+        S.oth_v[at] = v;
       }
       S.drv[l] = lane_val64(base, besti);
       S.len[l] = best;
-      S.drvw[l] = lane_val(w, besti);
+      S.drvv[l] = lane_val(v, besti);
       S.oth_n[l] = nb - 1;
       S.cur[l] = 0;
       S.mask[l] = 0;
@@ -474,11 +481,10 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       for (uint32_t i = 0; i < nmax; ++i)
         if (i < my_i) t &= t - 1;  // drop the lower set bits: t's lowest bit is list my_i
       const bool act = my_i < my_n;
-      uint32_t w = 0, sub = 0;
+      uint32_t v = 0, sub = 0;
       uint64_t base = 0;
       if (act) {
-        w = (uint32_t)__ffs(t) - 1;
-        const uint32_t v = S.f[w];
+        v = S.f[__ffs(t) - 1];
         const uint64_t off = P.G.row_off[v];
         const uint64_t li = P.lix[(uint64_t)v * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
         base = off + (uint32_t)li;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (hi && act) {
           S.st_base[my_i] = base;
           S.st_len[my_i] = sub;
-          S.st_w[my_i] = w;
+          S.st_v[my_i] = v;
         }
         S.st_n = nb1;
         uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         }
         S.st_h = h;
       }
-      finish_level(l, nb, act && !hi, w, base, sub);
+      finish_level(l, nb, act && !hi, v, base, sub);
       if (count) TALLY_ALWAYS(7, 1);
       if (l == k - 1) {
         const uint32_t u = uni(pl->order[l]);
@@ -519,25 +525,27 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     auto init_leaf_fast = [&](uint32_t bit) -> bool {
       const uint32_t l = k - 1;
       const uint32_t u = uni(pl->order[k - 2]);
-      S.f[u] = uni(S.pf_c[bit]);
+      const uint32_t c = uni(S.pf_c[bit]);
+      S.f[u] = c;
+      S.fo[k - 2] = c;
       S.fx[u] = uni(S.pf_x[bit]);
       const uint32_t nb1 = uni(S.st_n);
       const bool dyn = (uni(pl->back[l]) >> u) & 1u;
       const uint32_t dlen = uni(S.pf_len[bit]);
       if (dyn && dlen == 0) return false;
       const uint32_t nb = nb1 + (dyn ? 1u : 0u);
-      uint32_t w = 0, sub = 0;
+      uint32_t v = 0, sub = 0;
       uint64_t base = 0;
       if ((uint32_t)lane < nb1) {
-        w = S.st_w[lane];
+        v = S.st_v[lane];
         base = S.st_base[lane];
         sub = S.st_len[lane];
       } else if ((uint32_t)lane == nb1) {
-        w = u;
+        v = c;
         base = uni64(S.pf_base[bit]);
         sub = dlen;
       }
-      finish_level(l, nb, (uint32_t)lane < nb, w, base, sub);
+      finish_level(l, nb, (uint32_t)lane < nb, v, base, sub);
       S.hpre = uni64(S.st_h) + uni64(S.pf_h[bit]);
       TALLY_ALWAYS(7, 1);
       return true;
@@ -590,12 +598,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         ++st_scan;
       }
       const uint32_t c = e & GM_IDMASK;
-      for (uint32_t j = 0; j < l; ++j) ok = ok && (c != S.f[pl->order[j]]);
+      const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
+      for (uint32_t j = 0; j < l; ++j) ok = ok && (c != lane_val(fo_all, j));
       if (ok && l + 1 < k) {
         ok = (P.cand[(uint64_t)q * n + c] >> u) & 1u;
         st_bytes += 2;
       }
-      if (ok && (e & GM_FLAG)) ok = visible(P.H, S.f[S.drvw[l]], c, ord, sign, st_bytes);
+      if (ok && (e & GM_FLAG)) ok = visible(P.H, S.drvv[l], c, ord, sign, st_bytes);
       const uint32_t on = uni(S.oth_n[l]);
       const uint32_t ob = uni(pl->bofs[l]);
       for (uint32_t i = 0; i < on; ++i) {
@@ -612,7 +621,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
             if ((e2 & GM_IDMASK) != c)
               ok = false;
             else if (e2 & GM_FLAG)
-              ok = visible(P.H, S.f[S.oth_w[ob + i]], c, ord, sign, st_bytes);
+              ok = visible(P.H, S.oth_v[ob + i], c, ord, sign, st_bytes);
           }
         }
       }
@@ -662,13 +671,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         for (int tries = 0; nz && target < 0 && tries < 2; ++tries) {
           const int ln = __ffsll((unsigned long long)nz) - 1;
           nz &= nz - 1;
-          uint64_t vv = shfl64(v, ln);
+          uint64_t vv = lane_val64(v, (uint32_t)ln);
           const uint32_t word = (start + r + (uint32_t)ln) % nwords;
           for (int b_try = 0; vv && target < 0 && b_try < 4; ++b_try) {
             const int b = __ffsll((unsigned long long)vv) - 1;
             unsigned long long old = 0;
             if (lane == 0) old = atomicAnd(&P.idle_bits[word], ~(1ull << b));
-            old = shfl64(old, 0);
+            old = lane_val64(old, 0);
             if ((old >> b) & 1ull)
               target = (int32_t)(word * 64 + b);
             else
@@ -677,7 +686,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         }
       }
       if (target < 0) return;
-      atomicSub(&P.idle_rep[lane], 1u);
+      if ((uint32_t)lane < IDLE_REPS) atomicSub(&P.idle_rep[lane * IDLE_STRIDE], 1u);
       if (kind == 1)
         S.len[lv] = mid;
       else
@@ -731,23 +740,21 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) x[j] = 0;
       }
+      // candidates scanned and their bytes, counted once per wave
+      uint32_t n_in = 0;
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j)
-        if (ok[j]) {
-          st_bytes += need_x ? 8 : 4;
-          ++st_scan;
-        }
+      for (int j = 0; j < LEAF_UNROLL; ++j) n_in += (uint32_t)__popcll(__ballot(ok[j]));
+      u_scan += n_in;
+      u_bytes += (uint64_t)n_in * (need_x ? 8u : 4u);
       CNT(0, 1);
-#if GM_DFS_COUNT
-#pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) CNT(3, __popcll(__ballot(ok[j])));
-#endif
+      CNT(3, n_in);
+      const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
       for (uint32_t jj = 0; jj < l; ++jj) {
-        const uint32_t fv = uni(S.f[pl->order[jj]]);
+        const uint32_t fv = lane_val(fo_all, jj);
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
       }
-      const uint32_t fdrv = uni(S.f[S.drvw[l]]);
+      const uint32_t fdrv = uni(S.drvv[l]);
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j)
         if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, fdrv, e[j] & GM_IDMASK, ord, sign, st_bytes);
@@ -758,10 +765,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (!__ballot(anyok)) break;
         const uint64_t base = S.oth_base[ob + i];
         const uint32_t olen = uni(S.oth_len[ob + i]);
-#if GM_DFS_COUNT
+        // a lower-bound search over olen entries reads at most
+        // bit_length(olen) entries, plus the entry it lands on
+        uint32_t n_probe = 0;
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) CNT(2, __popcll(__ballot(ok[j])));
-#endif
+        for (int j = 0; j < LEAF_UNROLL; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
+        u_bytes += 4ull * n_probe * (uint32_t)(33 - __clz((int)olen));
+        CNT(2, n_probe);
         CNT(4, olen);
         {
           uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
@@ -778,7 +788,6 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
               // clamped so a finished search still reads inside the list (olen >= 1)
               const uint32_t at = lo[j] + (cnt[j] >> 1);
               v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
-              if (cnt[j]) st_bytes += 4;
             }
             CNT(1, LEAF_UNROLL);
 #pragma unroll
@@ -796,7 +805,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
             }
             if (!__ballot(any)) break;
           }
-          const uint32_t wv = uni(S.f[S.oth_w[ob + i]]);
+          const uint32_t wv = uni(S.oth_v[ob + i]);
           uint32_t e2[LEAF_UNROLL];
 #pragma unroll
           for (int j = 0; j < LEAF_UNROLL; ++j) {
@@ -829,11 +838,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       // an empty first level (a seed with no extension)
     } else {
       if (handed) {
-        S.cur[l] = uni(__shfl((int)tword, 6, GM_WAVE));
-        S.len[l] = uni(__shfl((int)tword, 7, GM_WAVE));
-        S.chunk[l] = uni(__shfl((int)tword, 3, GM_WAVE));
-        const uint32_t mlo = uni(__shfl((int)tword, 4, GM_WAVE));
-        const uint32_t mhi = uni(__shfl((int)tword, 5, GM_WAVE));
+        S.cur[l] = lane_val(tword, 6);
+        S.len[l] = lane_val(tword, 7);
+        S.chunk[l] = lane_val(tword, 3);
+        const uint32_t mlo = lane_val(tword, 4);
+        const uint32_t mhi = lane_val(tword, 5);
         S.mask[l] = ((uint64_t)mhi << 32) | mlo;
       }
       for (;;) {
@@ -849,13 +858,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
               if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) atomicExch(&P.ctr->aborted, 1u);
               ab = ld_coherent(&P.ctr->aborted);
             }
-            if (uni(__shfl(ab, 0, GM_WAVE))) {
+            if (lane_val(ab, 0)) {
               abort_now = true;
               break;
             }
             if (P.donate) {
               // gate: with c idle waves, about 8c of the busy waves try per period
-              const uint32_t c = ld_coherent(&P.idle_rep[slot & 63]);
+              const uint32_t c = ld_coherent(&P.idle_rep[(blockIdx.x & (IDLE_REPS - 1)) * IDLE_STRIDE]);
               if (c != 0 && c < 0x80000000u) {
                 const uint32_t roll = (uint32_t)gm_mix64(((uint64_t)slot << 32) ^ now) & 1023u;
                 if (roll < (c >= 128 ? 1024u : c * 8u)) try_donate(l);
@@ -901,6 +910,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         const uint32_t c = uni(col[at] & GM_IDMASK);
         const uint32_t u = uni(pl->order[l]);
         S.f[u] = c;
+        S.fo[l] = c;
         S.fx[u] = uni(ext[at]);
         st_bytes += 8;
         if (init_level(l + 1, true)) ++l;
@@ -911,14 +921,14 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     if (P.donate) {
       unsigned long long left = 1;
       if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
-      if (shfl64(left, 0) == 1) broadcast_stop(P, lane);
+      if (lane_val64(left, 0) == 1) broadcast_stop(P, lane);
     }
   }
   flush_acc(P, A, lane);
 #undef TALLY
 #undef TALLY_ALWAYS
 #undef CYCLES
-  const uint64_t ss = wave_sum64(st_scan), sb = wave_sum64(st_bytes);
+  const uint64_t ss = wave_sum64(st_scan) + u_scan, sb = wave_sum64(st_bytes) + u_bytes;
   if (lane < 6) atomicAdd(&P.ctr->cyc[lane], (unsigned long long)S.tally[lane]);
   if (lane == 0) {
     atomicAdd(&P.ctr->steals, (unsigned long long)S.tally[6]);

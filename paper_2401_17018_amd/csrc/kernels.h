@@ -70,7 +70,7 @@ struct GmDfsParams {
   uint32_t* mbox;                 // [n_slots][32] task records
   uint32_t* mflag;                // [n_slots] 1 = a task waits in the mailbox
   unsigned long long* idle_bits;  // [ceil(n_slots / 64)] bit set = the wave waits for work
-  uint32_t* idle_rep;             // [64] replicated count of idle waves (a polling hint)
+  uint32_t* idle_rep;             // [8 x 32] count of idle waves in 8 copies, 128 B apart (a polling hint)
   uint32_t n_slots;
   uint32_t donate;                // 0 = no hand-over (each wave keeps its seed)
   uint64_t deadline_ticks;        // wall-clock ticks a wave may search (0 = no deadline)

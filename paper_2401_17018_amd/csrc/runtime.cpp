@@ -229,8 +229,8 @@ struct gamma_ctx {
     for (auto& q : queries)
       for (auto& p : q.plans)
         for (uint32_t l = 0; l < q.k; ++l)
-          p.lslot[l] = (uint8_t)(std::lower_bound(lix_labels.begin(), lix_labels.end(), (uint32_t)p.lab[l]) -
-                                 lix_labels.begin());
+          p.lslot[l] = (uint32_t)(std::lower_bound(lix_labels.begin(), lix_labels.end(), p.lab[l]) -
+                                  lix_labels.begin());
     if (!lix_labels.empty()) {
       uint32_t* dl = ensure<uint32_t>(lix_lab, lix_labels.size());
       chk(hipMemcpyAsync(dl, lix_labels.data(), lix_labels.size() * 4, hipMemcpyHostToDevice, stream), "h2d");
@@ -766,7 +766,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.mbox = C.ensure<uint32_t>(C.mbox, (size_t)slots * 32);
       P.mflag = C.ensure<uint32_t>(C.mflag, slots);
       P.idle_bits = (unsigned long long*)C.ensure<uint64_t>(C.idle_bits, (slots + 63) / 64);
-      P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 64);
+      P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 256);
       P.n_slots = slots;
       P.donate = C.tun.steal == 1 ? 1u : 0u;
       P.deadline_ticks = (uint64_t)C.opt.deadline_ms * C.wall_khz;
@@ -782,7 +782,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
         }
         gm::fill_u32(P.mflag, 0, slots, s);
         gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
-        gm::fill_u32(P.idle_rep, 0, 64, s);
+        gm::fill_u32(P.idle_rep, 0, 256, s);
         gm::launch_pending_init(ctr, s);
         gm::launch_dfs(P, blocks, s);
       }
