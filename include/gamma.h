@@ -241,6 +241,83 @@ gamma_status gamma_autotune(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
                             const uint8_t* op, gamma_mem where, uint32_t flags, uint32_t max_points,
                             uint32_t reps, gamma_tuning* best, double* best_ms, double* base_ms);
 
+/* ------------------------------------------------------------------ serving
+ * A served update stream with continuous batching (the paper's asynchronous
+ * pipeline keeps batch preparation off the search's critical path,
+ * Sec. IV-A).  A server owns a worker thread that applies queued update
+ * requests to the context's graph.  Each device batch takes queued requests
+ * in submission order while their updates fit max_batch_updates, and closes
+ * before a request that inserts an edge another request of the batch
+ * deletes (or the reverse): such pairs are applied in order.  After each
+ * batch the graph equals the one that applying its requests one at a time
+ * would give, and the batch's net result per query (|+| - |-|) equals the
+ * sum of theirs; the batch reports M(G_after) \ M(G_before) and the reverse.
+ * Batches commit in submission order.  While a server exists, the context
+ * may only be used through the server (the worker calls gamma_apply_batch
+ * on it). */
+typedef struct gamma_server gamma_server;
+
+typedef struct gamma_serve_options {
+  uint32_t max_batch_updates; /* admission limit per device batch, 1..2^20 (0 = 2^17); a single
+                                 request may not exceed it */
+  uint32_t flags;             /* GAMMA_F_HASH / GAMMA_F_PER_UPDATE for every batch (no TUPLES,
+                                 DRY_RUN or CANONICAL) */
+  uint32_t coalesce;          /* 1 = continuous batching (default), 2 = one request per batch */
+  uint32_t reserved[5];
+} gamma_serve_options;
+
+/* A committed request. */
+typedef struct gamma_request_result {
+  uint64_t ticket;       /* submission order, from 0 */
+  uint64_t batch;        /* device batch that committed it */
+  double t_submit_ms;    /* server clock (ms since gamma_serve_create) at submission */
+  double t_done_ms;      /* at commit of its batch */
+  uint32_t n_updates;
+  int32_t status;        /* the batch's gamma_status */
+} gamma_request_result;
+
+/* A device batch of the server. */
+typedef struct gamma_serve_batch {
+  uint64_t batch;
+  uint64_t first_ticket; /* its requests are first_ticket .. first_ticket + n_requests - 1 */
+  uint32_t n_requests;
+  uint32_t n_updates;    /* before canonicalisation */
+  uint32_t n_canonical;
+  uint32_t n_queries;
+  int32_t status;
+  float ms_device;       /* stats.ms_total of the batch */
+  double t_start_ms, t_done_ms;
+} gamma_serve_batch;
+
+/* Start a server on a context with a loaded graph.  Errors: EINVAL (bad
+ * options), ESTATE (no graph), ENOMEM. */
+gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, gamma_server** out);
+
+/* Queue one request (host arrays, copied; thread-safe).  The request is
+ * validated like a batch (ids < n, no self loop, no +e with -e inside it):
+ * EINVAL / ECONFLICT reject it and nothing is queued.  *ticket (may be
+ * NULL) receives its ticket. */
+gamma_status gamma_serve_submit(gamma_server* srv, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                const uint8_t* op, uint64_t* ticket);
+
+/* Move up to `max` committed requests (ticket order) into out[]; *n_out
+ * receives how many.  Each is returned once. */
+gamma_status gamma_serve_poll(gamma_server* srv, gamma_request_result* out, uint32_t max, uint32_t* n_out);
+
+/* Block until every submitted request is committed. */
+gamma_status gamma_serve_drain(gamma_server* srv);
+
+/* Requests submitted and committed, and device batches applied (any may be NULL). */
+gamma_status gamma_serve_counts(gamma_server* srv, uint64_t* submitted, uint64_t* committed, uint64_t* batches);
+
+/* Information and per-query results (up to max_queries entries, may be
+ * NULL) of device batch `batch`.  Errors: EINVAL (no such batch). */
+gamma_status gamma_serve_get_batch(gamma_server* srv, uint64_t batch, gamma_serve_batch* info,
+                                   gamma_query_result* queries, uint32_t max_queries);
+
+/* Apply what is queued, stop the worker and free the server.  NULL is accepted. */
+gamma_status gamma_serve_destroy(gamma_server* srv);
+
 /* Copy up to max_records tuple records of the last batch into caller
  * buffers (any may be NULL) on the context stream; `where` is the memory
  * kind of the destinations.  Layout as in gamma_batch_result.  Errors:

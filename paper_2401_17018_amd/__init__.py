@@ -28,7 +28,7 @@ from . import capi
 from .capi import (F_CANONICAL, F_COUNT, F_DRY_RUN, F_HASH, F_PER_UPDATE, F_SEED_ATTR, F_TUPLES,
                    GAMMA_MEM_DEVICE, GAMMA_MEM_HOST)
 
-__all__ = ["Context", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch"]
+__all__ = ["Context", "Server", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch"]
 
 
 class GammaError(RuntimeError):
@@ -313,6 +313,80 @@ class Context:
                                             lab.ctypes.data_as(ctypes.c_void_p)),
                "export_graph")
         return rp, col[: nnz.value], lab
+
+
+class Server:
+    """A served update stream on a Context (continuous batching by the
+    library's worker thread).  While it exists, use the context only
+    through it."""
+
+    def __init__(self, ctx: Context, max_batch_updates: int = 0, hash: bool = True, per_update: bool = False,
+                 coalesce: bool = True):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        o = capi.ServeOptions()
+        o.max_batch_updates = int(max_batch_updates)
+        o.flags = F_COUNT | (F_HASH if hash else 0) | (F_PER_UPDATE if per_update else 0)
+        o.coalesce = 1 if coalesce else 2
+        self._ptr = ctypes.c_void_p()
+        _check(self._lib, ctx._ptr, self._lib.gamma_serve_create(ctx._ptr, ctypes.byref(o), ctypes.byref(self._ptr)),
+               "serve_create")
+        self.n_queries = len(ctx.query_k)
+
+    def submit(self, src, dst, op) -> int:
+        s = np.ascontiguousarray(src, dtype=np.uint32)
+        d = np.ascontiguousarray(dst, dtype=np.uint32)
+        o = np.ascontiguousarray(op, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        st = self._lib.gamma_serve_submit(self._ptr, int(s.shape[0]), s.ctypes.data_as(ctypes.c_void_p),
+                                          d.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(t))
+        if st < 0:
+            raise GammaError(st, "serve_submit: %s" % self._lib.gamma_status_string(st).decode())
+        return int(t.value)
+
+    def poll(self, max_results: int = 1024) -> List[dict]:
+        buf = (capi.RequestResult * max_results)()
+        n = ctypes.c_uint32()
+        _check(self._lib, None, self._lib.gamma_serve_poll(self._ptr, buf, max_results, ctypes.byref(n)), "serve_poll")
+        return [{f: getattr(buf[i], f) for f, _ in capi.RequestResult._fields_} for i in range(n.value)]
+
+    def drain(self):
+        _check(self._lib, None, self._lib.gamma_serve_drain(self._ptr), "serve_drain")
+
+    def counts(self):
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self._lib, None, self._lib.gamma_serve_counts(self._ptr, ctypes.byref(a), ctypes.byref(b),
+                                                             ctypes.byref(c)), "serve_counts")
+        return int(a.value), int(b.value), int(c.value)
+
+    def batch(self, i: int) -> dict:
+        info = capi.ServeBatch()
+        qs = (capi.QueryResult * max(self.n_queries, 1))()
+        _check(self._lib, None, self._lib.gamma_serve_get_batch(self._ptr, int(i), ctypes.byref(info), qs,
+                                                                self.n_queries), "serve_get_batch")
+        d = {f: getattr(info, f) for f, _ in capi.ServeBatch._fields_}
+        d["counts"] = np.array([[qs[q].count[sg] for sg in range(2)] for q in range(info.n_queries)], np.uint64)
+        d["hash_sum"] = np.array([[qs[q].hash_sum[sg] for sg in range(2)] for q in range(info.n_queries)], np.uint64)
+        d["hash_xor"] = np.array([[qs[q].hash_xor[sg] for sg in range(2)] for q in range(info.n_queries)], np.uint64)
+        return d
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            self._lib.gamma_serve_destroy(self._ptr)
+            self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def validate_graph(row_ptr, col, labels) -> int:

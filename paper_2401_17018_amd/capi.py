@@ -24,6 +24,8 @@ F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL, F_DRY_RUN = 1
 EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
     "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
+    "gamma_serve_create", "gamma_serve_submit", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
+    "gamma_serve_get_batch", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
     "gamma_validate_query", "gamma_validate_batch", "gamma_status_string", "gamma_last_error",
     "gamma_version",
@@ -58,6 +60,41 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in self.FIELDS}
+
+
+class ServeOptions(ctypes.Structure):
+    _fields_ = [
+        ("max_batch_updates", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("coalesce", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
+    ]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("batch", ctypes.c_uint64),
+        ("t_submit_ms", ctypes.c_double),
+        ("t_done_ms", ctypes.c_double),
+        ("n_updates", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class ServeBatch(ctypes.Structure):
+    _fields_ = [
+        ("batch", ctypes.c_uint64),
+        ("first_ticket", ctypes.c_uint64),
+        ("n_requests", ctypes.c_uint32),
+        ("n_updates", ctypes.c_uint32),
+        ("n_canonical", ctypes.c_uint32),
+        ("n_queries", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+        ("ms_device", ctypes.c_float),
+        ("t_start_ms", ctypes.c_double),
+        ("t_done_ms", ctypes.c_double),
+    ]
 
 
 class QueryResult(ctypes.Structure):
@@ -158,6 +195,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_autotune.restype = st
     lib.gamma_autotune.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, u32, u32, ctypes.POINTER(Tuning),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.gamma_serve_create.restype = st
+    lib.gamma_serve_create.argtypes = [P, ctypes.POINTER(ServeOptions), ctypes.POINTER(P)]
+    lib.gamma_serve_submit.restype = st
+    lib.gamma_serve_submit.argtypes = [P, u32, P, P, P, ctypes.POINTER(u64)]
+    lib.gamma_serve_poll.restype = st
+    lib.gamma_serve_poll.argtypes = [P, ctypes.POINTER(RequestResult), u32, ctypes.POINTER(u32)]
+    lib.gamma_serve_drain.restype = st
+    lib.gamma_serve_drain.argtypes = [P]
+    lib.gamma_serve_counts.restype = st
+    lib.gamma_serve_counts.argtypes = [P, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.gamma_serve_get_batch.restype = st
+    lib.gamma_serve_get_batch.argtypes = [P, u64, ctypes.POINTER(ServeBatch), ctypes.POINTER(QueryResult), u32]
+    lib.gamma_serve_destroy.restype = st
+    lib.gamma_serve_destroy.argtypes = [P]
     lib.gamma_copy_tuples.restype = st
     lib.gamma_copy_tuples.argtypes = [P, P, P, P, u64, ctypes.c_int]
     lib.gamma_result_release.restype = st

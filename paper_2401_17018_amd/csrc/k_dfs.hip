@@ -61,6 +61,13 @@ constexpr uint32_t IDLE_REPS = 8, IDLE_STRIDE = 32;
 #define GM_LEAF_UNROLL 4
 #endif
 constexpr int LEAF_UNROLL = GM_LEAF_UNROLL;          // last-level chunks examined per step
+// survivors of level k-2 whose last-level list is at most this long are
+// walked together (packed); longer ones keep their own level so that the
+// hand-over can split them
+#ifndef GM_PACK_MAX
+#define GM_PACK_MAX 512
+#endif
+constexpr uint32_t PACK_MAX = GM_PACK_MAX;
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
@@ -86,6 +93,7 @@ struct WaveState {
   uint32_t st_len[GM_MAX_K];
   uint32_t st_v[GM_MAX_K];
   uint32_t st_n;
+  uint32_t st_min;         // shortest static list (0xFFFFFFFF: none)
   uint64_t st_h;           // checksum salt + element terms of order[0 .. k-3]
   uint32_t pf_c[GM_WAVE];  // survivor's internal id
   uint32_t pf_x[GM_WAVE];  // its external id
@@ -115,6 +123,15 @@ __device__ inline uint64_t shfl_xor64(uint64_t v, int m) {
   int lo = __shfl_xor((int)(uint32_t)v, m, GM_WAVE);
   int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, GM_WAVE);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+// inclusive prefix sum over the lanes of a wave
+__device__ inline uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int d = 1; d < GM_WAVE; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)v, d, GM_WAVE);
+    if (lane >= d) v += o;
+  }
+  return v;
 }
 __device__ inline uint64_t wave_sum64(uint64_t v) {
 #pragma unroll
@@ -229,9 +246,12 @@ __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
 }
 
 // Emit the matches of one ballot: lane bit set <=> (prefix, u -> cx) is a match.
+// (p2, x2): a prefix position whose external id differs per lane (packed
+// last level), or p2 = 0xFFFFFFFF.
 __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t k, uint32_t u, bool ok,
                             uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q, uint32_t sign,
-                            uint32_t ord, int lane, uint64_t lt, uint64_t& bytes) {
+                            uint32_t ord, int lane, uint64_t lt, uint64_t& bytes, uint32_t p2 = 0xFFFFFFFFu,
+                            uint32_t x2 = 0) {
   if (ok) A.cnt += 1;
   uint64_t h = 0;
   if (P.flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
@@ -249,7 +269,8 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t
     const uint64_t pos = base + (uint64_t)__popcll(m & lt);
     if (ok && pos < P.tcap) {
       uint32_t* row = P.tuples + pos * P.twidth;
-      for (uint32_t j = 0; j < P.twidth; ++j) row[j] = j < k ? (j == u ? cx : S.fx[j]) : 0xFFFFFFFFu;
+      for (uint32_t j = 0; j < P.twidth; ++j)
+        row[j] = j < k ? (j == u ? cx : (j == p2 ? x2 : S.fx[j])) : 0xFFFFFFFFu;
       P.tmeta[pos] = (q << 1) | sign;
       if (P.flags & GM_F_SEED_ATTR) P.tord[pos] = ord;
       bytes += 4ull * P.twidth + 8;
@@ -501,6 +522,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           S.st_v[my_i] = v;
         }
         S.st_n = nb1;
+        uint32_t mn = 0xFFFFFFFFu;
+        for (uint32_t i = 0; i < nb1; ++i) mn = min(mn, lane_val(sub, 32 + i));
+        S.st_min = mn;
         uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
         for (uint32_t j = 0; j < l; ++j) {
           const uint32_t uj = uni(pl->order[j]);
@@ -554,7 +578,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // After a level-(k-2) chunk: every survivor lane records its external id,
     // its element term and (when order[k-2] is a matched neighbour of the
     // last vertex) its own row's subrange for the last vertex's label.
-    auto prefetch_leaf = [&](uint32_t l, uint32_t idx, uint32_t c, bool ok) {
+    auto prefetch_leaf = [&](uint32_t l, uint32_t idx, uint32_t c, bool ok) -> uint32_t {
       const uint32_t u = uni(pl->order[l]);
       const bool dyn = (uni(pl->back[k - 1]) >> u) & 1u;
       const uint32_t ls1 = uni(pl->lslot[k - 1]);
@@ -575,7 +599,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         S.pf_base[lane] = base;
         S.pf_len[lane] = sub;
         S.pf_h[lane] = elem_hash(x, u);
+        return sub;
       }
+      return 0u;
     };
 
     auto init_level = [&](uint32_t l, bool count) -> bool {
@@ -709,6 +735,62 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
     };
 
+    // ---- keep candidate e[j] (lane, chunk j) only if it is in the sorted
+    // list [base, base + olen) of row wv and that entry is visible; the
+    // LEAF_UNROLL lower-bound searches run interleaved.
+    auto probe_list = [&](bool (&ok)[LEAF_UNROLL], const uint32_t (&e)[LEAF_UNROLL], uint64_t base, uint32_t olen,
+                          uint32_t wv) {
+      // a lower-bound search over olen entries reads at most
+      // bit_length(olen) entries, plus the entry it lands on
+      uint32_t n_probe = 0;
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
+      u_bytes += 4ull * n_probe * (uint32_t)(33 - __clz((int)olen));
+      CNT(2, n_probe);
+      CNT(4, olen);
+      uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) {
+        lo[j] = 0;
+        cnt[j] = ok[j] ? olen : 0u;
+      }
+      for (;;) {
+        uint32_t v[LEAF_UNROLL];
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          // clamped so a finished search still reads inside the list (olen >= 1)
+          const uint32_t at = lo[j] + (cnt[j] >> 1);
+          v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
+        }
+        CNT(1, LEAF_UNROLL);
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          if (cnt[j]) {
+            any = true;
+            const uint32_t half = cnt[j] >> 1;
+            if (v[j] < (e[j] & GM_IDMASK)) {
+              lo[j] += half + 1;
+              cnt[j] -= half + 1;
+            } else {
+              cnt[j] = half;
+            }
+          }
+        }
+        if (!__ballot(any)) break;
+      }
+      uint32_t e2[LEAF_UNROLL];
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) {
+        const bool in = lo[j] < olen;
+        e2[j] = col[base + (in ? lo[j] : olen - 1)];
+        if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
+      }
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j)
+        if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+    };
+
     // ---- last level: LEAF_UNROLL chunks per step.  Ids and external ids are
     // loaded together, and the binary searches in the other back-neighbour
     // lists run interleaved, so every memory round trip serves 4 chunks.
@@ -763,60 +845,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) anyok = anyok || ok[j];
         if (!__ballot(anyok)) break;
-        const uint64_t base = S.oth_base[ob + i];
-        const uint32_t olen = uni(S.oth_len[ob + i]);
-        // a lower-bound search over olen entries reads at most
-        // bit_length(olen) entries, plus the entry it lands on
-        uint32_t n_probe = 0;
-#pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
-        u_bytes += 4ull * n_probe * (uint32_t)(33 - __clz((int)olen));
-        CNT(2, n_probe);
-        CNT(4, olen);
-        {
-          uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
-#pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
-            lo[j] = 0;
-            cnt[j] = ok[j] ? olen : 0u;
-          }
-          for (;;) {
-            uint32_t v[LEAF_UNROLL];
-            bool any = false;
-#pragma unroll
-            for (int j = 0; j < LEAF_UNROLL; ++j) {
-              // clamped so a finished search still reads inside the list (olen >= 1)
-              const uint32_t at = lo[j] + (cnt[j] >> 1);
-              v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
-            }
-            CNT(1, LEAF_UNROLL);
-#pragma unroll
-            for (int j = 0; j < LEAF_UNROLL; ++j) {
-              if (cnt[j]) {
-                any = true;
-                const uint32_t half = cnt[j] >> 1;
-                if (v[j] < (e[j] & GM_IDMASK)) {
-                  lo[j] += half + 1;
-                  cnt[j] -= half + 1;
-                } else {
-                  cnt[j] = half;
-                }
-              }
-            }
-            if (!__ballot(any)) break;
-          }
-          const uint32_t wv = uni(S.oth_v[ob + i]);
-          uint32_t e2[LEAF_UNROLL];
-#pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
-            const bool in = lo[j] < olen;
-            e2[j] = col[base + (in ? lo[j] : olen - 1)];
-            if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
-          }
-#pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j)
-            if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
-        }
+        probe_list(ok, e, uni64(S.oth_base[ob + i]), uni(S.oth_len[ob + i]), uni(S.oth_v[ob + i]));
       }
       const uint64_t hpre = uni64(S.hpre);
 #pragma unroll
@@ -830,6 +859,139 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint64_t t0 = CYCLES();
       try_donate_impl(lcur);
       TALLY(4, CYCLES() - t0);
+    };
+
+    // ---- every poll_cycles: deadline check, then (gated) hand-over of the
+    // shallowest splittable work at levels <= lcur.  Returns true to abort.
+    auto poll = [&](uint32_t lcur) -> bool {
+      const uint64_t now = __builtin_readcyclecounter();
+      if (now - last_poll < poll_cycles) return false;
+      last_poll = now;
+      // cooperative deadline: the first wave past it raises the abort word;
+      // every wave checks the word here and leaves
+      uint32_t ab = 0;
+      if (lane == 0) {
+        if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) atomicExch(&P.ctr->aborted, 1u);
+        ab = ld_coherent(&P.ctr->aborted);
+      }
+      if (lane_val(ab, 0)) return true;
+      if (P.donate) {
+        // gate: with c idle waves, about 8c of the busy waves try per period
+        const uint32_t c = ld_coherent(&P.idle_rep[(blockIdx.x & (IDLE_REPS - 1)) * IDLE_STRIDE]);
+        if (c != 0 && c < 0x80000000u) {
+          const uint32_t roll = (uint32_t)gm_mix64(((uint64_t)slot << 32) ^ now) & 1023u;
+          if (roll < (c >= 128 ? 1024u : c * 8u)) try_donate(lcur);
+        }
+      }
+      return false;
+    };
+
+    // ---- packed last level.  When the last query vertex's lists include
+    // the row of order[k-2], every survivor s of a level-(k-2) chunk whose
+    // own list (from its prefetch record) is short and no longer than the
+    // static lists drives its last level with that list.  Those lists are
+    // walked as one flattened range, 256 candidates per step, lane t taking
+    // candidate t of the concatenation; the other survivors are left in
+    // the level's mask for the regular descent.  my_len = this lane's
+    // survivor list length (0 if not a survivor).
+    auto leaf_packed = [&](uint32_t l, uint64_t m, uint32_t my_len) {
+      const uint32_t lf = k - 1;
+      const uint32_t u = uni(pl->order[lf]);
+      const uint32_t u2 = uni(pl->order[l]);
+      if (!((uni(pl->back[lf]) >> u2) & 1u)) return;
+      const bool in_m = (m >> lane) & 1ull;
+      const uint32_t st_min = uni(S.st_min);
+      // survivors with an empty list have no extension at all
+      const uint64_t empty = __ballot(in_m && my_len == 0);
+      const uint64_t pm = __ballot(in_m && my_len != 0 && my_len <= PACK_MAX && my_len <= st_min);
+      S.mask[l] = m & ~pm & ~empty;
+      if (!pm) return;
+      TALLY_ALWAYS(7, (uint32_t)__popcll(pm));
+      const uint32_t lenv = ((pm >> lane) & 1ull) ? my_len : 0u;
+      const uint32_t incl = wave_incl_scan(lenv, lane);  // end of each survivor's range
+      const uint32_t T = lane_val(incl, GM_WAVE - 1);
+      const uint32_t b0 = (uint32_t)__ffsll((unsigned long long)pm) - 1;
+      const uint32_t nb1 = uni(S.st_n);
+      const uint64_t st_h = uni64(S.st_h);
+      const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
+      const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
+      uint64_t wnd = pm;  // survivors whose range is not finished
+      for (uint32_t t0 = 0; t0 < T; t0 += LEAF_UNROLL * GM_WAVE) {
+        if (poll(l)) {
+          abort_now = true;
+          return;
+        }
+        while (wnd && lane_val(incl, (uint32_t)__ffsll((unsigned long long)wnd) - 1) <= t0) wnd &= wnd - 1;
+        // survivor of each candidate: scan the few survivors overlapping
+        // [t0, t0 + 256) (lanes past T read survivor b0's first entry)
+        uint32_t sl[LEAF_UNROLL], off[LEAF_UNROLL];
+        bool ok[LEAF_UNROLL], found[LEAF_UNROLL];
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
+          ok[j] = t < T;
+          sl[j] = b0;
+          off[j] = t;
+          found[j] = false;
+        }
+        const uint32_t tend = t0 + LEAF_UNROLL * GM_WAVE;
+        for (uint64_t w = wnd; w; w &= w - 1) {
+          const uint32_t b = (uint32_t)__ffsll((unsigned long long)w) - 1;
+          const uint32_t hb = lane_val(incl, b), lb = hb - lane_val(lenv, b);
+          if (lb >= tend) break;
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
+            if (ok[j] && !found[j] && t < hb) {
+              sl[j] = b;
+              off[j] = lb;
+              found[j] = true;
+            }
+          }
+        }
+        uint32_t e[LEAF_UNROLL], x[LEAF_UNROLL], cs[LEAF_UNROLL];
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
+          const uint64_t at = S.pf_base[sl[j]] + (t - off[j]);
+          e[j] = col[at];
+          x[j] = need_x ? ext[at] : 0u;
+          cs[j] = S.pf_c[sl[j]];
+        }
+        uint32_t n_in = 0;
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) n_in += (uint32_t)__popcll(__ballot(ok[j]));
+        u_scan += n_in;
+        u_bytes += (uint64_t)n_in * (need_x ? 8u : 4u);
+        CNT(0, 1);
+        CNT(3, n_in);
+        // injectivity against order[0 .. k-3] (a neighbour of the survivor
+        // is never the survivor itself)
+        for (uint32_t jj = 0; jj < l; ++jj) {
+          const uint32_t fv = lane_val(fo_all, jj);
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
+        }
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j)
+          if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, cs[j], e[j] & GM_IDMASK, ord, sign, st_bytes);
+        for (uint32_t i = 0; i < nb1; ++i) {
+          bool anyok = false;
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) anyok = anyok || ok[j];
+          if (!__ballot(anyok)) break;
+          probe_list(ok, e, uni64(S.st_base[i]), uni(S.st_len[i]), uni(S.st_v[i]));
+        }
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint64_t mm = __ballot(ok[j]);
+          if (mm) {
+            const uint64_t hpre = st_h + S.pf_h[sl[j]];
+            const uint32_t x2 = (P.flags & GM_F_TUPLES) ? S.pf_x[sl[j]] : 0u;
+            emit(P, S, A, k, u, ok[j], mm, x[j], hpre, q, sign, ord, lane, lt, st_bytes, u2, x2);
+          }
+        }
+      }
     };
 
     uint32_t l = base_l;
@@ -848,28 +1010,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       for (;;) {
         uint64_t m = uni64(S.mask[l]);
         if (m == 0) {
-          const uint64_t now = __builtin_readcyclecounter();
-          if (now - last_poll >= poll_cycles) {
-            last_poll = now;
-            // cooperative deadline: the first wave past it raises the abort
-            // word; every wave checks the word here and leaves
-            uint32_t ab = 0;
-            if (lane == 0) {
-              if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) atomicExch(&P.ctr->aborted, 1u);
-              ab = ld_coherent(&P.ctr->aborted);
-            }
-            if (lane_val(ab, 0)) {
-              abort_now = true;
-              break;
-            }
-            if (P.donate) {
-              // gate: with c idle waves, about 8c of the busy waves try per period
-              const uint32_t c = ld_coherent(&P.idle_rep[(blockIdx.x & (IDLE_REPS - 1)) * IDLE_STRIDE]);
-              if (c != 0 && c < 0x80000000u) {
-                const uint32_t roll = (uint32_t)gm_mix64(((uint64_t)slot << 32) ^ now) & 1023u;
-                if (roll < (c >= 128 ? 1024u : c * 8u)) try_donate(l);
-              }
-            }
+          if (poll(l)) {
+            abort_now = true;
+            break;
           }
           const uint32_t cur = uni(S.cur[l]);
           if (cur >= uni(S.len[l])) {
@@ -889,12 +1032,19 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           uint32_t c, eidx;
           bool ok;
           m = eval_chunk(l, cur, c, eidx, ok);
-          if (l == pf_lvl) {
-            if (m) prefetch_leaf(l, eidx, c, ok);
-            pf_ok = true;
-          }
-          TALLY(2, CYCLES() - t_ev);
           S.mask[l] = m;
+          TALLY(2, CYCLES() - t_ev);
+          if (l == pf_lvl) {
+            pf_ok = true;
+            if (m) {
+              const uint32_t my_len = prefetch_leaf(l, eidx, c, ok);
+              const uint64_t t_pk = CYCLES();
+              leaf_packed(l, m, my_len);
+              TALLY(3, CYCLES() - t_pk);
+              if (abort_now) break;
+              m = uni64(S.mask[l]);
+            }
+          }
           if (m == 0) continue;
         }
         const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/gamma.h"
+#include "ctx_access.h"
 #include "dev_common.h"
 #include "host_plan.h"
 #include "kernels.h"
@@ -921,6 +922,18 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     return out->n_tuples < out->n_tuples_found ? GAMMA_TRUNCATED : GAMMA_OK;
   });
 }
+
+}  // extern "C"
+
+namespace gm {
+bool ctx_has_graph(const gamma_ctx* c, uint32_t* n) {
+  if (!c || !c->has_graph) return false;
+  if (n) *n = c->n;
+  return true;
+}
+}  // namespace gm
+
+extern "C" {
 
 gamma_status gamma_get_tuning(const gamma_ctx* c, gamma_tuning* out) {
   if (!c || !out) return GAMMA_EINVAL;

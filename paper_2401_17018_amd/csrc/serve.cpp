@@ -1,0 +1,250 @@
+// Served update stream with continuous batching.
+//
+// The paper keeps host-side preparation of the next batch off the critical
+// path of the GPU search (its asynchronous pipeline, Sec. IV-A).  Here a
+// server owns one worker thread per context.  Callers submit update
+// requests from any thread; the worker turns the queue into device batches:
+// each batch takes queued requests in submission order while they fit the
+// admission limit, and closes before a request that would insert an edge
+// some request of the batch deletes (or delete one it inserts), because
+// such a pair must be applied in order.  Duplicates across requests
+// collapse as they would in sequence, so after every batch the graph equals
+// the graph that applying its requests one by one would give, and the
+// batch's net result (|+| - |-| per query) equals the sum of theirs.
+// Batches are applied and committed in order; a request completes when its
+// batch is committed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gamma.h"
+#include "ctx_access.h"
+
+namespace {
+
+struct Request {
+  uint64_t ticket;
+  double t_submit;
+  std::vector<uint32_t> src, dst;
+  std::vector<uint8_t> op;
+};
+
+struct BatchRecord {
+  gamma_serve_batch info;
+  std::vector<gamma_query_result> q;
+};
+
+}  // namespace
+
+struct gamma_server {
+  gamma_ctx* ctx = nullptr;
+  gamma_serve_options opt{};
+  uint32_t n = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request> queue;
+  std::deque<gamma_request_result> done;  // completed, not yet polled (ticket order)
+  std::vector<BatchRecord> batches;
+  uint64_t next_ticket = 0, n_committed = 0;
+  bool stop = false;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  void run() {
+    std::vector<uint32_t> src, dst;
+    std::vector<uint8_t> op;
+    std::unordered_map<uint64_t, uint8_t> seen;
+    for (;;) {
+      std::vector<Request> take;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        if (queue.empty()) break;  // stop requested and nothing left
+        // admission, in submission order
+        size_t nupd = 0;
+        seen.clear();
+        while (!queue.empty()) {
+          Request& r = queue.front();
+          if (!take.empty()) {
+            if (opt.coalesce == 2 || nupd + r.op.size() > opt.max_batch_updates) break;
+            bool conflict = false;
+            for (size_t i = 0; i < r.op.size() && !conflict; ++i) {
+              const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
+              auto it = seen.find((a << 32) | b);
+              conflict = it != seen.end() && it->second != (r.op[i] ? 1 : 0);
+            }
+            if (conflict) break;
+          }
+          for (size_t i = 0; i < r.op.size(); ++i) {
+            const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
+            seen[(a << 32) | b] = r.op[i] ? 1 : 0;
+          }
+          nupd += r.op.size();
+          take.push_back(std::move(r));
+          queue.pop_front();
+        }
+      }
+      // merge the admitted requests into one batch and apply it
+      src.clear();
+      dst.clear();
+      op.clear();
+      for (auto& r : take) {
+        src.insert(src.end(), r.src.begin(), r.src.end());
+        dst.insert(dst.end(), r.dst.begin(), r.dst.end());
+        op.insert(op.end(), r.op.begin(), r.op.end());
+      }
+      const double t_start = now_ms();
+      gamma_batch_result res;
+      std::memset(&res, 0, sizeof(res));
+      const gamma_status st = gamma_apply_batch(ctx, (uint32_t)op.size(), src.data(), dst.data(), op.data(),
+                                                GAMMA_MEM_HOST, opt.flags, &res);
+      const double t_done = now_ms();
+      BatchRecord rec;
+      std::memset(&rec.info, 0, sizeof(rec.info));
+      rec.info.first_ticket = take.front().ticket;
+      rec.info.n_requests = (uint32_t)take.size();
+      rec.info.n_updates = (uint32_t)op.size();
+      rec.info.status = st;
+      rec.info.t_start_ms = t_start;
+      rec.info.t_done_ms = t_done;
+      if (st >= 0) {
+        rec.info.n_canonical = res.n_canonical;
+        rec.info.ms_device = res.stats.ms_total;
+        rec.q.assign(res.queries, res.queries + res.n_queries);
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      rec.info.batch = batches.size();
+      for (auto& r : take) {
+        gamma_request_result d;
+        std::memset(&d, 0, sizeof(d));
+        d.ticket = r.ticket;
+        d.batch = rec.info.batch;
+        d.t_submit_ms = r.t_submit;
+        d.t_done_ms = t_done;
+        d.n_updates = (uint32_t)r.op.size();
+        d.status = st;
+        done.push_back(d);
+      }
+      batches.push_back(std::move(rec));
+      n_committed += take.size();
+      cv_done.notify_all();
+    }
+  }
+};
+
+extern "C" {
+
+gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, gamma_server** out) {
+  if (!ctx || !out) return GAMMA_EINVAL;
+  *out = nullptr;
+  gamma_serve_options o{};
+  if (opt) o = *opt;
+  if (o.max_batch_updates == 0) o.max_batch_updates = 1u << 17;
+  if (o.coalesce == 0) o.coalesce = 1;
+  if (o.max_batch_updates > (1u << 20) || (o.coalesce != 1 && o.coalesce != 2) ||
+      (o.flags & (GAMMA_F_TUPLES | GAMMA_F_DRY_RUN | GAMMA_F_CANONICAL)))
+    return GAMMA_EINVAL;
+  uint32_t n = 0;
+  if (!gm::ctx_has_graph(ctx, &n)) return GAMMA_ESTATE;
+  gamma_server* s = new (std::nothrow) gamma_server();
+  if (!s) return GAMMA_ENOMEM;
+  s->ctx = ctx;
+  s->opt = o;
+  s->n = n;
+  s->t0 = std::chrono::steady_clock::now();
+  try {
+    s->worker = std::thread([s] { s->run(); });
+  } catch (...) {
+    delete s;
+    return GAMMA_ENOMEM;
+  }
+  *out = s;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_submit(gamma_server* s, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                const uint8_t* op, uint64_t* ticket) {
+  if (!s) return GAMMA_EINVAL;
+  if (n_upd == 0 || n_upd > s->opt.max_batch_updates) return GAMMA_EINVAL;
+  const gamma_status v = gamma_validate_batch(s->n, n_upd, src, dst, op);
+  if (v != GAMMA_OK) return v;
+  Request r;
+  r.src.assign(src, src + n_upd);
+  r.dst.assign(dst, dst + n_upd);
+  r.op.assign(op, op + n_upd);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return GAMMA_ESTATE;
+  r.ticket = s->next_ticket++;
+  r.t_submit = s->now_ms();
+  if (ticket) *ticket = r.ticket;
+  s->queue.push_back(std::move(r));
+  s->cv_work.notify_one();
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_poll(gamma_server* s, gamma_request_result* out, uint32_t max, uint32_t* n_out) {
+  if (!s || !n_out || (max && !out)) return GAMMA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  uint32_t k = 0;
+  while (k < max && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n_out = k;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_drain(gamma_server* s) {
+  if (!s) return GAMMA_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->n_committed == s->next_ticket; });
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_counts(gamma_server* s, uint64_t* submitted, uint64_t* committed, uint64_t* batches) {
+  if (!s) return GAMMA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (submitted) *submitted = s->next_ticket;
+  if (committed) *committed = s->n_committed;
+  if (batches) *batches = s->batches.size();
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_get_batch(gamma_server* s, uint64_t batch, gamma_serve_batch* info,
+                                   gamma_query_result* queries, uint32_t max_queries) {
+  if (!s || !info) return GAMMA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batch >= s->batches.size()) return GAMMA_EINVAL;
+  const BatchRecord& r = s->batches[batch];
+  *info = r.info;
+  info->n_queries = (uint32_t)r.q.size();
+  if (queries)
+    for (uint32_t i = 0; i < std::min<uint32_t>(max_queries, (uint32_t)r.q.size()); ++i) queries[i] = r.q[i];
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_destroy(gamma_server* s) {
+  if (!s) return GAMMA_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  delete s;
+  return GAMMA_OK;
+}
+
+}  // extern "C"

@@ -54,6 +54,11 @@ def test_create_without_gpu_fails_cleanly(lib):
     assert lib.gamma_get_tuning(None, ctypes.byref(t)) == capi.GAMMA_EINVAL
     assert lib.gamma_set_tuning(None, ctypes.byref(t)) == capi.GAMMA_EINVAL
     assert lib.gamma_autotune(None, 0, None, None, None, 0, 0, 8, 1, ctypes.byref(t), None, None) == capi.GAMMA_EINVAL
+    srv = ctypes.c_void_p()
+    assert lib.gamma_serve_create(None, None, ctypes.byref(srv)) == capi.GAMMA_EINVAL and not srv.value
+    assert lib.gamma_serve_submit(None, 0, None, None, None, None) == capi.GAMMA_EINVAL
+    assert lib.gamma_serve_drain(None) == capi.GAMMA_EINVAL
+    assert lib.gamma_serve_destroy(None) == capi.GAMMA_OK
 
 
 def test_validate_graph(lib):

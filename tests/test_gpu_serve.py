@@ -1,0 +1,198 @@
+"""GPU: the served update stream (continuous batching).
+
+Isolation, with zero tolerance: every device batch the server forms gives
+exactly what the plain path and the oracle give for the same merged batch
+on the same graph; its net count per query equals the sum of its
+requests' net counts applied one at a time; the final graph equals the
+one sequential application gives; every request is committed once, in
+submission order."""
+import threading
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import plain as O2
+from paper_2401_17018_amd import GammaError, Server, capi
+from test_gpu_parity import _er, make_ctx
+from test_gpu_tuning import _queries
+
+pytestmark = pytest.mark.gpu
+
+
+def _request_stream(g, seed, n_req, max_size):
+    """Requests valid in sequence: each inserts absent edges or deletes
+    present ones of the graph as it stands after the previous requests, so
+    later requests often undo earlier ones (cross-request conflicts) or
+    repeat them (duplicates)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    present = set(g.edge_keys().tolist())
+    touched = []
+    reqs = []
+    for _ in range(n_req):
+        size = int(rng.integers(1, max_size + 1))
+        src, dst, op, keys = [], [], [], set()
+        while len(op) < size:
+            if touched and rng.random() < 0.3:
+                key = touched[int(rng.integers(0, len(touched)))]  # revisit an edge touched before
+            else:
+                u, v = (int(x) for x in rng.integers(0, g.n, 2))
+                if u == v:
+                    continue
+                key = (min(u, v) << 32) | max(u, v)
+            if key in keys:
+                continue
+            keys.add(key)
+            a, b = key >> 32, key & 0xFFFFFFFF
+            if rng.random() < 0.5:
+                a, b = b, a
+            src.append(a)
+            dst.append(b)
+            op.append(0 if key in present else 1)
+        for a, b, o in zip(src, dst, op):
+            key = (min(a, b) << 32) | max(a, b)
+            if o:
+                present.add(key)
+            else:
+                present.discard(key)
+            touched.append(key)
+        reqs.append((np.array(src, np.uint32), np.array(dst, np.uint32), np.array(op, np.uint8)))
+    return reqs
+
+
+def _setup(ctx, g, qs):
+    ctx.load_graph(g.row_ptr, g.col, g.labels)
+    for q in qs:
+        ctx.register_query(q.k, q.labels, q.edges)
+
+
+def _graph(ctx, labels):
+    rp, col, lab = ctx.export_graph()
+    return W.Graph(len(lab), rp, col, lab)
+
+
+@pytest.mark.parametrize("seed,max_size", [(1, 40), (2, 300)])
+def test_served_stream_isolation(seed, max_size):
+    g = _er(1200, 7000, 30 + seed, 3)
+    qs = _queries(seed, [3, 4, 5])
+    reqs = _request_stream(g, seed, 48, max_size)
+    with make_ctx(cap=0) as ctx:
+        _setup(ctx, g, qs)
+        with Server(ctx, max_batch_updates=2 * max_size) as srv:
+            tickets = [srv.submit(*r) for r in reqs]
+            srv.drain()
+            done = srv.poll(4096)
+            n_sub, n_com, n_bat = srv.counts()
+            batches = [srv.batch(i) for i in range(n_bat)]
+        served_final = _graph(ctx, g.labels)
+    assert tickets == list(range(len(reqs))) and n_sub == n_com == len(reqs)
+    assert [d["ticket"] for d in done] == tickets
+    assert all(d["status"] == 0 for d in done)
+    # batches cover the requests in order, each exactly once
+    nxt = 0
+    for b in batches:
+        assert b["first_ticket"] == nxt and b["status"] == 0
+        nxt += b["n_requests"]
+    assert nxt == len(reqs)
+    assert len(batches) < len(reqs)  # requests were coalesced
+    # replay: each batch on the plain path, checked against the oracle; each
+    # request alone on a third context for the net counts
+    with make_ctx(cap=0) as plain, make_ctx(cap=0) as single:
+        _setup(plain, g, qs)
+        _setup(single, g, qs)
+        for b in batches:
+            rs = reqs[b["first_ticket"]:b["first_ticket"] + b["n_requests"]]
+            merged = W.Batch(np.concatenate([r[0] for r in rs]), np.concatenate([r[1] for r in rs]),
+                             np.concatenate([r[2] for r in rs]))
+            before = _graph(plain, g.labels)
+            res = plain.apply_batch(merged.src, merged.dst, merged.op, hash=True)
+            assert np.array_equal(res.counts, b["counts"])
+            assert np.array_equal(res.hash_sum, b["hash_sum"]) and np.array_equal(res.hash_xor, b["hash_xor"])
+            for qid, q in enumerate(qs):
+                ref = O2.run(before, q, merged, qid=qid, threads=4, want_tuples=False)
+                assert [int(res.counts[qid, 0]), int(res.counts[qid, 1])] == [ref.count[0], ref.count[1]]
+                assert int(res.hash_sum[qid, 1]) == ref.hsum[1] and int(res.hash_xor[qid, 0]) == ref.hxor[0]
+            net = np.zeros(len(qs), np.int64)
+            for r in rs:
+                o = single.apply_batch(r[0], r[1], r[2], hash=False)
+                net += o.counts[:, 1].astype(np.int64) - o.counts[:, 0].astype(np.int64)
+            assert np.array_equal(net, b["counts"][:, 1].astype(np.int64) - b["counts"][:, 0].astype(np.int64))
+        plain_final = _graph(plain, g.labels)
+        single_final = _graph(single, g.labels)
+    for other in (plain_final, single_final):
+        assert np.array_equal(served_final.row_ptr, other.row_ptr) and np.array_equal(served_final.col, other.col)
+
+
+def test_one_request_per_batch_and_validation():
+    g = _er(600, 3000, 41, 2)
+    qs = _queries(7, [3, 4], n_labels=2)
+    reqs = _request_stream(g, 9, 12, 30)
+    with make_ctx(cap=0) as ctx:
+        _setup(ctx, g, qs)
+        with Server(ctx, coalesce=False) as srv:
+            with pytest.raises(GammaError) as ei:
+                srv.submit(np.array([3], np.uint32), np.array([3], np.uint32), np.array([1], np.uint8))
+            assert ei.value.status == capi.GAMMA_EINVAL
+            with pytest.raises(GammaError) as ei:
+                srv.submit(np.array([1, 2], np.uint32), np.array([2, 1], np.uint32), np.array([1, 0], np.uint8))
+            assert ei.value.status == capi.GAMMA_ECONFLICT
+            for r in reqs:
+                srv.submit(*r)
+            srv.drain()
+            n_sub, n_com, n_bat = srv.counts()
+            batches = [srv.batch(i) for i in range(n_bat)]
+    assert n_sub == n_com == n_bat == len(reqs)
+    with make_ctx(cap=0) as single:
+        _setup(single, g, qs)
+        for b, r in zip(batches, reqs):
+            o = single.apply_batch(r[0], r[1], r[2], hash=True)
+            assert np.array_equal(o.counts, b["counts"]) and np.array_equal(o.hash_sum, b["hash_sum"])
+
+
+def test_concurrent_submitters():
+    g = _er(1000, 6000, 43, 3)
+    qs = _queries(11, [3, 4])
+    # four threads, each its own edges (disjoint vertex ranges), so any
+    # interleaving is valid
+    def stream(part):
+        rng = np.random.Generator(np.random.PCG64(100 + part))
+        lo = part * 250
+        out = []
+        present = set(g.edge_keys().tolist())
+        for _ in range(10):
+            n = int(rng.integers(1, 50))
+            keys = set()
+            while len(keys) < n:
+                u, v = (int(x) for x in rng.integers(lo, lo + 250, 2))
+                if u != v:
+                    keys.add((min(u, v) << 32) | max(u, v))
+            ks = sorted(keys)
+            src = np.array([k >> 32 for k in ks], np.uint32)
+            dst = np.array([k & 0xFFFFFFFF for k in ks], np.uint32)
+            op = np.array([0 if k in present else 1 for k in ks], np.uint8)
+            for k, o in zip(ks, op):
+                (present.add if o else present.discard)(k)
+            out.append((src, dst, op))
+        return out
+    parts = [stream(p) for p in range(4)]
+    with make_ctx(cap=0) as ctx:
+        _setup(ctx, g, qs)
+        with Server(ctx, max_batch_updates=500) as srv:
+            ts = [threading.Thread(target=lambda rs=rs: [srv.submit(*r) for r in rs]) for rs in parts]
+            for t in ts:
+                t.start()
+            for t in ts:
+                t.join()
+            srv.drain()
+            done = srv.poll(4096)
+            n_sub, n_com, n_bat = srv.counts()
+        final = _graph(ctx, g.labels)
+    assert n_sub == n_com == 40 and [d["ticket"] for d in done] == list(range(40))
+    # the final graph: the four disjoint streams applied in any order
+    with make_ctx(cap=0) as single:
+        _setup(single, g, qs)
+        for rs in parts:
+            for r in rs:
+                single.apply_batch(r[0], r[1], r[2])
+        ref = _graph(single, g.labels)
+    assert np.array_equal(final.row_ptr, ref.row_ptr) and np.array_equal(final.col, ref.col)

@@ -579,6 +579,54 @@ def large(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
 BATCHED_QUERY_MIN_LABEL = 8  # Zipf(1.2) over 16 labels: each label >= 8 covers <= 2.6% of vertices
 
 
+def _batched_spec(seed: int, n_queries: int):
+    d = Draws(sub_seed(seed, TAG_QUERY + 1000), TAG_QUERY)
+    spec = []
+    for i in range(n_queries):
+        k = 4 + d.below(9)
+        spec.append((4 + (k - 4) % 5, "sparse") if i % 2 == 0 else (k, "dense"))
+    return spec
+
+
+def served_stream(seed: int = 0, n_requests: int = 200, n_queries: int = 32, size_lo: int = 100,
+                  size_hi: int = 10000, ins_frac: float = 0.85, threads: int = 0) -> Workload:
+    """A request stream for the served path: the mid graph, the first
+    n_queries standing queries of batched_queries(), and n_requests update
+    requests valid in sequence, of log-uniform size in [size_lo, size_hi]
+    with ins_frac insertions (held-out edges) and the rest deletions of
+    present edges.  meta["gaps"] holds unit-mean exponential inter-arrival
+    gaps (a Poisson process once scaled to the offered load)."""
+    d = Draws(sub_seed(seed, TAG_STREAM + 11), TAG_STREAM)
+    lo, hi = math.log10(size_lo), math.log10(size_hi)
+    u = d.block(n_requests).astype(np.float64) / 2.0 ** 64
+    sizes = np.floor(10.0 ** (lo + u * (hi - lo))).astype(np.int64)
+    n_ins = np.rint(sizes * ins_frac).astype(np.int64)
+    n_del = sizes - n_ins
+    gaps = -np.log1p(-d.block(n_requests).astype(np.float64) / 2.0 ** 64)
+    g, pl, ph = rmat_graph_with_pool(20, 8 << 20, int(n_ins.sum()), 16, 1.2, seed, threads=threads,
+                                     name="served-rmat20")
+    pool = keys_of(pl, ph)
+    ins0 = pool[: int(n_ins[0])]
+    queries, protect = [], set()
+    for qi, (k, kind) in enumerate(_batched_spec(seed, n_queries)):
+        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)),
+                          min_label=BATCHED_QUERY_MIN_LABEL)
+        queries.append(q)
+        for (x, y) in q.edges.tolist():
+            a, b = q.planted[x], q.planted[y]
+            protect.add((min(a, b) << 32) | max(a, b))
+    shadow = EdgeShadow(g)
+    bd = Draws(sub_seed(seed, TAG_BATCH + 11), TAG_BATCH)
+    reqs, at = [], 0
+    for i in range(n_requests):
+        ins = pool[at:at + int(n_ins[i])]
+        at += int(n_ins[i])
+        dels = shadow.sample_deletions(int(n_del[i]), bd, protect) if n_del[i] else np.zeros(0, np.uint64)
+        shadow.add(ins)
+        reqs.append(make_batch(ins, dels, bd))
+    return Workload("served-rmat20", g, queries, reqs, {"seed": seed, "gaps": gaps, "sizes": sizes})
+
+
 def batched_queries(seed: int = 0, n_batches: int = 1, n_queries: int = 64, threads: int = 0,
                     query_min_label: int = BATCHED_QUERY_MIN_LABEL) -> Workload:
     """The mid graph with 64 standing queries (even ids sparse with 4..8
@@ -588,11 +636,7 @@ def batched_queries(seed: int = 0, n_batches: int = 1, n_queries: int = 64, thre
     Sparse queries (a walk tree plus one cycle edge) of 9..12 vertices have
     more than 10^10 incremental matches per batch on this graph, so their
     size stops at 8."""
-    d = Draws(sub_seed(seed, TAG_QUERY + 1000), TAG_QUERY)
-    spec = []
-    for i in range(n_queries):
-        k = 4 + d.below(9)
-        spec.append((4 + (k - 4) % 5, "sparse") if i % 2 == 0 else (k, "dense"))
+    spec = _batched_spec(seed, n_queries)
     return rmat_stream(20, 8 << 20, 16, 1.2, 8000, 2000, n_batches, spec, seed,
                        pool_batches=max(64, n_batches), name="batched-rmat20", threads=threads,
                        query_min_label=query_min_label)
