@@ -67,8 +67,8 @@ typedef struct gamma_options {
   int32_t device;            /* HIP device ordinal */
   void* stream;              /* hipStream_t to run on; NULL = library-created stream */
   uint64_t tuple_capacity;   /* max tuple records stored per batch (0 = no tuple buffer) */
-  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 16, of which as many
-                                as the kernel's register use allows are resident) */
+  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 12; more than the
+                                kernel's register use lets reside add nothing) */
   uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
   uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
   uint32_t deadline_ms;      /* search deadline per batch (0 = none); past it the batch
@@ -97,7 +97,9 @@ typedef struct gamma_tuning {
   uint32_t split_inner;   /* smallest inner-level candidate range handed over, 2..2^20 */
   uint32_t split_leaf;    /* smallest last-level candidate range handed over, 2..2^20 */
   uint32_t query_launch;  /* 1 = every query's seeds in one search launch, 2 = one launch per query */
-  uint32_t reserved[2];
+  uint32_t handover_gate; /* with c idle waves a busy wave tries a hand-over per poll with
+                             probability min(1, c * handover_gate / 1024), 1..1024 */
+  uint32_t reserved[1];
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),
@@ -232,7 +234,7 @@ gamma_status gamma_set_tuning(gamma_ctx* ctx, const gamma_tuning* in);
  * Every evaluation is a dry run (GAMMA_F_DRY_RUN with `flags`) of the batch,
  * timed as the median device time of `reps` runs (1..9).  Coordinate
  * search from the current tunables over query_launch, steal, waves_per_cu,
- * poll_cycles, split_leaf and split_inner, at most max_points evaluations
+ * handover_gate, poll_cycles, split_leaf and split_inner, at most max_points evaluations
  * (1..64).  The fastest point is applied and written to *best; *best_ms and
  * *base_ms (may be NULL) receive its time and the starting point's.  The
  * graph is unchanged.  Errors: those of gamma_apply_batch (ETIMEDOUT from a

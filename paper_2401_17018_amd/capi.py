@@ -53,10 +53,11 @@ class Tuning(ctypes.Structure):
         ("split_inner", ctypes.c_uint32),
         ("split_leaf", ctypes.c_uint32),
         ("query_launch", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 2),
+        ("handover_gate", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 1),
     ]
 
-    FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch")
+    FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch", "handover_gate")
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in self.FIELDS}

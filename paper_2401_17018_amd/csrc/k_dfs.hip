@@ -876,11 +876,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       if (lane_val(ab, 0)) return true;
       if (P.donate) {
-        // gate: with c idle waves, about 8c of the busy waves try per period
+        // gate: with c idle waves, a busy wave tries with probability
+        // min(1, c * gate / 1024), so about c * gate / 1024 of them per period
         const uint32_t c = ld_coherent(&P.idle_rep[(blockIdx.x & (IDLE_REPS - 1)) * IDLE_STRIDE]);
         if (c != 0 && c < 0x80000000u) {
           const uint32_t roll = (uint32_t)gm_mix64(((uint64_t)slot << 32) ^ now) & 1023u;
-          if (roll < (c >= 128 ? 1024u : c * 8u)) try_donate(lcur);
+          if (roll < (c >= 1024u / P.gate ? 1024u : c * P.gate)) try_donate(lcur);
         }
       }
       return false;

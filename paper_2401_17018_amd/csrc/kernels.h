@@ -77,7 +77,7 @@ struct GmDfsParams {
   uint32_t poll_cycles;           // shader cycles between a busy wave's hand-over polls
   uint32_t split_inner;           // smallest inner-level range worth handing over
   uint32_t split_leaf;            // smallest last-level range worth handing over
-  uint32_t pad2;
+  uint32_t gate;                  // hand-over attempt probability per idle wave, in 1/1024
 };
 
 namespace gm {

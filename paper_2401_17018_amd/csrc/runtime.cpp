@@ -385,12 +385,16 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
       delete c;
       return GAMMA_EDEVICE;
     }
-  c->tun.waves_per_cu = c->opt.waves_per_cu ? std::min<uint32_t>(c->opt.waves_per_cu, 32) : 16;
+  // defaults from a sweep on the mid workload: 12 waves per CU (all of them
+  // resident at the kernel's register use), few hand-over attempts per idle
+  // wave (contending donors cost more than they save), a 10 us poll
+  c->tun.waves_per_cu = c->opt.waves_per_cu ? std::min<uint32_t>(c->opt.waves_per_cu, 32) : 12;
   c->tun.steal = (c->opt.steal_set && !c->opt.steal) ? 2 : 1;
-  c->tun.poll_cycles = 6000;  // ~2.5 us at 2.4 GHz
+  c->tun.poll_cycles = 24000;  // ~10 us at 2.4 GHz
   c->tun.split_inner = 128;
   c->tun.split_leaf = 512;
   c->tun.query_launch = 1;
+  c->tun.handover_gate = 2;
   *out = c;
   return GAMMA_OK;
 }
@@ -774,7 +778,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.poll_cycles = C.tun.poll_cycles;
       P.split_inner = C.tun.split_inner;
       P.split_leaf = C.tun.split_leaf;
-      P.pad2 = 0;
+      P.gate = C.tun.handover_gate;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
@@ -946,7 +950,7 @@ bool tuning_ok(const gamma_tuning& t) {
   return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && (t.steal == 1 || t.steal == 2) &&
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
-         (t.query_launch == 1 || t.query_launch == 2);
+         (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024;
 }
 }  // namespace
 
@@ -959,6 +963,7 @@ gamma_status gamma_set_tuning(gamma_ctx* c, const gamma_tuning* in) {
   if (in->split_inner) t.split_inner = in->split_inner;
   if (in->split_leaf) t.split_leaf = in->split_leaf;
   if (in->query_launch) t.query_launch = in->query_launch;
+  if (in->handover_gate) t.handover_gate = in->handover_gate;
   if (!tuning_ok(t)) return fail(c, GAMMA_EINVAL, "set_tuning: value out of range");
   c->tun = t;
   return GAMMA_OK;
@@ -974,7 +979,8 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
   std::vector<std::pair<gamma_tuning, double>> seen;
   auto same = [](const gamma_tuning& a, const gamma_tuning& b) {
     return a.waves_per_cu == b.waves_per_cu && a.steal == b.steal && a.poll_cycles == b.poll_cycles &&
-           a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch;
+           a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch &&
+           a.handover_gate == b.handover_gate;
   };
   gamma_status err = GAMMA_OK;
   // median device time of `reps` dry runs at tuning t (< 0: failed)
@@ -1010,6 +1016,7 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
   const uint32_t poll_v[] = {1500, 3000, 6000, 12000, 24000};
   const uint32_t leaf_v[] = {128, 256, 512, 1024, 2048};
   const uint32_t inner_v[] = {64, 128, 256, 512};
+  const uint32_t gate_v[] = {1, 2, 4, 8, 16};
   const bool many_q = c->queries.size() > 1;
   for (int pass = 0; pass < 3; ++pass) {
     bool moved = false;
@@ -1032,6 +1039,7 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
     sweep(&gamma_tuning::steal, steal_v, 2);
     sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);
     if (cur.steal == 1) {
+      sweep(&gamma_tuning::handover_gate, gate_v, 5);
       sweep(&gamma_tuning::poll_cycles, poll_v, 5);
       sweep(&gamma_tuning::split_leaf, leaf_v, 5);
       sweep(&gamma_tuning::split_inner, inner_v, 4);

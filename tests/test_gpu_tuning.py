@@ -76,10 +76,10 @@ def test_per_query_launches_identical():
 
 
 TUNINGS = [
-    dict(waves_per_cu=4, steal=1, poll_cycles=500, split_inner=2, split_leaf=2),  # hand over almost anything
+    dict(waves_per_cu=4, steal=1, poll_cycles=500, split_inner=2, split_leaf=2, handover_gate=1024),  # hand over almost anything
     dict(waves_per_cu=32, steal=1, poll_cycles=1000000, split_inner=1 << 20, split_leaf=1 << 20),
     dict(waves_per_cu=12, steal=2),
-    dict(waves_per_cu=1, steal=1, poll_cycles=3000),
+    dict(waves_per_cu=1, steal=1, poll_cycles=3000, handover_gate=1),
 ]
 
 
@@ -106,7 +106,7 @@ def test_set_tuning_rejects_out_of_range():
     with make_ctx(cap=0) as ctx:
         before = ctx.get_tuning()
         for bad in (dict(split_inner=1), dict(waves_per_cu=33), dict(steal=3), dict(query_launch=7),
-                    dict(poll_cycles=10)):
+                    dict(poll_cycles=10), dict(handover_gate=2000)):
             with pytest.raises(GammaError) as ei:
                 ctx.set_tuning(**bad)
             assert ei.value.status == capi.GAMMA_EINVAL
