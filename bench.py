@@ -66,7 +66,8 @@ def percentile(xs, p):
 
 def cpu_baseline(w, queries, budget_s: float = 20.0):
     """Time the oracle on a deterministic 1-in-M sample of the first batch's
-    seeds (by canonical ord), shrinking M until the run takes a few seconds."""
+    seeds (by canonical ord), shrinking M until the run takes a few seconds
+    and has found matches (or the time budget is spent)."""
     from oracle import plain as O2
     threads = min(os.cpu_count() or 1, 16)
     g, b = w.graph, w.batches[0]
@@ -82,7 +83,9 @@ def cpu_baseline(w, queries, budget_s: float = 20.0):
             n_seeds = len(range(0, r.n_canonical, M))
         spent += tot_s
         best = (tot_matches, tot_s, M, n_seeds)
-        if tot_s >= budget_s / 4 or M == 1 or spent + 4 * tot_s > budget_s * 1.5:
+        if M == 1 or spent + 4 * tot_s > budget_s * 2:
+            break
+        if tot_matches > 0 and tot_s >= budget_s / 4:
             break
         M //= 4
     matches, secs, M, n_seeds = best
