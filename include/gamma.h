@@ -99,7 +99,10 @@ typedef struct gamma_tuning {
   uint32_t query_launch;  /* 1 = every query's seeds in one search launch, 2 = one launch per query */
   uint32_t handover_gate; /* with c idle waves a busy wave tries a hand-over per poll with
                              probability min(1, c * handover_gate / 1024), 1..1024 */
-  uint32_t reserved[1];
+  uint32_t coalesced_search; /* 2 = on (default): directed query edges that a label-preserving
+                                automorphism of the query maps onto each other are searched
+                                once and the other matches are produced by permuting the
+                                found ones (Sec. V-B); 1 = off */
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),
@@ -233,7 +236,7 @@ gamma_status gamma_set_tuning(gamma_ctx* ctx, const gamma_tuning* in);
 /* Tune the search for the current graph and queries on a calibration batch.
  * Every evaluation is a dry run (GAMMA_F_DRY_RUN with `flags`) of the batch,
  * timed as the median device time of `reps` runs (1..9).  Coordinate
- * search from the current tunables over query_launch, steal, waves_per_cu,
+ * search from the current tunables over query_launch, coalesced_search, steal, waves_per_cu,
  * handover_gate, poll_cycles, split_leaf and split_inner, at most max_points evaluations
  * (1..64).  The fastest point is applied and written to *best; *best_ms and
  * *base_ms (may be NULL) receive its time and the starting point's.  The

@@ -54,10 +54,11 @@ class Tuning(ctypes.Structure):
         ("split_leaf", ctypes.c_uint32),
         ("query_launch", ctypes.c_uint32),
         ("handover_gate", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 1),
+        ("coalesced_search", ctypes.c_uint32),
     ]
 
-    FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch", "handover_gate")
+    FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch", "handover_gate",
+              "coalesced_search")
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in self.FIELDS}

@@ -38,6 +38,21 @@ struct alignas(16) GmPlan {
   uint32_t pos[GM_MAX_K];   // pos[u] = level at which query vertex u is matched
   uint32_t bofs[GM_MAX_K];  // first slot of level l's neighbour-list records
   uint32_t lslot[GM_MAX_K]; // label-index slot of order[l]'s label
+  // Coalesced search (Sec. V-B): with it on, only representative plans are
+  // seeded (n_perm >= 1); every match f found from one stands for the
+  // matches f o pi of the perms [perm_base, perm_base + n_perm) (the first
+  // is the identity).  n_perm = 0: a plan other plans stand for.
+  uint32_t n_perm;
+  uint32_t perm_base;
+};
+
+#define GM_MAX_PERM 16
+
+// A label-preserving automorphism pi of a query, as its forward map and its
+// inverse (query vertex -> query vertex).
+struct GmPerm {
+  uint32_t fwd[GM_MAX_K];
+  uint32_t inv[GM_MAX_K];
 };
 
 // Per query: plan range and size.

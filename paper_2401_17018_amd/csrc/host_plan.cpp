@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <set>
 
@@ -134,6 +135,101 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
       placed |= 1u << u;
     }
     q.plans.push_back(p);
+  }
+  coalesce_query(q);
+}
+
+namespace {
+
+// Label-preserving automorphisms of q (sigma[i] = image of query vertex i),
+// by backtracking: an image must agree in label and degree with the vertex
+// and in adjacency to every vertex mapped before it.  Stops after `cap`.
+void automorphisms(const HostQuery& q, size_t cap, std::vector<std::vector<uint32_t>>& out) {
+  const uint32_t k = q.k;
+  std::vector<uint32_t> adj(k, 0), deg(k, 0), m(k, 0);
+  for (auto& e : q.edges) {
+    adj[e.first] |= 1u << e.second;
+    adj[e.second] |= 1u << e.first;
+  }
+  for (uint32_t u = 0; u < k; ++u) deg[u] = (uint32_t)__builtin_popcount(adj[u]);
+  uint32_t used = 0;
+  std::function<bool(uint32_t)> extend = [&](uint32_t i) -> bool {
+    if (i == k) {
+      out.push_back(m);
+      return out.size() < cap;
+    }
+    for (uint32_t c = 0; c < k; ++c) {
+      if (((used >> c) & 1u) || q.labels[c] != q.labels[i] || deg[c] != deg[i]) continue;
+      bool ok = true;
+      for (uint32_t j = 0; j < i && ok; ++j) ok = ((adj[i] >> j) & 1u) == ((adj[c] >> m[j]) & 1u);
+      if (!ok) continue;
+      m[i] = c;
+      used |= 1u << c;
+      const bool more = extend(i + 1);
+      used &= ~(1u << c);
+      if (!more) return false;
+    }
+    return true;
+  };
+  extend(0);
+}
+
+}  // namespace
+
+void coalesce_query(HostQuery& q) {
+  const uint32_t k = q.k;
+  q.perms.clear();
+  GmPerm id;
+  std::memset(&id, 0, sizeof(id));
+  for (uint32_t i = 0; i < k; ++i) id.fwd[i] = id.inv[i] = i;
+  q.perms.push_back(id);
+  for (auto& p : q.plans) {
+    p.n_perm = 1;  // by default every plan stands for itself
+    p.perm_base = 0;
+  }
+  std::vector<std::vector<uint32_t>> aut;
+  automorphisms(q, 4096, aut);
+  if (aut.size() <= 1) return;
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t> dir;
+  for (uint32_t i = 0; i < q.plans.size(); ++i) dir[{q.plans[i].x, q.plans[i].y}] = i;
+  const uint32_t nd = (uint32_t)q.plans.size();
+  std::vector<char> seen(nd, 0);
+  std::vector<std::vector<uint32_t>> tau(nd);  // tau[d]: automorphism taking the class's first plan to d
+  for (uint32_t d0 = 0; d0 < nd; ++d0) {
+    if (seen[d0]) continue;
+    std::vector<uint32_t> cls{d0};
+    seen[d0] = 1;
+    tau[d0].assign(id.fwd, id.fwd + k);
+    for (size_t h = 0; h < cls.size(); ++h) {
+      const uint32_t a = cls[h];
+      for (auto& s : aut) {
+        const uint32_t b = dir.at({s[q.plans[a].x], s[q.plans[a].y]});
+        if (seen[b]) continue;
+        seen[b] = 1;
+        tau[b].resize(k);
+        for (uint32_t i = 0; i < k; ++i) tau[b][i] = s[tau[a][i]];  // s after tau[a]
+        cls.push_back(b);
+      }
+    }
+    // groups of at most GM_MAX_PERM plans; the first of a group is searched,
+    // pi = tau[r] o tau[m]^-1 takes member m onto the group's first plan r
+    for (size_t g0 = 0; g0 < cls.size(); g0 += GM_MAX_PERM) {
+      const size_t g1 = std::min(cls.size(), g0 + GM_MAX_PERM);
+      const uint32_t r = cls[g0];
+      q.plans[r].n_perm = (uint32_t)(g1 - g0);
+      q.plans[r].perm_base = (uint32_t)q.perms.size();
+      for (size_t j = g0; j < g1; ++j) {
+        const uint32_t mb = cls[j];
+        std::vector<uint32_t> tinv(k);
+        for (uint32_t i = 0; i < k; ++i) tinv[tau[mb][i]] = i;
+        GmPerm pi;
+        std::memset(&pi, 0, sizeof(pi));
+        for (uint32_t i = 0; i < k; ++i) pi.fwd[i] = tau[r][tinv[i]];
+        for (uint32_t i = 0; i < k; ++i) pi.inv[pi.fwd[i]] = i;
+        q.perms.push_back(pi);
+        if (j != g0) q.plans[mb].n_perm = 0;
+      }
+    }
   }
 }
 

@@ -16,6 +16,7 @@ struct HostQuery {
   std::vector<uint32_t> labels;                       // [k]
   std::vector<std::pair<uint32_t, uint32_t>> edges;   // undirected, as given
   std::vector<GmPlan> plans;                          // one per directed edge
+  std::vector<GmPerm> perms;                          // coalesced search, referenced by plans
 };
 
 // Validates a query; on failure returns the status code (EINVAL or
@@ -28,6 +29,12 @@ int validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32
 // the most matched neighbours; ties go to the higher query degree, then to
 // the rarer label (label_count), then to the lower id.
 void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& label_count);
+
+// Coalesced search (Sec. V-B) for automorphisms of the whole query: finds
+// label-preserving automorphisms (up to a cap), groups the directed query
+// edges they map onto each other (groups of at most GM_MAX_PERM), and sets
+// each plan's n_perm / perm_base (perm_base indexes q.perms).
+void coalesce_query(HostQuery& q);
 
 // Candidate-filter tables for all queries over data labels < label_slots:
 // entries per data label (sorted by query), each with its neighbour-label

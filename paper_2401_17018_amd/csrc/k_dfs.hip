@@ -81,6 +81,7 @@ struct WaveState {
   uint32_t drvv[GM_MAX_K]; // data vertex whose row drives level l
   uint32_t oth_n[GM_MAX_K];
   uint64_t hpre;           // checksum salt + element terms of every position but the last vertex
+  uint64_t hpp[GM_MAX_PERM]; // the same for each permutation of a coalesced plan
   uint64_t tally[8];       // idle, init, inner, leaf, hand-over cycles; tasks received; hand-overs; nodes
   uint64_t oth_base[MAX_OTH];
   uint32_t oth_len[MAX_OTH];
@@ -106,6 +107,7 @@ struct WaveState {
 // through the constant address space lets uniform reads use scalar loads.
 typedef const __attribute__((address_space(4))) GmPlan* CPlan;
 typedef const __attribute__((address_space(4))) GmQueryDev* CQuery;
+typedef const __attribute__((address_space(4))) GmPerm* CPerm;
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline uint64_t uni64(uint64_t x) {
@@ -247,16 +249,19 @@ __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
 
 // Emit the matches of one ballot: lane bit set <=> (prefix, u -> cx) is a match.
 // (p2, x2): a prefix position whose external id differs per lane (packed
-// last level), or p2 = 0xFFFFFFFF.
+// last level), or p2 = 0xFFFFFFFF.  pf: for a coalesced plan, the
+// permutation pi whose match f o pi is emitted (tuple position j holds
+// f(pi(j))), and hu = pi^-1(u), the position the candidate's term takes in
+// the checksum (hpre then holds the other positions' terms for pi).
 __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t k, uint32_t u, bool ok,
                             uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q, uint32_t sign,
                             uint32_t ord, int lane, uint64_t lt, uint64_t& bytes, uint32_t p2 = 0xFFFFFFFFu,
-                            uint32_t x2 = 0) {
+                            uint32_t x2 = 0, CPerm pf = nullptr, uint32_t hu = 0xFFFFFFFFu) {
   if (ok) A.cnt += 1;
   uint64_t h = 0;
   if (P.flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
     if (ok) {
-      h = gm_mix64(hpre + elem_hash(cx, u));  // hpre: salt + terms of every other position
+      h = gm_mix64(hpre + elem_hash(cx, hu == 0xFFFFFFFFu ? u : hu));  // hpre: terms of every other position
       A.sum += h;
       A.xr ^= h;
     }
@@ -269,8 +274,10 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t
     const uint64_t pos = base + (uint64_t)__popcll(m & lt);
     if (ok && pos < P.tcap) {
       uint32_t* row = P.tuples + pos * P.twidth;
-      for (uint32_t j = 0; j < P.twidth; ++j)
-        row[j] = j < k ? (j == u ? cx : (j == p2 ? x2 : S.fx[j])) : 0xFFFFFFFFu;
+      for (uint32_t j = 0; j < P.twidth; ++j) {
+        const uint32_t src = (pf && j < k) ? pf->fwd[j] : j;
+        row[j] = j < k ? (src == u ? cx : (src == p2 ? x2 : S.fx[src])) : 0xFFFFFFFFu;
+      }
       P.tmeta[pos] = (q << 1) | sign;
       if (P.flags & GM_F_SEED_ATTR) P.tord[pos] = ord;
       bytes += 4ull * P.twidth + 8;
@@ -424,6 +431,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 
     CPlan pl = (CPlan)P.plans + ((CQuery)P.queries)[q].plan_base + dq;
     const uint32_t k = uni(pl->k);
+    // coalesced search: this plan's matches stand for nperm permutations
+    const uint32_t nperm = P.coalesce ? uni(pl->n_perm) : 1u;
+    CPerm perm0 = (CPerm)P.perms + (P.coalesce ? uni(pl->perm_base) : 0u);
     const uint32_t key = (q << 1) | sign;
     if (key != A.key) {
       flush_acc(P, A, lane);
@@ -439,9 +449,18 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     st_bytes += 4ull * base_l;
 
     if (k == 2) {
-      // the seed itself is the whole match
-      const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], 0);
-      emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
+      // the seed itself is the whole match (and, coalesced, its mirror image)
+      if (nperm == 1) {
+        const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], 0);
+        emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
+      } else {
+        for (uint32_t pi = 0; pi < nperm; ++pi) {
+          CPerm pp = perm0 + pi;
+          const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], uni(pp->inv[0]));
+          emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu, 0, pp,
+               uni(pp->inv[1]));
+        }
+      }
       if (P.donate) {
         unsigned long long left = 1;
         if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
@@ -456,6 +475,17 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // i as (w = query vertex, base = arena index of the subrange, sub = its
     // length).
     const uint32_t pf_lvl = k >= 4 ? k - 2 : 0xFFFFFFFFu;
+    // checksum terms of every position but the last vertex's, for each
+    // permutation pi of a coalesced plan: position i's vertex f(i) takes
+    // position pi^-1(i) in the permuted tuple
+    auto perm_prefixes = [&](uint32_t ulast) {
+      for (uint32_t pi = 0; pi < nperm; ++pi) {
+        CPerm pp = perm0 + pi;
+        uint64_t t = 0;
+        if ((uint32_t)lane < k && (uint32_t)lane != ulast) t = elem_hash(S.fx[lane], pp->inv[lane]);
+        S.hpp[pi] = gm_mix64(((uint64_t)q << 1) | sign) + wave_sum64(t);
+      }
+    };
     auto finish_level = [&](uint32_t l, uint32_t nb, bool act, uint32_t v, uint64_t base, uint32_t sub) {
       uint32_t best = 0xFFFFFFFFu, besti = 0;
       for (uint32_t i = 0; i < nb; ++i) {
@@ -540,6 +570,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         for (uint32_t j = 0; j < k; ++j)
           if (j != u) h += elem_hash(S.fx[j], j);
         S.hpre = h;
+        if (nperm > 1) perm_prefixes(u);
       }
       return true;
     };
@@ -571,6 +602,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       finish_level(l, nb, (uint32_t)lane < nb, v, base, sub);
       S.hpre = uni64(S.st_h) + uni64(S.pf_h[bit]);
+      if (nperm > 1) perm_prefixes(uni(pl->order[l]));
       TALLY_ALWAYS(7, 1);
       return true;
     };
@@ -847,11 +879,25 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (!__ballot(anyok)) break;
         probe_list(ok, e, uni64(S.oth_base[ob + i]), uni(S.oth_len[ob + i]), uni(S.oth_v[ob + i]));
       }
-      const uint64_t hpre = uni64(S.hpre);
+      if (nperm == 1) {
+        const uint64_t hpre = uni64(S.hpre);
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) {
-        const uint64_t m = __ballot(ok[j]);
-        if (m) emit(P, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint64_t m = __ballot(ok[j]);
+          if (m) emit(P, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
+        }
+      } else {
+        // coalesced plan: every match found stands for nperm permuted ones
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const uint64_t m = __ballot(ok[j]);
+          if (m)
+            for (uint32_t pi = 0; pi < nperm; ++pi) {
+              CPerm pp = perm0 + pi;
+              emit(P, S, A, k, u, ok[j], m, x[j], uni64(S.hpp[pi]), q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu,
+                   0, pp, uni(pp->inv[u]));
+            }
+        }
       }
     };
 
@@ -896,6 +942,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // the level's mask for the regular descent.  my_len = this lane's
     // survivor list length (0 if not a survivor).
     auto leaf_packed = [&](uint32_t l, uint64_t m, uint32_t my_len) {
+      if (nperm > 1) return;  // coalesced plans take the regular last level
       const uint32_t lf = k - 1;
       const uint32_t u = uni(pl->order[lf]);
       const uint32_t u2 = uni(pl->order[l]);
@@ -918,7 +965,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
       uint64_t wnd = pm;  // survivors whose range is not finished
       for (uint32_t t0 = 0; t0 < T; t0 += LEAF_UNROLL * GM_WAVE) {
-        if (poll(l)) {
+        // the cycle-counter read behind a poll is a scalar memory access:
+        // every 4th step is often enough
+        if ((t0 & (4 * LEAF_UNROLL * GM_WAVE - 1)) == 0 && poll(l)) {
           abort_now = true;
           return;
         }

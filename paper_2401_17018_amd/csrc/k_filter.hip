@@ -76,7 +76,7 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
                         const uint8_t* __restrict__ canon_sign, uint32_t n_canon,
                         const GmQueryDev* __restrict__ qs, uint32_t nq, const GmPlan* __restrict__ plans,
                         const uint16_t* __restrict__ cand, uint32_t n, GmSeed* __restrict__ seeds,
-                        uint64_t cap, GmCounters* ctr, uint32_t only_q) {
+                        uint64_t cap, GmCounters* ctr, uint32_t only_q, uint32_t coalesce) {
   const uint32_t nqs = only_q < nq ? 1u : nq;
   const uint64_t total = (uint64_t)n_canon * nqs;
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
@@ -88,6 +88,7 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
     const GmQueryDev Q = qs[q];
     for (uint32_t d = 0; d < Q.n_plans; ++d) {
       const GmPlan& P = plans[Q.plan_base + d];
+      if (coalesce && P.n_perm == 0) continue;  // another plan's matches stand for this one's
       if (((ca >> P.x) & 1u) && ((cb >> P.y) & 1u)) {
         unsigned long long pos = atomicAdd(&ctr->n_seeds, 1ull);
         if (pos < cap) {
@@ -166,11 +167,11 @@ void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
-                  uint32_t only_q, hipStream_t s) {
+                  uint32_t only_q, uint32_t coalesce, hipStream_t s) {
   if (!n_canon || !nq) return;
   const uint64_t work = (uint64_t)n_canon * (only_q < nq ? 1u : nq);
   k_seeds<<<grid_for(work, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, n_canon, qs, nq, plans, cand, n,
-                                              seeds, cap, ctr, only_q);
+                                              seeds, cap, ctr, only_q, coalesce);
 }
 
 }  // namespace gm

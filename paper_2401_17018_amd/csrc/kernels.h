@@ -78,6 +78,9 @@ struct GmDfsParams {
   uint32_t split_inner;           // smallest inner-level range worth handing over
   uint32_t split_leaf;            // smallest last-level range worth handing over
   uint32_t gate;                  // hand-over attempt probability per idle wave, in 1/1024
+  const GmPerm* perms;            // coalesced search: permutation table referenced by plans
+  uint32_t coalesce;              // 1: search representative plans only and permute their matches
+  uint32_t pad3;
 };
 
 namespace gm {
@@ -150,7 +153,7 @@ void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
                   uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
-                  uint32_t only_q, hipStream_t s);  // only_q = 0xFFFFFFFF: every query
+                  uint32_t only_q, uint32_t coalesce, hipStream_t s);  // only_q = 0xFFFFFFFF: every query
 
 // search (k_dfs.hip)
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);

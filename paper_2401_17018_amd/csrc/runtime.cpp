@@ -86,7 +86,7 @@ struct gamma_ctx {
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
-  DevBuf lix, lix_lab, r0_off, r0_len;
+  DevBuf lix, lix_lab, r0_off, r0_len, permtab;
   uint32_t wall_khz = 100000;
   gamma_tuning tun{};                // search tunables (never change results)
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
@@ -108,7 +108,7 @@ struct gamma_ctx {
 
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
-                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len,
+                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len, &permtab,
                       &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
@@ -236,13 +236,26 @@ struct gamma_ctx {
       uint32_t* dl = ensure<uint32_t>(lix_lab, lix_labels.size());
       chk(hipMemcpyAsync(dl, lix_labels.data(), lix_labels.size() * 4, hipMemcpyHostToDevice, stream), "h2d");
     }
+    std::vector<GmPerm> all_perms;
     for (auto& q : queries) {
       GmQueryDev d{};
       d.k = q.k;
       d.plan_base = (uint32_t)all_plans.size();
       d.n_plans = (uint32_t)q.plans.size();
       qd.push_back(d);
-      for (auto& p : q.plans) all_plans.push_back(p);
+      const uint32_t pofs = (uint32_t)all_perms.size();
+      for (auto& p : q.plans) {
+        GmPlan pp = p;
+        pp.perm_base += pofs;
+        all_plans.push_back(pp);
+      }
+      all_perms.insert(all_perms.end(), q.perms.begin(), q.perms.end());
+    }
+    if (!all_perms.empty()) {
+      GmPerm* dperm = ensure<GmPerm>(permtab, all_perms.size());
+      chk(hipMemcpyAsync(dperm, all_perms.data(), all_perms.size() * sizeof(GmPerm), hipMemcpyHostToDevice,
+                         stream),
+          "h2d");
     }
     total_plans = (uint32_t)all_plans.size();
     GmPlan* dp = ensure<GmPlan>(plans, std::max<size_t>(all_plans.size(), 1));
@@ -395,6 +408,7 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
   c->tun.split_leaf = 512;
   c->tun.query_launch = 1;
   c->tun.handover_gate = 2;
+  c->tun.coalesced_search = 2;
   *out = c;
   return GAMMA_OK;
 }
@@ -726,7 +740,8 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     gm::launch_seed_window(ctr, s);
     if (nq && !per_query)
       gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
-                       (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu, s);
+                       (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu,
+                       C.tun.coalesced_search == 2 ? 1u : 0u, s);
     chk(hipEventRecord(C.ev[4], s), "event");
 
     // ---------------------------------------------------------- search
@@ -779,11 +794,14 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.split_inner = C.tun.split_inner;
       P.split_leaf = C.tun.split_leaf;
       P.gate = C.tun.handover_gate;
+      P.perms = (const GmPerm*)C.permtab.p;
+      P.coalesce = C.tun.coalesced_search == 2 ? 1u : 0u;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
           gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
-                           (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi, s);
+                           (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi,
+                           C.tun.coalesced_search == 2 ? 1u : 0u, s);
         }
         gm::fill_u32(P.mflag, 0, slots, s);
         gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
@@ -950,7 +968,8 @@ bool tuning_ok(const gamma_tuning& t) {
   return t.waves_per_cu >= 1 && t.waves_per_cu <= 32 && (t.steal == 1 || t.steal == 2) &&
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
-         (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024;
+         (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
+         (t.coalesced_search == 1 || t.coalesced_search == 2);
 }
 }  // namespace
 
@@ -964,6 +983,7 @@ gamma_status gamma_set_tuning(gamma_ctx* c, const gamma_tuning* in) {
   if (in->split_leaf) t.split_leaf = in->split_leaf;
   if (in->query_launch) t.query_launch = in->query_launch;
   if (in->handover_gate) t.handover_gate = in->handover_gate;
+  if (in->coalesced_search) t.coalesced_search = in->coalesced_search;
   if (!tuning_ok(t)) return fail(c, GAMMA_EINVAL, "set_tuning: value out of range");
   c->tun = t;
   return GAMMA_OK;
@@ -980,7 +1000,7 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
   auto same = [](const gamma_tuning& a, const gamma_tuning& b) {
     return a.waves_per_cu == b.waves_per_cu && a.steal == b.steal && a.poll_cycles == b.poll_cycles &&
            a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch &&
-           a.handover_gate == b.handover_gate;
+           a.handover_gate == b.handover_gate && a.coalesced_search == b.coalesced_search;
   };
   gamma_status err = GAMMA_OK;
   // median device time of `reps` dry runs at tuning t (< 0: failed)
@@ -1034,8 +1054,9 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
         }
       }
     };
-    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2};
+    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1};
     if (many_q) sweep(&gamma_tuning::query_launch, ql_v, 2);
+    sweep(&gamma_tuning::coalesced_search, cs_v, 2);
     sweep(&gamma_tuning::steal, steal_v, 2);
     sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);
     if (cur.steal == 1) {

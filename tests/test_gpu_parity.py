@@ -233,10 +233,10 @@ def test_labels_wide_and_absent():
     assert res.counts[1].sum() == 0
 
 
-def test_star_and_edge_closed_forms_on_mid_graph():
-    """Full-size mid R-MAT graph: star and single-edge queries against closed forms."""
-    w = W.mid()
-    g, b = w.graph, w.batches[0]
+def star_and_edge_check(g, b):
+    """A star (centre label 0, leaves labels 1 and 2) and a single-edge query
+    (labels 0-1) on a full-size graph, against closed forms computed from
+    the oracle's canonical batch and updated graph."""
     qs = [W.query_from_edges(3, [(0, 1), (0, 2)], (0, 1, 2)),
           W.query_from_edges(2, [(0, 1)], (0, 1))]
     with make_ctx(cap=0) as ctx:
@@ -244,22 +244,35 @@ def test_star_and_edge_closed_forms_on_mid_graph():
         for q in qs:
             ctx.register_query(q.k, q.labels, q.edges)
         res = ctx.apply_batch(b.src, b.dst, b.op, canonical=True)
-    ins = [(int(a), int(c)) for a, c, s in zip(res.canon_lo, res.canon_hi, res.canon_sign) if s]
-    dels = [(int(a), int(c)) for a, c, s in zip(res.canon_lo, res.canon_hi, res.canon_sign) if not s]
+    # the oracle's canonical batch (a sampled run does no search work)
+    ref = O2.run(g, qs[1], b, qid=1, threads=16, sample_mod=1 << 30, sample_rem=1, want_tuples=False)
+    assert ref.status == 0
+    assert np.array_equal(res.canon_lo, ref.canon_lo) and np.array_equal(res.canon_hi, ref.canon_hi)
+    assert np.array_equal(res.canon_sign, ref.canon_sign)
+    ins = [(int(a), int(c)) for a, c, s in zip(ref.canon_lo, ref.canon_hi, ref.canon_sign) if s]
+    dels = [(int(a), int(c)) for a, c, s in zip(ref.canon_lo, ref.canon_hi, ref.canon_sign) if not s]
     assert res.count(1, 1) == CF.single_edge_delta(ins, g.labels, 0, 1)
     assert res.count(1, 0) == CF.single_edge_delta(dels, g.labels, 0, 1)
     # star: count centres' neighbour labels before and after
     rp2, col2 = O2.updated_graph(g, b)
 
     def star_total(rp, col):
-        src = np.repeat(np.arange(g.n), np.diff(rp).astype(np.int64))
+        src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(rp).astype(np.int64))
         lab = g.labels[col]
-        cnt1 = np.bincount(src[lab == 1], minlength=g.n).astype(object)
-        cnt2 = np.bincount(src[lab == 2], minlength=g.n).astype(object)
+        cnt1 = np.bincount(src[lab == 1], minlength=g.n).astype(np.int64)
+        cnt2 = np.bincount(src[lab == 2], minlength=g.n).astype(np.int64)
         centre = g.labels == 0
-        return int(np.sum((cnt1 * cnt2)[centre]))
+        # products stay below 2^63: a centre has fewer than 2^31 neighbours
+        return int(np.sum((cnt1 * cnt2)[centre], dtype=np.int64))
 
     assert res.count(0, 1) - res.count(0, 0) == star_total(rp2, col2) - star_total(g.row_ptr, g.col)
+    return res
+
+
+def test_star_and_edge_closed_forms_on_mid_graph():
+    """Full-size mid R-MAT graph: star and single-edge queries against closed forms."""
+    w = W.mid()
+    star_and_edge_check(w.graph, w.batches[0])
 
 
 def _skewed_graph(seed):
