@@ -487,11 +487,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
     };
     auto finish_level = [&](uint32_t l, uint32_t nb, bool act, uint32_t v, uint64_t base, uint32_t sub) {
-      uint32_t best = 0xFFFFFFFFu, besti = 0;
+      uint32_t best = 0xFFFFFFFFu, bestv = 0xFFFFFFFFu, besti = 0;
       for (uint32_t i = 0; i < nb; ++i) {
-        const uint32_t si = lane_val(sub, i);
-        if (si < best) {
+        const uint32_t si = lane_val(sub, i), vi = lane_val(v, i);
+        if (si < best || (si == best && vi < bestv)) {
           best = si;
+          bestv = vi;
           besti = i;
         }
       }

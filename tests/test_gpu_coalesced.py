@@ -69,3 +69,27 @@ def test_coalesced_many_queries_with_handover():
     assert on.stats["steals"] > 0
     for qid, q in enumerate(qs):
         check_against_o2(on, g, q, b, qid=qid, check_tuples=not on.truncated)
+
+
+def test_handover_of_last_level_ranges_keeps_the_driver():
+    """Regression: a wave that receives part of a last-level range rebuilds
+    that level and must drive it with the donor's list.  With equal list
+    lengths the choice once depended on the order the lists were gathered
+    in, and K4 on label 0 of the mid graph lost matches with hand-over on."""
+    from paper_2401_17018_amd import Context
+    w = W.symmetric_queries()
+    q, b = w.queries[2], w.batches[0]
+    outs = []
+    with Context(device=0) as ctx:
+        ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
+        ctx.register_query(q.k, q.labels, q.edges)
+        for tun in (dict(steal=2, coalesced_search=1), dict(steal=1, coalesced_search=1),
+                    dict(steal=1, coalesced_search=2),
+                    dict(steal=1, coalesced_search=1, poll_cycles=500, split_leaf=2, split_inner=2,
+                         handover_gate=1024)):
+            ctx.set_tuning(**tun)
+            outs.append(ctx.apply_batch(b.src, b.dst, b.op, per_update=True, dry_run=True))
+    assert outs[0].counts.sum() > 0
+    for o in outs[1:]:
+        _same(outs[0], o)
+    assert outs[3].stats["steals"] > 0

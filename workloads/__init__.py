@@ -581,13 +581,13 @@ BATCHED_QUERY_MIN_LABEL = 8  # Zipf(1.2) over 16 labels: each label >= 8 covers 
 
 def symmetric_queries(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
     """The mid graph and its batch stream with four queries that have
-    label-preserving automorphisms (equal-label triangle, 4-cycle and K4, a
-    star with equal leaves), on labels 8..11 (each <= 2.6% of vertices)."""
+    label-preserving automorphisms: triangle and K4 on label 0, a 4-cycle
+    on label 1, a star with a label-2 centre and three label-1 leaves."""
     w = mid(seed, n_batches=n_batches, threads=threads)
-    w.queries = [query_from_edges(3, [(0, 1), (1, 2), (2, 0)], (8, 8, 8), "dense"),
-                 query_from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)], (9, 9, 9, 9), "sparse"),
-                 query_from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], (10, 10, 10, 10), "dense"),
-                 query_from_edges(4, [(0, 1), (0, 2), (0, 3)], (11, 8, 8, 8), "tree")]
+    w.queries = [query_from_edges(3, [(0, 1), (1, 2), (2, 0)], (0, 0, 0), "dense"),
+                 query_from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)], (1, 1, 1, 1), "sparse"),
+                 query_from_edges(4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], (0, 0, 0, 0), "dense"),
+                 query_from_edges(4, [(0, 1), (0, 2), (0, 3)], (2, 1, 1, 1), "tree")]
     w.name = "symmetric-rmat20"
     return w
 
