@@ -226,6 +226,37 @@ gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* s
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);
 
+/* Vertex updates (Sec. II-A, the batch-dynamic setting): a vertex deletion
+ * is the deletion of all of its incident edges; a vertex insertion adds the
+ * vertex first, its edges then come as edge insertions.
+ *
+ * gamma_apply_batch_vertices applies one batch of edge updates plus vertex
+ * deletions.  Each deleted vertex (external id in vdel[n_vdel], duplicates
+ * allowed) is expanded on the device into deletions of every edge it has in
+ * the current graph, appended after the explicit updates; the merged batch
+ * is then applied exactly as by gamma_apply_batch (same flags, result and
+ * per-update attribution, whose canonical order covers the expanded edges
+ * too).  The vertex keeps its id and label and is isolated afterwards.
+ *   src,dst,op,n_upd  explicit edge updates as for gamma_apply_batch
+ *   vdel,n_vdel       vertices to delete, n_vdel <= 2^20
+ *   where             memory kind of all five arrays
+ * Errors: EINVAL (an id >= n, null arrays, more than 2^20 updates after the
+ * expansion), ECONFLICT (an explicit insertion touches a deleted vertex, or
+ * the rules of gamma_apply_batch), and those of gamma_apply_batch.  Any
+ * error leaves the graph unchanged. */
+gamma_status gamma_apply_batch_vertices(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
+                                        const uint32_t* dst, const uint8_t* op, uint32_t n_vdel,
+                                        const uint32_t* vdel, gamma_mem where, uint32_t flags,
+                                        gamma_batch_result* out);
+
+/* Append `count` isolated vertices with host labels[count] (< 2^16); they
+ * get the external ids n, n+1, ... (*first_id = n, may be NULL).  The graph
+ * is rebuilt on the device and registered queries are re-planned, as by
+ * gamma_load_graph.  Errors: EINVAL (count 0, null labels, n + count >=
+ * 2^31), ESTATE (no graph), ENOMEM, EDEVICE; on error the graph is as before
+ * except after EDEVICE. */
+gamma_status gamma_add_vertices(gamma_ctx* ctx, uint32_t count, const uint32_t* labels, uint32_t* first_id);
+
 /* Current search tunables (every field filled).  Errors: EINVAL (NULL). */
 gamma_status gamma_get_tuning(const gamma_ctx* ctx, gamma_tuning* out);
 

@@ -13,6 +13,8 @@ Contents
   plain         O2: the plain incremental enumerator (C, libo2.so) that
                 follows Algorithm 1 of Sec. IV-C with the order rule stated
                 after it; ctypes wrapper.
+  vertices      vertex insertions and deletions reduced to edge updates
+                (Sec. II-A), for use with brute and plain.
   closed_forms  closed-form counts (stars, single edges, equal-label
                 triangles), label-preserving automorphisms, per-tuple
                 validation and the multiset hash.

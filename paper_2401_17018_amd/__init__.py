@@ -5,7 +5,10 @@ only marshals arguments: graph loading, batch canonicalisation, the graph
 update, the candidate filter, seeding, the search and the commit all run in
 the library's HIP kernels on the GPU.  Inputs may be numpy arrays (host
 memory) or torch tensors on the context's device; torch is used for device
-memory and streams only.
+memory and streams only.  To pass torch tensors, import torch (and touch
+its GPU) before the first Context: torch ships its own libamdhip64.so.7,
+the library then shares that runtime; loaded the other way round, torch's
+GPU initialisation fails in the process.
 
     ctx = Context(device=0)
     ctx.load_graph(row_ptr, col, labels)
@@ -169,13 +172,21 @@ class Context:
         return int(qid.value)
 
     def apply_batch(self, src, dst, op, hash: bool = True, tuples: bool = False, seed_attr: bool = False,
-                    per_update: bool = False, canonical: bool = False, dry_run: bool = False) -> BatchOutput:
-        """Apply one batch (dry_run: search it without committing it)."""
+                    per_update: bool = False, canonical: bool = False, dry_run: bool = False,
+                    delete_vertices=None) -> BatchOutput:
+        """Apply one batch (dry_run: search it without committing it).
+
+        delete_vertices: ids whose incident edges are all deleted in the same
+        batch, appended after the explicit updates (gamma_apply_batch_vertices)."""
         s, k1, w1 = _arg(src, np.uint32)
         d, k2, w2 = _arg(dst, np.uint32)
         o, k3, w3 = _arg(op, np.uint8)
-        if len({w1, w2, w3}) != 1:
-            raise ValueError("src, dst and op must all be host arrays or all device tensors")
+        ws = {w1, w2, w3}
+        if delete_vertices is not None:
+            vd, k4, w4 = _arg(delete_vertices, np.uint32)
+            ws.add(w4)
+        if len(ws) != 1:
+            raise ValueError("src, dst, op (and delete_vertices) must all be host arrays or all device tensors")
         n_upd = int(k1.shape[0])
         flags = F_COUNT
         flags |= F_HASH if hash else 0
@@ -185,8 +196,14 @@ class Context:
         flags |= F_CANONICAL if canonical else 0
         flags |= F_DRY_RUN if dry_run else 0
         res = capi.BatchResult()
-        st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
-                                         o if n_upd else None, w1, flags, ctypes.byref(res))
+        if delete_vertices is None:
+            st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                             o if n_upd else None, w1, flags, ctypes.byref(res))
+        else:
+            nv = int(k4.shape[0])
+            st = self._lib.gamma_apply_batch_vertices(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                                      o if n_upd else None, nv, vd if nv else None, w1, flags,
+                                                      ctypes.byref(res))
         if st == capi.GAMMA_ETIMEDOUT:
             err = GammaError(st, "apply_batch: %s" % (self._lib.gamma_last_error(self._ptr) or b"").decode())
             err.stats = {name: getattr(res.stats, name) for name, _ in capi.BatchStats._fields_
@@ -238,6 +255,17 @@ class Context:
         stt = res.stats
         out.stats = {name: getattr(stt, name) for name, _ in capi.BatchStats._fields_ if not name.startswith("reserved")}
         return out
+
+    def add_vertices(self, labels) -> int:
+        """Append isolated vertices with these labels; returns the first new id."""
+        lab = np.ascontiguousarray(np.asarray(labels, dtype=np.uint32))
+        first = ctypes.c_uint32(0)
+        _check(self._lib, self._ptr,
+               self._lib.gamma_add_vertices(self._ptr, int(lab.shape[0]),
+                                            lab.ctypes.data_as(ctypes.c_void_p) if lab.size else None,
+                                            ctypes.byref(first)),
+               "add_vertices")
+        return int(first.value)
 
     # ------------------------------------------------------------ tuning
 

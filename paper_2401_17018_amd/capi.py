@@ -23,7 +23,7 @@ F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL, F_DRY_RUN = 1
 # every function declared in include/gamma.h
 EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
-    "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
+    "gamma_apply_batch_vertices", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
     "gamma_serve_create", "gamma_serve_submit", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
     "gamma_serve_get_batch", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
@@ -190,6 +190,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_register_query.argtypes = [P, u32, P, u32, P, ctypes.POINTER(u32)]
     lib.gamma_apply_batch.restype = st
     lib.gamma_apply_batch.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, ctypes.POINTER(BatchResult)]
+    lib.gamma_apply_batch_vertices.restype = st
+    lib.gamma_apply_batch_vertices.argtypes = [P, u32, P, P, P, u32, P, ctypes.c_int, u32,
+                                               ctypes.POINTER(BatchResult)]
+    lib.gamma_add_vertices.restype = st
+    lib.gamma_add_vertices.argtypes = [P, u32, P, ctypes.POINTER(u32)]
     lib.gamma_get_tuning.restype = st
     lib.gamma_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.gamma_set_tuning.restype = st

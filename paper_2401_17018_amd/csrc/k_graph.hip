@@ -187,6 +187,57 @@ __global__ void k_gather_ext(const uint32_t* __restrict__ col, const uint32_t* _
     ext[i] = o2n[col[i] & GM_IDMASK];
 }
 
+// Vertex deletion as edge deletions (the paper's reduction, Sec. II-A):
+// the row length of every deleted vertex (external id; ids >= n raise the
+// range error and count 0), marking it in an n-bit map; then its incident
+// edges as (v, w, delete).
+__global__ void k_vdel_len(GmGraphDev G, const uint32_t* __restrict__ vdel, uint32_t nv,
+                           uint64_t* __restrict__ len, uint32_t* __restrict__ mark, uint32_t* __restrict__ err) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+    const uint32_t v = vdel[i];
+    if (v >= G.n) {
+      atomicOr(err, GM_ERR_RANGE);
+      len[i] = 0;
+    } else {
+      len[i] = G.row_len[G.new_of_old[v]];
+      atomicOr(&mark[v >> 5], 1u << (v & 31));
+    }
+  }
+}
+
+// an explicit insertion that touches a deleted vertex cannot be ordered
+// against the deletion: conflict (ids >= n are left to the batch's own
+// range check)
+__global__ void k_vdel_check(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                             const uint8_t* __restrict__ op, uint32_t n_upd, uint32_t n,
+                             const uint32_t* __restrict__ mark, uint32_t* __restrict__ err) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_upd; i += gridDim.x * blockDim.x) {
+    if (!op[i]) continue;
+    const uint32_t a = src[i], b = dst[i];
+    const bool hit = (a < n && ((mark[a >> 5] >> (a & 31)) & 1u)) || (b < n && ((mark[b >> 5] >> (b & 31)) & 1u));
+    if (hit) atomicOr(err, GM_ERR_CONFLICT);
+  }
+}
+
+__global__ void k_vdel_expand(GmGraphDev G, const uint32_t* __restrict__ vdel, uint32_t nv,
+                              const uint64_t* __restrict__ offs, uint32_t* __restrict__ src,
+                              uint32_t* __restrict__ dst, uint8_t* __restrict__ op) {
+  // one wave per deleted vertex, lanes over its row
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < nv; i += (gridDim.x * blockDim.x) >> 6) {
+    const uint32_t v = vdel[i];
+    if (v >= G.n) continue;
+    const uint32_t vi = G.new_of_old[v];
+    const uint64_t base = G.row_off[vi], o = offs[i];
+    const uint32_t len = G.row_len[vi];
+    for (uint32_t j = lane; j < len; j += 64) {
+      src[o + j] = v;
+      dst[o + j] = G.ext[base + j];
+      op[o + j] = 0;
+    }
+  }
+}
+
 unsigned grid_for(uint64_t work, unsigned per_block) {
   uint64_t b = (work + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -242,6 +293,24 @@ void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n
 void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
                       const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s) {
   k_copy_rows<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(row_off, row_len, src, new_off, dst, n);
+}
+
+void launch_vdel_len(GmGraphDev G, const uint32_t* vdel, uint32_t nv, uint64_t* len, uint32_t* mark, uint32_t* err,
+                     hipStream_t s) {
+  if (!nv) return;
+  k_vdel_len<<<grid_for(nv, 256), 256, 0, s>>>(G, vdel, nv, len, mark, err);
+}
+
+void launch_vdel_check(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd, uint32_t n,
+                       const uint32_t* mark, uint32_t* err, hipStream_t s) {
+  if (!n_upd) return;
+  k_vdel_check<<<grid_for(n_upd, 256), 256, 0, s>>>(src, dst, op, n_upd, n, mark, err);
+}
+
+void launch_vdel_expand(GmGraphDev G, const uint32_t* vdel, uint32_t nv, const uint64_t* offs, uint32_t* src,
+                        uint32_t* dst, uint8_t* op, hipStream_t s) {
+  if (!nv) return;
+  k_vdel_expand<<<grid_for((uint64_t)nv * 64, 256), 256, 0, s>>>(G, vdel, nv, offs, src, dst, op);
 }
 
 void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,

@@ -105,6 +105,16 @@ void launch_rows_from_scan(const uint64_t* offs, const uint64_t* deg, uint32_t n
 void launch_copy_rows(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* src,
                       const uint64_t* new_off, uint32_t* dst, uint32_t n, hipStream_t s);
 void launch_u32_to_u64(const uint32_t* in, uint64_t* out, uint32_t n, hipStream_t s);
+// vertex deletions: row lengths (err |= GM_ERR_RANGE for ids >= n) with
+// each deleted vertex set in the n-bit map `mark` (cleared by the caller);
+// explicit insertions touching a marked vertex (err |= GM_ERR_CONFLICT);
+// then the incident edges as deletions at offs[i] (external ids)
+void launch_vdel_len(GmGraphDev G, const uint32_t* vdel, uint32_t nv, uint64_t* len, uint32_t* mark, uint32_t* err,
+                     hipStream_t s);
+void launch_vdel_check(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd, uint32_t n,
+                       const uint32_t* mark, uint32_t* err, hipStream_t s);
+void launch_vdel_expand(GmGraphDev G, const uint32_t* vdel, uint32_t nv, const uint64_t* offs, uint32_t* src,
+                        uint32_t* dst, uint8_t* op, hipStream_t s);
 void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,
                        hipStream_t s);
 

@@ -87,6 +87,7 @@ struct gamma_ctx {
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
   DevBuf lix, lix_lab, r0_off, r0_len, permtab;
+  DevBuf vx_src, vx_dst, vx_op, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
   uint32_t wall_khz = 100000;
   gamma_tuning tun{};                // search tunables (never change results)
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
@@ -109,6 +110,7 @@ struct gamma_ctx {
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
                       &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len, &permtab,
+                      &vx_src, &vx_dst, &vx_op, &vx_del, &vx_len, &vx_off, &vx_mark,
                       &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
@@ -956,6 +958,90 @@ bool ctx_has_graph(const gamma_ctx* c, uint32_t* n) {
 }  // namespace gm
 
 extern "C" {
+
+gamma_status gamma_apply_batch_vertices(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                        const uint8_t* op, uint32_t n_vdel, const uint32_t* vdel, gamma_mem where,
+                                        uint32_t flags, gamma_batch_result* out) {
+  size_t N = 0;  // explicit updates + expanded vertex deletions
+  const gamma_status st = guarded(c, [&]() -> gamma_status {
+    if (!out) return fail(c, GAMMA_EINVAL, "apply_batch_vertices: null result");
+    if (!c->has_graph) return fail(c, GAMMA_ESTATE, "apply_batch_vertices: no graph loaded");
+    if (n_upd > (1u << 20) || n_vdel > (1u << 20)) return fail(c, GAMMA_EINVAL, "apply_batch_vertices: too many updates");
+    if ((n_upd && (!src || !dst || !op)) || (n_vdel && !vdel))
+      return fail(c, GAMMA_EINVAL, "apply_batch_vertices: null arrays");
+    chk(hipSetDevice(c->device), "set device");
+    gamma_ctx& C = *c;
+    hipStream_t s = C.stream;
+    const uint32_t* d_vdel = stage_in<uint32_t>(c, C.vx_del, vdel, n_vdel, where);
+    uint64_t* len = C.ensure<uint64_t>(C.vx_len, std::max<uint32_t>(n_vdel, 1));
+    uint64_t* offs = C.ensure<uint64_t>(C.vx_off, (size_t)n_vdel + 1);
+    // word 0: error flags; words 1..: the deleted-vertex bit map
+    const size_t mwords = ((size_t)C.n + 31) / 32;
+    uint32_t* err = C.ensure<uint32_t>(C.vx_mark, 1 + mwords);
+    uint32_t* mark = err + 1;
+    gm::fill_u32(err, 0, 1 + mwords, s);
+    gm::launch_vdel_len(C.G(), d_vdel, n_vdel, len, mark, err, s);
+    const uint32_t* e_src = stage_in<uint32_t>(c, C.vx_src, src, n_upd, where);
+    const uint32_t* e_dst = stage_in<uint32_t>(c, C.vx_dst, dst, n_upd, where);
+    const uint8_t* e_op = stage_in<uint8_t>(c, C.vx_op, op, n_upd, where);
+    gm::launch_vdel_check(e_src, e_dst, e_op, n_upd, C.n, mark, err, s);
+    C.scan64(len, offs, n_vdel);
+    uint64_t total = 0;
+    uint32_t herr = 0;
+    if (n_vdel) chk(hipMemcpyAsync(&total, offs + n_vdel, 8, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s), "d2h");
+    chk(hipStreamSynchronize(s), "sync");
+    if (herr & GM_ERR_RANGE) return fail(c, GAMMA_EINVAL, "apply_batch_vertices: vertex id out of range");
+    if (herr & GM_ERR_CONFLICT)
+      return fail(c, GAMMA_ECONFLICT, "apply_batch_vertices: an insertion touches a deleted vertex");
+    if ((uint64_t)n_upd + total > (1u << 20))
+      return fail(c, GAMMA_EINVAL, "apply_batch_vertices: more than 2^20 updates after expanding vertex deletions");
+    N = (size_t)n_upd + total;
+    uint32_t* xs = C.ensure<uint32_t>(C.vx_src, std::max<size_t>(N, 1));
+    uint32_t* xd = C.ensure<uint32_t>(C.vx_dst, std::max<size_t>(N, 1));
+    uint8_t* xo = C.ensure<uint8_t>(C.vx_op, std::max<size_t>(N, 1));
+    const hipMemcpyKind kind = where == GAMMA_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (n_upd) {
+      chk(hipMemcpyAsync(xs, src, (size_t)n_upd * 4, kind, s), "copy");
+      chk(hipMemcpyAsync(xd, dst, (size_t)n_upd * 4, kind, s), "copy");
+      chk(hipMemcpyAsync(xo, op, n_upd, kind, s), "copy");
+    }
+    gm::launch_vdel_expand(C.G(), d_vdel, n_vdel, offs, xs + n_upd, xd + n_upd, xo + n_upd, s);
+    chk(hipGetLastError(), "vertex deletion launch");
+    return GAMMA_OK;
+  });
+  if (st != GAMMA_OK) return st;
+  // the merged batch is device-resident and ordered on the context stream
+  // after the expansion
+  return gamma_apply_batch(c, (uint32_t)N, (const uint32_t*)c->vx_src.p, (const uint32_t*)c->vx_dst.p,
+                           (const uint8_t*)c->vx_op.p, GAMMA_MEM_DEVICE, flags, out);
+}
+
+gamma_status gamma_add_vertices(gamma_ctx* c, uint32_t count, const uint32_t* labels, uint32_t* first_id) {
+  return guarded(c, [&]() -> gamma_status {
+    if (!c->has_graph) return fail(c, GAMMA_ESTATE, "add_vertices: no graph loaded");
+    if (count == 0 || !labels) return fail(c, GAMMA_EINVAL, "add_vertices: nothing to add");
+    const uint32_t n = c->n;
+    if ((uint64_t)n + count >= 0x80000000ull) return fail(c, GAMMA_EINVAL, "add_vertices: n would reach 2^31");
+    for (uint32_t i = 0; i < count; ++i)
+      if (labels[i] > 0xFFFFu) return fail(c, GAMMA_EINVAL, "add_vertices: label >= 65536");
+    // the new vertices are isolated: rebuild with the extended vertex set
+    // (label-grouped internal ids interleave them with the old ones)
+    const uint64_t nnz = c->live;
+    std::vector<uint64_t> rp((size_t)n + count + 1);
+    std::vector<uint32_t> col(std::max<uint64_t>(nnz, 1)), lab((size_t)n + count);
+    gamma_status st = gamma_export_graph(c, nullptr, nullptr, rp.data(), col.data(), lab.data());
+    if (st < 0) return st;
+    for (uint32_t i = 0; i < count; ++i) {
+      rp[(size_t)n + 1 + i] = nnz;
+      lab[(size_t)n + i] = labels[i];
+    }
+    st = gamma_load_graph(c, n + count, nnz, rp.data(), nnz ? col.data() : nullptr, lab.data(), GAMMA_MEM_HOST);
+    if (st < 0) return st;
+    if (first_id) *first_id = n;
+    return GAMMA_OK;
+  });
+}
 
 gamma_status gamma_get_tuning(const gamma_ctx* c, gamma_tuning* out) {
   if (!c || !out) return GAMMA_EINVAL;
