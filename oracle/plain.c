@@ -21,6 +21,16 @@
  *   A match is an injective, label-preserving map f: V(Q) -> V such that
  *   every query edge maps onto a data edge (non-induced; Def. 2).
  *
+ * Edge labels (Sec. II-A: the labelling function also covers edges): every
+ * data edge, query edge and update carries a label in [0, L), L = 1 for an
+ * unlabelled graph.  A query edge (u, w) with label e maps onto a data edge
+ * {f(u), f(w)} with label e.  Data edges are the triples {v, w, e}; one
+ * pair may hold edges of several labels.  An update names its triple; two
+ * updates of one pair in a batch must be the same triple with the same op
+ * (duplicates) or the batch is rejected as conflicting.  Internally a row
+ * holds keys w * L + e in ascending order, so with L = 1 the key is the
+ * neighbour itself.
+ *
  * How (Sec. IV-C, Algorithm 1 and the order rule that follows it):
  *   every update edge e_i of a pass carries ord i = its rank in ascending
  *   (lo, hi) order over the canonical batch.  For each seed e_i and each
@@ -65,7 +75,8 @@ enum {
   MUT_DELETE_ON_GPRIME = 4, /* deletion pass searches G' instead of G */
   MUT_SKIP_FIRST_CHECK = 5, /* w0's edge is not checked against the order rule */
   MUT_NO_LABEL_CHECK = 6,   /* extension ignores labels */
-  MUT_KEEP_NOOPS = 7        /* no-op updates are not skipped */
+  MUT_KEEP_NOOPS = 7,       /* no-op updates are not skipped */
+  MUT_NO_EDGE_LABEL_CHECK = 8 /* extension ignores edge labels */
 };
 
 typedef struct {
@@ -84,6 +95,7 @@ typedef struct {
   uint64_t* seed_hxor; /* n_canonical: per seed (update) totals */
   double seconds;
   int32_t threads_used;
+  uint32_t* canon_e; /* n_canonical: edge label of each canonical update */
 } o2_result;
 
 /* ---------------------------------------------------------------- hashing */
@@ -108,7 +120,7 @@ static uint64_t tuple_hash(uint32_t qid, int sign, const uint32_t* f, uint32_t k
 typedef struct {
   uint32_t n;
   const uint64_t* rp;
-  const uint32_t* col;
+  const uint32_t* col; /* keys w * L + e, ascending per row */
 } csr_t;
 
 static int row_has(const csr_t* g, uint32_t u, uint32_t v) {
@@ -124,7 +136,7 @@ static int row_has(const csr_t* g, uint32_t u, uint32_t v) {
 }
 
 typedef struct {
-  uint32_t lo, hi;
+  uint32_t lo, hi, e;
   uint8_t op;
 } upd_t;
 
@@ -133,6 +145,7 @@ static int upd_cmp(const void* a, const void* b) {
   const upd_t* y = (const upd_t*)b;
   if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
   if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+  if (x->e != y->e) return x->e < y->e ? -1 : 1;
   if (x->op != y->op) return x->op < y->op ? -1 : 1;
   return 0;
 }
@@ -147,10 +160,12 @@ typedef struct {
   uint32_t n;
   uint32_t* lo;
   uint32_t* hi;
+  uint32_t* e;
   uint8_t* sign;
 } canon_t;
 
-/* Find (lo, hi) among the canonical edges; returns its ord or -1. */
+/* Find the pair (lo, hi) among the canonical edges; returns its ord or -1
+ * (a pair occurs at most once in a canonical batch). */
 static int64_t canon_find(const canon_t* c, uint32_t a, uint32_t b) {
   uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
   int64_t l = 0, r = (int64_t)c->n;
@@ -165,33 +180,36 @@ static int64_t canon_find(const canon_t* c, uint32_t a, uint32_t b) {
   return -1;
 }
 
-static int canonicalise(const csr_t* g, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
-                        const uint8_t* op, int mutant, canon_t* out, o2_result* res) {
+static int canonicalise(const csr_t* g, uint32_t L, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                        const uint8_t* op, const uint32_t* uel, int mutant, canon_t* out, o2_result* res) {
   upd_t* u = (upd_t*)malloc(sizeof(upd_t) * (n_upd ? n_upd : 1));
   for (uint32_t i = 0; i < n_upd; ++i) {
-    if (src[i] == dst[i] || src[i] >= g->n || dst[i] >= g->n) {
+    const uint32_t e = uel ? uel[i] : 0;
+    if (src[i] == dst[i] || src[i] >= g->n || dst[i] >= g->n || e >= L) {
       free(u);
       return -1;
     }
     u[i].lo = src[i] < dst[i] ? src[i] : dst[i];
     u[i].hi = src[i] < dst[i] ? dst[i] : src[i];
+    u[i].e = e;
     u[i].op = op[i] ? 1 : 0;
   }
   qsort(u, n_upd, sizeof(upd_t), upd_cmp);
   out->lo = (uint32_t*)malloc(4 * (n_upd ? n_upd : 1));
   out->hi = (uint32_t*)malloc(4 * (n_upd ? n_upd : 1));
+  out->e = (uint32_t*)malloc(4 * (n_upd ? n_upd : 1));
   out->sign = (uint8_t*)malloc(n_upd ? n_upd : 1);
   out->n = 0;
   for (uint32_t i = 0; i < n_upd; ++i) {
     if (i > 0 && u[i].lo == u[i - 1].lo && u[i].hi == u[i - 1].hi) {
-      if (u[i].op != u[i - 1].op) {
+      if (u[i].op != u[i - 1].op || u[i].e != u[i - 1].e) {
         free(u);
         return -2;
       }
       res->n_dup++;
       continue;
     }
-    int present = row_has(g, u[i].lo, u[i].hi);
+    int present = row_has(g, u[i].lo, u[i].hi * L + u[i].e);
     int noop = u[i].op ? present : !present;
     if (noop && mutant != MUT_KEEP_NOOPS) {
       res->n_noop++;
@@ -199,6 +217,7 @@ static int canonicalise(const csr_t* g, uint32_t n_upd, const uint32_t* src, con
     }
     out->lo[out->n] = u[i].lo;
     out->hi[out->n] = u[i].hi;
+    out->e[out->n] = u[i].e;
     out->sign[out->n] = u[i].op;
     out->n++;
   }
@@ -207,7 +226,7 @@ static int canonicalise(const csr_t* g, uint32_t n_upd, const uint32_t* src, con
 }
 
 /* G' = (E u I) \ D as a fresh CSR with ascending rows. */
-static void build_updated(const csr_t* g, const canon_t* c, uint64_t** rp_out, uint32_t** col_out) {
+static void build_updated(const csr_t* g, uint32_t L, const canon_t* c, uint64_t** rp_out, uint32_t** col_out) {
   uint32_t n = g->n;
   int64_t* delta = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   for (uint32_t i = 0; i < c->n; ++i) {
@@ -233,13 +252,13 @@ static void build_updated(const csr_t* g, const canon_t* c, uint64_t** rp_out, u
   uint8_t* bs = (uint8_t*)malloc(bstart[n] ? bstart[n] : 1);
   for (uint32_t i = 0; i < c->n; ++i) {
     uint64_t p = fill[c->lo[i]]++;
-    bn[p] = c->hi[i];
+    bn[p] = c->hi[i] * L + c->e[i];
     bs[p] = c->sign[i];
     p = fill[c->hi[i]]++;
-    bn[p] = c->lo[i];
+    bn[p] = c->lo[i] * L + c->e[i];
     bs[p] = c->sign[i];
   }
-  /* deleted neighbours of v, ascending, for a binary-search membership test */
+  /* deleted entries (keys) of v, ascending, for a binary-search membership test */
   uint32_t* dn = (uint32_t*)malloc(4 * (bstart[n] ? bstart[n] : 1));
   for (uint32_t v = 0; v < n; ++v) {
     uint64_t nd = 0;
@@ -280,6 +299,7 @@ typedef struct {
   uint32_t k;
   const uint32_t* qlab;
   uint8_t adj[16][16];
+  uint32_t qel[16][16]; /* edge label of query edge {a, b} */
   uint32_t n_dqe;
   uint32_t dx[256], dy[256];
   uint32_t order[256][16]; /* BFS matching order per directed query edge */
@@ -298,6 +318,7 @@ typedef struct {
   const canon_t* c;
   const uint32_t* labels;
   const query_t* q;
+  uint32_t L; /* number of edge labels */
   uint32_t qid;
   int mutant, want_tuples;
   uint32_t sample_mod, sample_rem;
@@ -336,13 +357,15 @@ static void emit(worker_t* w, int sign, uint32_t ord, const uint32_t* f) {
   w->out.n++;
 }
 
-/* Is data edge {a, b} usable by seed `ord` of pass `sign` on graph H? */
+/* Is data edge {a, b, el} usable by seed `ord` of pass `sign` on graph H?
+ * (Only the batch edge of that pair with that label is subject to the
+ * order rule; an edge of another label between a and b is not in the batch.) */
 static int edge_ok(const shared_t* sh, const csr_t* H, int sign, uint32_t ord, uint32_t a,
-                   uint32_t b) {
-  if (!row_has(H, a, b)) return 0;
+                   uint32_t b, uint32_t el) {
+  if (!row_has(H, a, b * sh->L + el)) return 0;
   if (sh->mutant == MUT_NO_ORDER_RULE) return 1;
   int64_t e = canon_find(sh->c, a, b);
-  if (e >= 0 && sh->c->sign[e] == (uint8_t)sign && (uint32_t)e < ord) return 0;
+  if (e >= 0 && sh->c->e[e] == el && sh->c->sign[e] == (uint8_t)sign && (uint32_t)e < ord) return 0;
   return 1;
 }
 
@@ -361,8 +384,10 @@ static void extend(worker_t* w, int sign, uint32_t ord, const uint32_t* pi, uint
     if (q->adj[u][pi[j]]) back[nb++] = pi[j];
   /* nb >= 1: the BFS order keeps every prefix connected */
   uint32_t a0 = f[back[0]];
+  const int any_el = sh->mutant == MUT_NO_EDGE_LABEL_CHECK;
   for (uint64_t t = H->rp[a0]; t < H->rp[a0 + 1]; ++t) {
-    uint32_t c = H->col[t];
+    uint32_t c = H->col[t] / sh->L, ce = H->col[t] % sh->L;
+    if (!any_el && ce != q->qel[u][back[0]]) continue;
     if (sh->mutant != MUT_NO_LABEL_CHECK && sh->labels[c] != q->qlab[u]) continue;
     if (sh->mutant != MUT_NO_INJECTIVITY) {
       int used = 0;
@@ -373,7 +398,9 @@ static void extend(worker_t* w, int sign, uint32_t ord, const uint32_t* pi, uint
     int ok = 1;
     for (uint32_t b = 0; b < nb && ok; ++b) {
       if (b == 0 && sh->mutant == MUT_SKIP_FIRST_CHECK) continue;
-      ok = edge_ok(sh, H, sign, ord, f[back[b]], c);
+      ok = edge_ok(sh, H, sign, ord, f[back[b]], c, b == 0 && any_el ? ce : q->qel[u][back[b]]);
+      for (uint32_t e2 = 0; any_el && b > 0 && !ok && e2 < sh->L; ++e2)
+        ok = edge_ok(sh, H, sign, ord, f[back[b]], c, e2);
     }
     if (!ok) continue;
     f[u] = c;
@@ -391,10 +418,11 @@ static void* worker_main(void* arg) {
     if (i >= sh->c->n) break;
     if (sh->sample_mod > 1 && i % sh->sample_mod != sh->sample_rem) continue;
     int sign = sh->c->sign[i];
-    uint32_t lo = sh->c->lo[i], hi = sh->c->hi[i];
+    uint32_t lo = sh->c->lo[i], hi = sh->c->hi[i], el = sh->c->e[i];
     for (uint32_t d = 0; d < q->n_dqe; ++d) {
       uint32_t x = q->dx[d], y = q->dy[d];
       if (sh->labels[lo] != q->qlab[x] || sh->labels[hi] != q->qlab[y]) continue;
+      if (sh->mutant != MUT_NO_EDGE_LABEL_CHECK && q->qel[x][y] != el) continue;
       f[x] = lo;
       f[y] = hi;
       extend(w, sign, i, q->order[d], 2, f);
@@ -423,25 +451,46 @@ static int bfs_order(const query_t* q, uint32_t x, uint32_t y, uint32_t* pi) {
 
 /* ---------------------------------------------------------------- API */
 
-int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* labels,
-           uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges,
-           uint32_t n_upd, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
-           int threads, uint32_t sample_mod, uint32_t sample_rem, int want_tuples, int mutant,
-           o2_result* res) {
+/* Row keys w * L + e of a CSR with per-entry edge labels (NULL: all 0),
+ * each row sorted; NULL if a label is >= L or n * L does not fit 32 bits. */
+static uint32_t* make_keys(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* elab,
+                           uint32_t L) {
+  if ((uint64_t)n * L > 0xFFFFFFFFull) return NULL;
+  const uint64_t nnz = row_ptr[n];
+  uint32_t* key = (uint32_t*)malloc(4 * (nnz ? nnz : 1));
+  for (uint64_t j = 0; j < nnz; ++j) {
+    const uint32_t e = elab ? elab[j] : 0;
+    if (e >= L) {
+      free(key);
+      return NULL;
+    }
+    key[j] = col[j] * L + e;
+  }
+  for (uint32_t v = 0; v < n; ++v) qsort(key + row_ptr[v], (size_t)(row_ptr[v + 1] - row_ptr[v]), 4, u32_cmp);
+  return key;
+}
+
+int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* labels,
+              uint32_t L, const uint32_t* elab, uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m,
+              const uint32_t* qedges, const uint32_t* qelab, uint32_t n_upd, const uint32_t* src,
+              const uint32_t* dst, const uint8_t* op, const uint32_t* uelab, int threads, uint32_t sample_mod,
+              uint32_t sample_rem, int want_tuples, int mutant, o2_result* res) {
   struct timespec t0, t1;
   clock_gettime(CLOCK_MONOTONIC, &t0);
   memset(res, 0, sizeof(*res));
-  if (k < 2 || k > 16 || m == 0 || m > 120) return -3;
+  if (k < 2 || k > 16 || m == 0 || m > 120 || L == 0) return -3;
   query_t* q = (query_t*)calloc(1, sizeof(query_t));
   q->k = k;
   q->qlab = qlabels;
   for (uint32_t e = 0; e < m; ++e) {
     uint32_t a = qedges[2 * e], b = qedges[2 * e + 1];
-    if (a >= k || b >= k || a == b) {
+    const uint32_t el = qelab ? qelab[e] : 0;
+    if (a >= k || b >= k || a == b || el >= L) {
       free(q);
       return -3;
     }
     q->adj[a][b] = q->adj[b][a] = 1;
+    q->qel[a][b] = q->qel[b][a] = el;
     q->dx[q->n_dqe] = a;
     q->dy[q->n_dqe] = b;
     q->n_dqe++;
@@ -457,13 +506,19 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
       return -3; /* disconnected query */
     }
 
-  csr_t G = {n, row_ptr, col};
+  uint32_t* key = make_keys(n, row_ptr, col, elab, L);
+  if (!key) {
+    free(q);
+    return -3;
+  }
+  csr_t G = {n, row_ptr, key};
   canon_t c;
   memset(&c, 0, sizeof(c));
-  int st = canonicalise(&G, n_upd, src, dst, op, mutant, &c, res);
+  int st = canonicalise(&G, L, n_upd, src, dst, op, uelab, mutant, &c, res);
   res->status = st;
   if (st != 0) {
     free(q);
+    free(key);
     return st;
   }
   res->n_canonical = c.n;
@@ -475,7 +530,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
   }
   uint64_t* rp2;
   uint32_t* col2;
-  build_updated(&G, &c, &rp2, &col2);
+  build_updated(&G, L, &c, &rp2, &col2);
   csr_t G2 = {n, rp2, col2};
 
   shared_t sh;
@@ -485,6 +540,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
   sh.c = &c;
   sh.labels = labels;
   sh.q = q;
+  sh.L = L;
   sh.qid = qid;
   sh.mutant = mutant;
   sh.want_tuples = want_tuples;
@@ -536,6 +592,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
   res->canon_lo = c.lo;
   res->canon_hi = c.hi;
   res->canon_sign = c.sign;
+  res->canon_e = c.e;
   res->seed_count = sh.seed_count;
   res->seed_hsum = sh.seed_hsum;
   res->seed_hxor = sh.seed_hxor;
@@ -544,28 +601,65 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
   free(th);
   free(rp2);
   free(col2);
+  free(key);
   free(q);
   clock_gettime(CLOCK_MONOTONIC, &t1);
   res->seconds = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
   return 0;
 }
 
-/* G' as a CSR for callers that chain batches (row_ptr n+1, col row_ptr[n]). */
-int o2_updated_graph(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint32_t n_upd,
-                     const uint32_t* src, const uint32_t* dst, const uint8_t* op,
-                     uint64_t** rp_out, uint32_t** col_out) {
-  csr_t G = {n, row_ptr, col};
+/* The unlabelled case: one edge label. */
+int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* labels,
+           uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges,
+           uint32_t n_upd, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+           int threads, uint32_t sample_mod, uint32_t sample_rem, int want_tuples, int mutant,
+           o2_result* res) {
+  return o2_run_el(n, row_ptr, col, labels, 1, NULL, qid, k, qlabels, m, qedges, NULL, n_upd, src, dst, op, NULL,
+                   threads, sample_mod, sample_rem, want_tuples, mutant, res);
+}
+
+/* G' as a CSR for callers that chain batches (row_ptr n+1; col and, when
+ * elab_out is not NULL, the edge labels, row_ptr[n] entries, each row
+ * ascending by (neighbour, label)). */
+int o2_updated_graph_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* elab,
+                        uint32_t L, uint32_t n_upd, const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+                        const uint32_t* uelab, uint64_t** rp_out, uint32_t** col_out, uint32_t** elab_out) {
+  if (L == 0) return -3;
+  uint32_t* key = make_keys(n, row_ptr, col, elab, L);
+  if (!key) return -3;
+  csr_t G = {n, row_ptr, key};
   canon_t c;
   memset(&c, 0, sizeof(c));
   o2_result tmp;
   memset(&tmp, 0, sizeof(tmp));
-  int st = canonicalise(&G, n_upd, src, dst, op, 0, &c, &tmp);
-  if (st != 0) return st;
-  build_updated(&G, &c, rp_out, col_out);
+  int st = canonicalise(&G, L, n_upd, src, dst, op, uelab, 0, &c, &tmp);
+  if (st != 0) {
+    free(key);
+    return st;
+  }
+  build_updated(&G, L, &c, rp_out, col_out);
+  const uint64_t nnz = (*rp_out)[n];
+  uint32_t* el = (uint32_t*)malloc(4 * (nnz ? nnz : 1));
+  for (uint64_t j = 0; j < nnz; ++j) {
+    el[j] = (*col_out)[j] % L;
+    (*col_out)[j] /= L;
+  }
+  if (elab_out)
+    *elab_out = el;
+  else
+    free(el);
+  free(key);
   free(c.lo);
   free(c.hi);
+  free(c.e);
   free(c.sign);
   return 0;
+}
+
+int o2_updated_graph(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, uint32_t n_upd,
+                     const uint32_t* src, const uint32_t* dst, const uint8_t* op,
+                     uint64_t** rp_out, uint32_t** col_out) {
+  return o2_updated_graph_el(n, row_ptr, col, NULL, 1, n_upd, src, dst, op, NULL, rp_out, col_out, NULL);
 }
 
 void o2_free_ptr(void* p) { free(p); }
@@ -577,6 +671,7 @@ void o2_free(o2_result* r) {
   free(r->canon_lo);
   free(r->canon_hi);
   free(r->canon_sign);
+  free(r->canon_e);
   free(r->seed_count);
   free(r->seed_hsum);
   free(r->seed_hxor);

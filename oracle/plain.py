@@ -23,6 +23,7 @@ _lib = None
 
 MUT_NONE, MUT_NO_INJECTIVITY, MUT_ONE_ORIENTATION, MUT_NO_ORDER_RULE = 0, 1, 2, 3
 MUT_DELETE_ON_GPRIME, MUT_SKIP_FIRST_CHECK, MUT_NO_LABEL_CHECK, MUT_KEEP_NOOPS = 4, 5, 6, 7
+MUT_NO_EDGE_LABEL_CHECK = 8
 
 
 class _Res(ctypes.Structure):
@@ -48,6 +49,7 @@ class _Res(ctypes.Structure):
         ("seed_hxor", ctypes.POINTER(ctypes.c_uint64)),
         ("seconds", ctypes.c_double),
         ("threads_used", ctypes.c_int32),
+        ("canon_e", ctypes.POINTER(ctypes.c_uint32)),
     ]
 
 
@@ -67,16 +69,17 @@ def _L():
         build_native(False)
         lib = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
-        lib.o2_run.restype = ctypes.c_int
-        lib.o2_run.argtypes = [ctypes.c_uint32, P, P, P, ctypes.c_uint32, ctypes.c_uint32, P, ctypes.c_uint32, P,
-                               ctypes.c_uint32, P, P, P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
-                               ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Res)]
+        u32 = ctypes.c_uint32
+        lib.o2_run_el.restype = ctypes.c_int
+        lib.o2_run_el.argtypes = [u32, P, P, P, u32, P, u32, u32, P, u32, P, P, u32, P, P, P, P, ctypes.c_int,
+                                  u32, u32, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Res)]
         lib.o2_free.restype = None
         lib.o2_free.argtypes = [ctypes.POINTER(_Res)]
-        lib.o2_updated_graph.restype = ctypes.c_int
-        lib.o2_updated_graph.argtypes = [ctypes.c_uint32, P, P, ctypes.c_uint32, P, P, P,
-                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64)),
-                                         ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32))]
+        lib.o2_updated_graph_el.restype = ctypes.c_int
+        lib.o2_updated_graph_el.argtypes = [u32, P, P, P, u32, u32, P, P, P, P,
+                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64)),
+                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32)),
+                                            ctypes.POINTER(ctypes.POINTER(ctypes.c_uint32))]
         lib.o2_free_ptr.restype = None
         lib.o2_free_ptr.argtypes = [P]
         lib.o2_tuple_hash.restype = ctypes.c_uint64
@@ -112,6 +115,7 @@ class O2Result:
     canon_lo: np.ndarray
     canon_hi: np.ndarray
     canon_sign: np.ndarray
+    canon_e: np.ndarray
     seed_count: np.ndarray
     seed_hsum: np.ndarray
     seed_hxor: np.ndarray
@@ -125,10 +129,27 @@ class O2Result:
         return {tuple(int(x) for x in row) for row in sel}
 
 
+def _labels_of(graph, query, batch):
+    """(L, per-entry, per-query-edge, per-update edge labels or None): edge
+    labels are optional attributes (elab, n_elabels; elabels; elab)."""
+    ge = getattr(graph, "elab", None)
+    L = int(getattr(graph, "n_elabels", 1) or 1)
+    qe = getattr(query, "elabels", None) if query is not None else None
+    be = getattr(batch, "elab", None)
+    as32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.uint32)
+    return L, as32(ge), as32(qe), as32(be)
+
+
+def _p(a):
+    return None if a is None or a.size == 0 else _ptr(a)
+
+
 def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1, sample_rem: int = 0,
         want_tuples: bool = True, mutant: int = MUT_NONE) -> O2Result:
-    """Run O2 on (graph, query, batch); graph/query/batch are workloads types."""
+    """Run O2 on (graph, query, batch); graph/query/batch are workloads types
+    (edge labels when they carry them)."""
     L = _L()
+    n_el, gel, qel, bel = _labels_of(graph, query, batch)
     rp = np.ascontiguousarray(graph.row_ptr, dtype=np.uint64)
     col = np.ascontiguousarray(graph.col, dtype=np.uint32)
     lab = np.ascontiguousarray(graph.labels, dtype=np.uint32)
@@ -145,9 +166,10 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
     else:
         n_upd = int(batch.src.shape[0])
     r = _Res()
-    rc = L.o2_run(graph.n, _ptr(rp), _ptr(col), _ptr(lab), qid, query.k, _ptr(ql), query.m, _ptr(qe),
-                  n_upd, _ptr(src), _ptr(dst), _ptr(op), int(threads), int(sample_mod), int(sample_rem),
-                  1 if want_tuples else 0, int(mutant), ctypes.byref(r))
+    rc = L.o2_run_el(graph.n, _ptr(rp), _ptr(col), _ptr(lab), n_el, _p(gel), qid, query.k, _ptr(ql), query.m,
+                     _ptr(qe), _p(qel), n_upd, _ptr(src), _ptr(dst), _ptr(op), _p(bel) if n_upd else None,
+                     int(threads), int(sample_mod), int(sample_rem), 1 if want_tuples else 0, int(mutant),
+                     ctypes.byref(r))
     if rc == -3:
         raise ValueError("query rejected by the oracle (k, edges or connectivity)")
     k = query.k
@@ -162,6 +184,7 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
         ord=(_arr(r.tord, nt, np.uint32) if want_tuples and rc == 0 else None),
         canon_lo=_arr(r.canon_lo, r.n_canonical, np.uint32), canon_hi=_arr(r.canon_hi, r.n_canonical, np.uint32),
         canon_sign=_arr(r.canon_sign, r.n_canonical, np.uint8),
+        canon_e=_arr(r.canon_e, r.n_canonical, np.uint32),
         seed_count=_arr(r.seed_count, r.n_canonical, np.uint64),
         seed_hsum=_arr(r.seed_hsum, r.n_canonical, np.uint64),
         seed_hxor=_arr(r.seed_hxor, r.n_canonical, np.uint64),
@@ -171,9 +194,11 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
     return out
 
 
-def updated_graph(graph, batch):
-    """G' after applying `batch` (canonical semantics), as (row_ptr, col)."""
+def updated_graph_el(graph, batch):
+    """G' after applying `batch` (canonical semantics), as (row_ptr, col,
+    elab); rows ascending by (neighbour, edge label)."""
     L = _L()
+    n_el, gel, _, bel = _labels_of(graph, None, batch)
     rp = np.ascontiguousarray(graph.row_ptr, dtype=np.uint64)
     col = np.ascontiguousarray(graph.col, dtype=np.uint32)
     if col.size == 0:
@@ -183,19 +208,27 @@ def updated_graph(graph, batch):
     op = np.ascontiguousarray(batch.op, dtype=np.uint8)
     n_upd = int(src.shape[0])
     if n_upd == 0:
-        return graph.row_ptr.copy(), graph.col.copy()
+        src = np.zeros(1, np.uint32); dst = np.zeros(1, np.uint32); op = np.zeros(1, np.uint8)
     prp = ctypes.POINTER(ctypes.c_uint64)()
     pcol = ctypes.POINTER(ctypes.c_uint32)()
-    rc = L.o2_updated_graph(graph.n, _ptr(rp), _ptr(col), n_upd, _ptr(src), _ptr(dst), _ptr(op),
-                            ctypes.byref(prp), ctypes.byref(pcol))
+    pel = ctypes.POINTER(ctypes.c_uint32)()
+    rc = L.o2_updated_graph_el(graph.n, _ptr(rp), _ptr(col), _p(gel), n_el, n_upd, _ptr(src), _ptr(dst), _ptr(op),
+                               _p(bel) if n_upd else None, ctypes.byref(prp), ctypes.byref(pcol), ctypes.byref(pel))
     if rc != 0:
         raise ValueError("invalid batch (status %d)" % rc)
     row_ptr = _arr(prp, graph.n + 1, np.uint64)
     nnz = int(row_ptr[-1])
     c = _arr(pcol, nnz, np.uint32)
-    L.o2_free_ptr(ctypes.cast(prp, ctypes.c_void_p))
-    L.o2_free_ptr(ctypes.cast(pcol, ctypes.c_void_p))
-    return row_ptr, c
+    el = _arr(pel, nnz, np.uint32)
+    for p in (prp, pcol, pel):
+        L.o2_free_ptr(ctypes.cast(p, ctypes.c_void_p))
+    return row_ptr, c, el
+
+
+def updated_graph(graph, batch):
+    """G' after applying `batch` (canonical semantics), as (row_ptr, col)."""
+    rp, col, _ = updated_graph_el(graph, batch)
+    return rp, col
 
 
 def tuple_hash(qid: int, sign: int, f) -> int:

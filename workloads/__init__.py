@@ -138,6 +138,8 @@ class Graph:
     col: np.ndarray  # uint32 [2m], ascending per row
     labels: np.ndarray  # uint32 [n]
     name: str = ""
+    elab: Optional[np.ndarray] = None  # uint32 [2m] edge label per CSR entry (None: unlabelled)
+    n_elabels: int = 1  # edge labels are < n_elabels
 
     @property
     def nnz(self) -> int:
@@ -173,6 +175,7 @@ class Query:
     edges: np.ndarray  # uint32 [m, 2]
     kind: str = ""
     planted: Optional[Tuple[int, ...]] = None  # a data-vertex tuple known to be in the + result
+    elabels: Optional[np.ndarray] = None  # uint32 [m] edge label per query edge (None: all 0)
 
     @property
     def m(self) -> int:
@@ -184,12 +187,14 @@ class Batch:
     src: np.ndarray  # uint32
     dst: np.ndarray  # uint32
     op: np.ndarray  # uint8, 1 = insertion, 0 = deletion
+    elab: Optional[np.ndarray] = None  # uint32 edge label per update (None: all 0)
 
     def __len__(self):
         return int(self.src.shape[0])
 
     def inverse(self) -> "Batch":
-        return Batch(self.src.copy(), self.dst.copy(), (1 - self.op).astype(np.uint8))
+        return Batch(self.src.copy(), self.dst.copy(), (1 - self.op).astype(np.uint8),
+                     None if self.elab is None else self.elab.copy())
 
 
 @dataclass
@@ -731,8 +736,49 @@ def batch_from_list(ups: Sequence[Tuple[str, int, int]]) -> Batch:
     return Batch(src, dst, op)
 
 
-def query_from_edges(k: int, edges: Sequence[Tuple[int, int]], labels: Sequence[int], kind: str = "") -> Query:
-    return Query(k, np.array(labels, dtype=np.uint32), np.array(edges, dtype=np.uint32).reshape(-1, 2), kind)
+def query_from_edges(k: int, edges: Sequence[Tuple[int, int]], labels: Sequence[int], kind: str = "",
+                     elabels: Optional[Sequence[int]] = None) -> Query:
+    return Query(k, np.array(labels, dtype=np.uint32), np.array(edges, dtype=np.uint32).reshape(-1, 2), kind,
+                 elabels=None if elabels is None else np.array(elabels, dtype=np.uint32))
+
+
+# --------------------------------------------------------------------------
+# edge labels
+
+
+def skewed_edge_label_draws(m: int, n_el: int, seed: int, skew: float = 1.0) -> np.ndarray:
+    """m labels in [0, n_el) with P(e) proportional to 1 / (e + 1)^skew (a
+    few frequent labels and a tail, as in edge-labelled graphs whose label
+    counts are highly uneven)."""
+    w = 1.0 / np.power(np.arange(1, n_el + 1, dtype=np.float64), skew)
+    cdf = np.cumsum(w / w.sum())
+    u = (Draws(seed, 0xE1AB).block(m) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    return np.minimum(np.searchsorted(cdf, u, side="right"), n_el - 1).astype(np.uint32)
+
+
+def with_edge_labels(g: Graph, n_el: int, seed: int, skew: float = 1.0) -> Graph:
+    """g with one label per undirected edge (both CSR entries carry it)."""
+    keys = g.edge_keys()
+    lab = skewed_edge_label_draws(len(keys), n_el, seed, skew)
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr).astype(np.int64))
+    dst = g.col.astype(np.uint64)
+    ek = (np.minimum(src, dst) << np.uint64(32)) | np.maximum(src, dst)
+    elab = lab[np.searchsorted(keys, ek)]
+    return Graph(g.n, g.row_ptr, g.col, g.labels, g.name, elab=elab, n_elabels=n_el)
+
+
+def graph_from_labelled_edges(n: int, triples: Sequence[Tuple[int, int, int]], labels: Sequence[int],
+                              n_el: int, name: str = "") -> Graph:
+    """CSR of labelled edges (u, v, e); a pair may carry several labels.
+    Rows ascend by (neighbour, label)."""
+    ent = sorted({(a, b, e) for (u, v, e) in triples for (a, b) in ((u, v), (v, u))})
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    for (a, _, _) in ent:
+        row_ptr[a + 1] += 1
+    row_ptr = np.cumsum(row_ptr).astype(np.uint64)
+    col = np.array([b for (_, b, _) in ent], dtype=np.uint32)
+    elab = np.array([e for (_, _, e) in ent], dtype=np.uint32)
+    return Graph(n, row_ptr, col, np.array(labels, dtype=np.uint32), name, elab=elab, n_elabels=n_el)
 
 
 def fingerprint(arr: np.ndarray) -> str:
