@@ -48,6 +48,9 @@
 extern "C" {
 #endif
 
+/* Edge labels are < GAMMA_MAX_EDGE_LABELS. */
+#define GAMMA_MAX_EDGE_LABELS 256u
+
 typedef enum gamma_status {
   GAMMA_OK = 0,
   GAMMA_TRUNCATED = 1,      /* success; tuple capacity reached, counts/hashes still exact */
@@ -193,6 +196,22 @@ gamma_status gamma_destroy(gamma_ctx* ctx);
 gamma_status gamma_load_graph(gamma_ctx* ctx, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
                               const uint32_t* col, const uint32_t* labels, gamma_mem where);
 
+/* Load an edge-labelled graph (Sec. II-A: the labelling function covers
+ * edges too).  As gamma_load_graph, plus
+ *   elabels    [nnz] uint32 < n_elabels, the label of each CSR entry (the
+ *              mirror entry carries the same label)
+ *   n_elabels  1 .. GAMMA_MAX_EDGE_LABELS
+ * The graph stays simple (one edge, with one label, per pair; rows ascend
+ * strictly as for gamma_load_graph).  A query edge with label e maps only
+ * onto data edges with label e.  Storage: one
+ * row per (vertex, label) (row id v << ceil(log2 n_elabels) | e), so device
+ * memory for row offsets and the label index grows with n * n_elabels; n
+ * times the power of two above n_elabels must stay below 2^31 (else
+ * EUNSUPPORTED).  gamma_load_graph is this call with one label. */
+gamma_status gamma_load_graph_el(gamma_ctx* ctx, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                 const uint32_t* col, const uint32_t* labels, const uint32_t* elabels,
+                                 uint32_t n_elabels, gamma_mem where);
+
 /* Register a standing query (host arrays).
  *   k        vertices, 2 <= k <= 16
  *   qlabels  [k] labels < 65536
@@ -205,6 +224,12 @@ gamma_status gamma_load_graph(gamma_ctx* ctx, uint32_t n, uint64_t nnz, const ui
  * ENOMEM, EDEVICE.  *out_qid receives the query id (0, 1, ...). */
 gamma_status gamma_register_query(gamma_ctx* ctx, uint32_t k, const uint32_t* qlabels, uint32_t m,
                                   const uint32_t* qedges, uint32_t* out_qid);
+
+/* As gamma_register_query with qelabels [m] < GAMMA_MAX_EDGE_LABELS, the
+ * label of each query edge (NULL: all 0).  A query with an edge label the
+ * loaded graph does not have (>= its n_elabels) matches nothing. */
+gamma_status gamma_register_query_el(gamma_ctx* ctx, uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                     const uint32_t* qedges, const uint32_t* qelabels, uint32_t* out_qid);
 
 /* Apply one batch and report its incremental matches for every registered
  * query (the problem statement of Sec. II-A; Algorithm 1 of Sec. IV-C).
@@ -226,6 +251,19 @@ gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* s
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);
 
+/* As gamma_apply_batch on an edge-labelled graph: update i names the
+ * triple {src[i], dst[i], elab[i]} (elab NULL: all 0; a label >= n_elabels
+ * gives EINVAL).  Two updates of one pair in a batch must name the same
+ * triple with the same op (a duplicate), else ECONFLICT; so a pair occurs
+ * at most once in the canonical batch and ord is its rank by (lo, hi).
+ * Inserting a present triple or deleting an absent one (also a present pair
+ * under another label) is a no-op; inserting a pair that is present under
+ * another label gives EINVAL (relabelling takes a deletion and a later
+ * insertion). */
+gamma_status gamma_apply_batch_el(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                  const uint8_t* op, const uint32_t* elab, gamma_mem where, uint32_t flags,
+                                  gamma_batch_result* out);
+
 /* Vertex updates (Sec. II-A, the batch-dynamic setting): a vertex deletion
  * is the deletion of all of its incident edges; a vertex insertion adds the
  * vertex first, its edges then come as edge insertions.
@@ -238,16 +276,18 @@ gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* s
  * per-update attribution, whose canonical order covers the expanded edges
  * too).  The vertex keeps its id and label and is isolated afterwards.
  *   src,dst,op,n_upd  explicit edge updates as for gamma_apply_batch
+ *   elab              their edge labels as for gamma_apply_batch_el (may be
+ *                     NULL); expanded deletions carry each edge's own label
  *   vdel,n_vdel       vertices to delete, n_vdel <= 2^20
- *   where             memory kind of all five arrays
+ *   where             memory kind of all six arrays
  * Errors: EINVAL (an id >= n, null arrays, more than 2^20 updates after the
  * expansion), ECONFLICT (an explicit insertion touches a deleted vertex, or
  * the rules of gamma_apply_batch), and those of gamma_apply_batch.  Any
  * error leaves the graph unchanged. */
 gamma_status gamma_apply_batch_vertices(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
-                                        const uint32_t* dst, const uint8_t* op, uint32_t n_vdel,
-                                        const uint32_t* vdel, gamma_mem where, uint32_t flags,
-                                        gamma_batch_result* out);
+                                        const uint32_t* dst, const uint8_t* op, const uint32_t* elab,
+                                        uint32_t n_vdel, const uint32_t* vdel, gamma_mem where,
+                                        uint32_t flags, gamma_batch_result* out);
 
 /* Append `count` isolated vertices with host labels[count] (< 2^16); they
  * get the external ids n, n+1, ... (*first_id = n, may be NULL).  The graph
@@ -369,6 +409,11 @@ gamma_status gamma_result_release(gamma_ctx* ctx, gamma_batch_result* res);
  * with col == NULL: *n_out and *nnz_out are always written. */
 gamma_status gamma_export_graph(gamma_ctx* ctx, uint32_t* n_out, uint64_t* nnz_out,
                                 uint64_t* row_ptr, uint32_t* col, uint32_t* labels);
+
+/* As gamma_export_graph, plus *n_elabels_out and elabels [nnz] (each row
+ * ascending by (neighbour, label)); any output may be NULL. */
+gamma_status gamma_export_graph_el(gamma_ctx* ctx, uint32_t* n_out, uint64_t* nnz_out, uint32_t* n_elabels_out,
+                                   uint64_t* row_ptr, uint32_t* col, uint32_t* labels, uint32_t* elabels);
 
 /* Host-only validators (no device needed); same rules as the calls above. */
 gamma_status gamma_validate_graph(uint32_t n, uint64_t nnz, const uint64_t* row_ptr,

@@ -119,10 +119,11 @@ def bdsm(graph, query, batch) -> dict:
 #
 # Sec. II-A lets the labelling function cover edges too.  A data edge is then
 # a triple (lo, hi, e); a query edge (a, b) with label e maps onto the data
-# edge {f(a), f(b)} with label e.  One pair may carry edges of several
-# labels.  An update names a triple; two updates of the same pair in one
-# batch must be the same triple and op (a duplicate), otherwise the batch is
-# a conflict.
+# edge {f(a), f(b)} with label e.  The graph stays simple: one edge, with one
+# label, per pair.  An update names a triple; two updates of the same pair in
+# one batch must be the same triple and op (a duplicate), otherwise the
+# batch is a conflict; inserting a pair present under another label is
+# invalid; deleting a triple whose pair has another label is a no-op.
 
 
 def edge_set_el(graph) -> Set[Tuple[int, int, int]]:
@@ -154,8 +155,11 @@ def canonical_el(n: int, n_el: int, edges: Set[Tuple[int, int, int]], ups):
             continue
         seen[pair] = (op, e)
     I, D, n_noop = [], [], 0
+    pair_label = {(lo, hi): e for (lo, hi, e) in edges}
     for (lo, hi), (op, e) in seen.items():
         present = (lo, hi, e) in edges
+        if op == 1 and not present and (lo, hi) in pair_label:
+            return "invalid", [], [], 0, 0
         if op == 1 and not present:
             I.append((lo, hi, e))
         elif op == 0 and present:

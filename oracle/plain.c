@@ -24,12 +24,14 @@
  * Edge labels (Sec. II-A: the labelling function also covers edges): every
  * data edge, query edge and update carries a label in [0, L), L = 1 for an
  * unlabelled graph.  A query edge (u, w) with label e maps onto a data edge
- * {f(u), f(w)} with label e.  Data edges are the triples {v, w, e}; one
- * pair may hold edges of several labels.  An update names its triple; two
+ * {f(u), f(w)} with label e.  The graph stays simple: a pair holds at most
+ * one edge, with one label.  An update names its triple {u, v, e}; two
  * updates of one pair in a batch must be the same triple with the same op
- * (duplicates) or the batch is rejected as conflicting.  Internally a row
- * holds keys w * L + e in ascending order, so with L = 1 the key is the
- * neighbour itself.
+ * (duplicates) or the batch is rejected as conflicting; inserting a pair
+ * that is present under another label is rejected as invalid (relabelling
+ * takes a deletion and a later insertion); deleting a triple whose pair
+ * has another label is a no-op.  Internally a row holds keys w * L + e in
+ * ascending order, so with L = 1 the key is the neighbour itself.
  *
  * How (Sec. IV-C, Algorithm 1 and the order rule that follows it):
  *   every update edge e_i of a pass carries ord i = its rank in ascending
@@ -123,6 +125,19 @@ typedef struct {
   const uint32_t* col; /* keys w * L + e, ascending per row */
 } csr_t;
 
+/* Does row u hold a key in [k0, k1)? */
+static int row_has_range(const csr_t* g, uint32_t u, uint32_t k0, uint32_t k1) {
+  uint64_t lo = g->rp[u], hi = g->rp[u + 1];
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (g->col[mid] < k0)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < g->rp[u + 1] && g->col[lo] < k1;
+}
+
 static int row_has(const csr_t* g, uint32_t u, uint32_t v) {
   uint64_t lo = g->rp[u], hi = g->rp[u + 1];
   while (lo < hi) {
@@ -210,6 +225,10 @@ static int canonicalise(const csr_t* g, uint32_t L, uint32_t n_upd, const uint32
       continue;
     }
     int present = row_has(g, u[i].lo, u[i].hi * L + u[i].e);
+    if (u[i].op && !present && row_has_range(g, u[i].lo, u[i].hi * L, u[i].hi * L + L)) {
+      free(u); /* the pair is present under another label */
+      return -1;
+    }
     int noop = u[i].op ? present : !present;
     if (noop && mutant != MUT_KEEP_NOOPS) {
       res->n_noop++;
@@ -452,7 +471,8 @@ static int bfs_order(const query_t* q, uint32_t x, uint32_t y, uint32_t* pi) {
 /* ---------------------------------------------------------------- API */
 
 /* Row keys w * L + e of a CSR with per-entry edge labels (NULL: all 0),
- * each row sorted; NULL if a label is >= L or n * L does not fit 32 bits. */
+ * each row sorted; NULL if a label is >= L, n * L does not fit 32 bits or
+ * a row names one neighbour twice. */
 static uint32_t* make_keys(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint32_t* elab,
                            uint32_t L) {
   if ((uint64_t)n * L > 0xFFFFFFFFull) return NULL;
@@ -466,7 +486,14 @@ static uint32_t* make_keys(uint32_t n, const uint64_t* row_ptr, const uint32_t* 
     }
     key[j] = col[j] * L + e;
   }
-  for (uint32_t v = 0; v < n; ++v) qsort(key + row_ptr[v], (size_t)(row_ptr[v + 1] - row_ptr[v]), 4, u32_cmp);
+  for (uint32_t v = 0; v < n; ++v) {
+    qsort(key + row_ptr[v], (size_t)(row_ptr[v + 1] - row_ptr[v]), 4, u32_cmp);
+    for (uint64_t j = row_ptr[v] + 1; j < row_ptr[v + 1]; ++j)
+      if (key[j] / L == key[j - 1] / L) { /* two edges on one pair: not a simple graph */
+        free(key);
+        return NULL;
+      }
+  }
   return key;
 }
 

@@ -23,16 +23,17 @@ import numpy as np
 
 
 class _Batch:
-    def __init__(self, src, dst, op):
-        self.src, self.dst, self.op = src, dst, op
+    def __init__(self, src, dst, op, elab=None):
+        self.src, self.dst, self.op, self.elab = src, dst, op, elab
 
     def __len__(self):
         return int(self.src.shape[0])
 
 
 class _Graph:
-    def __init__(self, n, row_ptr, col, labels):
+    def __init__(self, n, row_ptr, col, labels, elab=None, n_elabels=1):
         self.n, self.row_ptr, self.col, self.labels = n, row_ptr, col, labels
+        self.elab, self.n_elabels = elab, n_elabels
 
     def neighbors(self, v: int) -> np.ndarray:
         return self.col[int(self.row_ptr[v]):int(self.row_ptr[v + 1])]
@@ -40,9 +41,10 @@ class _Graph:
 
 def deletion_batch(graph, batch, vdel) -> Tuple[str, object]:
     """(status, merged batch): the explicit updates followed by one deletion
-    (v, w) for every neighbour w of every v in vdel, in G.  status is "ok",
-    "invalid" (an id >= n) or "conflict" (an explicit insertion touches a
-    deleted vertex)."""
+    (v, w) for every neighbour w of every v in vdel, in G (on an
+    edge-labelled graph, with the label of that edge: one deletion per
+    labelled edge).  status is "ok", "invalid" (an id >= n) or "conflict"
+    (an explicit insertion touches a deleted vertex)."""
     vdel = [int(v) for v in np.asarray(vdel).ravel()]
     if any(v < 0 or v >= graph.n for v in vdel):
         return "invalid", None
@@ -50,15 +52,22 @@ def deletion_batch(graph, batch, vdel) -> Tuple[str, object]:
     for s, d, o in zip(batch.src.tolist(), batch.dst.tolist(), batch.op.tolist()):
         if o == 1 and (s in dead or d in dead):
             return "conflict", None
-    src, dst = [], []
+    gel = getattr(graph, "elab", None)
+    src, dst, el = [], [], []
     for v in vdel:  # duplicates in vdel give duplicate deletions, which collapse
-        for w in graph.col[int(graph.row_ptr[v]):int(graph.row_ptr[v + 1])].tolist():
+        a, b = int(graph.row_ptr[v]), int(graph.row_ptr[v + 1])
+        for j in range(a, b):
             src.append(v)
-            dst.append(w)
+            dst.append(int(graph.col[j]))
+            el.append(int(gel[j]) if gel is not None else 0)
     m = len(src)
     out = _Batch(np.concatenate([np.asarray(batch.src, np.uint32), np.array(src, np.uint32)]),
                  np.concatenate([np.asarray(batch.dst, np.uint32), np.array(dst, np.uint32)]),
                  np.concatenate([np.asarray(batch.op, np.uint8), np.zeros(m, np.uint8)]))
+    if gel is not None:
+        bel = getattr(batch, "elab", None)
+        bel = np.zeros(len(batch), np.uint32) if bel is None else np.asarray(bel, np.uint32)
+        out.elab = np.concatenate([bel, np.array(el, np.uint32)])
     return "ok", out
 
 
@@ -67,5 +76,7 @@ def with_vertices(graph, labels):
     labels = np.asarray(labels, dtype=np.uint32).ravel()
     nnz = int(graph.row_ptr[-1])
     rp = np.concatenate([np.asarray(graph.row_ptr, np.uint64), np.full(len(labels), nnz, np.uint64)])
+    gel = getattr(graph, "elab", None)
     return _Graph(graph.n + len(labels), rp, np.asarray(graph.col, np.uint32).copy(),
-                  np.concatenate([np.asarray(graph.labels, np.uint32), labels]))
+                  np.concatenate([np.asarray(graph.labels, np.uint32), labels]),
+                  None if gel is None else np.asarray(gel, np.uint32).copy(), getattr(graph, "n_elabels", 1))

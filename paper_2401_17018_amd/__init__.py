@@ -142,46 +142,67 @@ class Context:
 
     # ------------------------------------------------------------------ calls
 
-    def load_graph(self, row_ptr, col, labels):
+    def load_graph(self, row_ptr, col, labels, elabels=None, n_elabels: int = 0):
+        """Load a CSR graph; elabels (one per CSR entry, < n_elabels; default
+        max + 1) makes it edge-labelled (gamma_load_graph_el)."""
         rp, k1, w1 = _arg(row_ptr, np.uint64)
         cl, k2, w2 = _arg(col, np.uint32)
         lb, k3, w3 = _arg(labels, np.uint32)
-        if len({w1, w2, w3}) != 1:
-            raise ValueError("row_ptr, col and labels must all be host arrays or all device tensors")
+        ws = {w1, w2, w3}
+        if elabels is not None:
+            el, k4, w4 = _arg(elabels, np.uint32)
+            ws.add(w4)
+        if len(ws) != 1:
+            raise ValueError("row_ptr, col, labels (and elabels) must all be host arrays or all device tensors")
         n = int(k3.shape[0])
         nnz = int(k2.shape[0])
-        _check(self._lib, self._ptr, self._lib.gamma_load_graph(self._ptr, n, nnz, rp, cl if nnz else None, lb, w1),
-               "load_graph")
-        self._sig = hashlib.sha256(b"graph n=%d nnz=%d" % (n, nnz))
+        if elabels is None:
+            _check(self._lib, self._ptr,
+                   self._lib.gamma_load_graph(self._ptr, n, nnz, rp, cl if nnz else None, lb, w1), "load_graph")
+        else:
+            if not n_elabels:
+                n_elabels = int(np.asarray(k4).max()) + 1 if nnz else 1
+            _check(self._lib, self._ptr,
+                   self._lib.gamma_load_graph_el(self._ptr, n, nnz, rp, cl if nnz else None, lb, el if nnz else None,
+                                                 int(n_elabels), w1), "load_graph")
+        self._sig = hashlib.sha256(b"graph n=%d nnz=%d el=%d" % (n, nnz, int(n_elabels or 1)))
         for q in getattr(self, "_queries", []):
             self._sig.update(q)
 
-    def register_query(self, k: int, labels, edges) -> int:
+    def register_query(self, k: int, labels, edges, elabels=None) -> int:
+        """Register a standing query; elabels: one label per edge."""
         ql = np.ascontiguousarray(np.asarray(labels), dtype=np.uint32)
         qe = np.ascontiguousarray(np.asarray(edges), dtype=np.uint32).reshape(-1)
+        qel = None if elabels is None else np.ascontiguousarray(np.asarray(elabels), dtype=np.uint32)
         qid = ctypes.c_uint32()
         _check(self._lib, self._ptr,
-               self._lib.gamma_register_query(self._ptr, int(k), ql.ctypes.data_as(ctypes.c_void_p),
-                                              int(qe.shape[0] // 2), qe.ctypes.data_as(ctypes.c_void_p),
-                                              ctypes.byref(qid)),
+               self._lib.gamma_register_query_el(self._ptr, int(k), ql.ctypes.data_as(ctypes.c_void_p),
+                                                 int(qe.shape[0] // 2), qe.ctypes.data_as(ctypes.c_void_p),
+                                                 qel.ctypes.data_as(ctypes.c_void_p) if qel is not None else None,
+                                                 ctypes.byref(qid)),
                "register_query")
         self.query_k.append(int(k))
-        qsig = b"query k=%d " % int(k) + ql.tobytes() + qe.tobytes()
+        qsig = b"query k=%d " % int(k) + ql.tobytes() + qe.tobytes() + (qel.tobytes() if qel is not None else b"")
         self._queries = getattr(self, "_queries", []) + [qsig]
         self._sig.update(qsig)
         return int(qid.value)
 
     def apply_batch(self, src, dst, op, hash: bool = True, tuples: bool = False, seed_attr: bool = False,
                     per_update: bool = False, canonical: bool = False, dry_run: bool = False,
-                    delete_vertices=None) -> BatchOutput:
+                    delete_vertices=None, elab=None) -> BatchOutput:
         """Apply one batch (dry_run: search it without committing it).
 
         delete_vertices: ids whose incident edges are all deleted in the same
-        batch, appended after the explicit updates (gamma_apply_batch_vertices)."""
+        batch, appended after the explicit updates (gamma_apply_batch_vertices).
+        elab: the edge label of each update (edge-labelled graphs)."""
         s, k1, w1 = _arg(src, np.uint32)
         d, k2, w2 = _arg(dst, np.uint32)
         o, k3, w3 = _arg(op, np.uint8)
         ws = {w1, w2, w3}
+        el = None
+        if elab is not None:
+            el, k5, w5 = _arg(elab, np.uint32)
+            ws.add(w5)
         if delete_vertices is not None:
             vd, k4, w4 = _arg(delete_vertices, np.uint32)
             ws.add(w4)
@@ -197,13 +218,14 @@ class Context:
         flags |= F_DRY_RUN if dry_run else 0
         res = capi.BatchResult()
         if delete_vertices is None:
-            st = self._lib.gamma_apply_batch(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
-                                             o if n_upd else None, w1, flags, ctypes.byref(res))
+            st = self._lib.gamma_apply_batch_el(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                                o if n_upd else None, el if n_upd else None, w1, flags,
+                                                ctypes.byref(res))
         else:
             nv = int(k4.shape[0])
             st = self._lib.gamma_apply_batch_vertices(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
-                                                      o if n_upd else None, nv, vd if nv else None, w1, flags,
-                                                      ctypes.byref(res))
+                                                      o if n_upd else None, el if n_upd else None, nv,
+                                                      vd if nv else None, w1, flags, ctypes.byref(res))
         if st == capi.GAMMA_ETIMEDOUT:
             err = GammaError(st, "apply_batch: %s" % (self._lib.gamma_last_error(self._ptr) or b"").decode())
             err.stats = {name: getattr(res.stats, name) for name, _ in capi.BatchStats._fields_
@@ -341,6 +363,22 @@ class Context:
                                             lab.ctypes.data_as(ctypes.c_void_p)),
                "export_graph")
         return rp, col[: nnz.value], lab
+
+    def export_graph_el(self):
+        """(row_ptr, col, labels, elabels, n_elabels) of the current graph."""
+        n, nnz, nel = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+        _check(self._lib, self._ptr,
+               self._lib.gamma_export_graph_el(self._ptr, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nel),
+                                               None, None, None, None), "export_graph")
+        rp = np.zeros(n.value + 1, dtype=np.uint64)
+        col = np.zeros(max(nnz.value, 1), dtype=np.uint32)
+        el = np.zeros(max(nnz.value, 1), dtype=np.uint32)
+        lab = np.zeros(n.value, dtype=np.uint32)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(self._lib, self._ptr,
+               self._lib.gamma_export_graph_el(self._ptr, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nel),
+                                               ptr(rp), ptr(col), ptr(lab), ptr(el)), "export_graph")
+        return rp, col[: nnz.value], lab, el[: nnz.value], int(nel.value)
 
 
 class Server:

@@ -16,6 +16,7 @@
 #define GM_ERR_SELFLOOP 2u
 #define GM_ERR_CONFLICT 4u   // +e and -e in one batch
 #define GM_ERR_CSR 8u        // malformed CSR (order, symmetry, offsets)
+#define GM_ERR_RELABEL 16u   // an inserted pair is present under another edge label
 
 // Flags of the search kernel (mirror the public GAMMA_F_* values).
 #define GM_F_HASH 2u
@@ -44,6 +45,7 @@ struct alignas(16) GmPlan {
   // is the identity).  n_perm = 0: a plan other plans stand for.
   uint32_t n_perm;
   uint32_t perm_base;
+  uint32_t el;  // edge label of the query edge (x, y) (0 without edge labels)
 };
 
 #define GM_MAX_PERM 16
@@ -64,10 +66,13 @@ struct GmQueryDev {
 };
 
 // Candidate-filter requirement list entry: query vertex (q, u) of a given
-// label needs at least `cnt` neighbours of label `lab`.
+// label needs at least `cnt` neighbours of label `lab` through edges of
+// label `el`.
 struct GmReq {
   uint16_t lab;
   uint16_t cnt;
+  uint16_t el;
+  uint16_t pad;
 };
 struct GmFilterEntry {
   uint32_t q;

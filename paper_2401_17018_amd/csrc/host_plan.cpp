@@ -82,17 +82,24 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
   };
   q.plans.clear();
   std::vector<std::pair<uint32_t, uint32_t>> dirs;
-  for (auto& e : q.edges) {
+  std::vector<uint32_t> dir_el;
+  for (size_t i = 0; i < q.edges.size(); ++i) {
+    const auto& e = q.edges[i];
+    const uint32_t el = i < q.elabels.size() ? q.elabels[i] : 0u;
     dirs.push_back({e.first, e.second});
     dirs.push_back({e.second, e.first});
+    dir_el.push_back(el);
+    dir_el.push_back(el);
   }
-  for (auto& d : dirs) {
+  for (size_t di = 0; di < dirs.size(); ++di) {
+    const auto& d = dirs[di];
     GmPlan p;
     std::memset(&p, 0, sizeof(p));
     p.k = k;
     p.x = d.first;
     p.y = d.second;
     p.q = qindex;
+    p.el = dir_el[di];
     uint32_t matched = (1u << d.first) | (1u << d.second);
     p.order[0] = d.first;
     p.order[1] = d.second;
@@ -143,13 +150,18 @@ namespace {
 
 // Label-preserving automorphisms of q (sigma[i] = image of query vertex i),
 // by backtracking: an image must agree in label and degree with the vertex
-// and in adjacency to every vertex mapped before it.  Stops after `cap`.
+// and in adjacency, and edge label, to every vertex mapped before it.
+// Stops after `cap`.
 void automorphisms(const HostQuery& q, size_t cap, std::vector<std::vector<uint32_t>>& out) {
   const uint32_t k = q.k;
   std::vector<uint32_t> adj(k, 0), deg(k, 0), m(k, 0);
-  for (auto& e : q.edges) {
+  std::vector<uint32_t> el(GM_MAX_K * GM_MAX_K, 0);
+  for (size_t i = 0; i < q.edges.size(); ++i) {
+    const auto& e = q.edges[i];
     adj[e.first] |= 1u << e.second;
     adj[e.second] |= 1u << e.first;
+    const uint32_t l = i < q.elabels.size() ? q.elabels[i] : 0u;
+    el[e.first * GM_MAX_K + e.second] = el[e.second * GM_MAX_K + e.first] = l;
   }
   for (uint32_t u = 0; u < k; ++u) deg[u] = (uint32_t)__builtin_popcount(adj[u]);
   uint32_t used = 0;
@@ -161,7 +173,10 @@ void automorphisms(const HostQuery& q, size_t cap, std::vector<std::vector<uint3
     for (uint32_t c = 0; c < k; ++c) {
       if (((used >> c) & 1u) || q.labels[c] != q.labels[i] || deg[c] != deg[i]) continue;
       bool ok = true;
-      for (uint32_t j = 0; j < i && ok; ++j) ok = ((adj[i] >> j) & 1u) == ((adj[c] >> m[j]) & 1u);
+      for (uint32_t j = 0; j < i && ok; ++j) {
+        ok = ((adj[i] >> j) & 1u) == ((adj[c] >> m[j]) & 1u);
+        if (ok && ((adj[i] >> j) & 1u)) ok = el[i * GM_MAX_K + j] == el[c * GM_MAX_K + m[j]];
+      }
       if (!ok) continue;
       m[i] = c;
       used |= 1u << c;
@@ -240,10 +255,13 @@ void build_filter_tables(const std::vector<HostQuery>& qs, uint32_t label_slots,
   reqs.clear();
   for (uint32_t qi = 0; qi < qs.size(); ++qi) {
     const HostQuery& q = qs[qi];
-    std::vector<std::map<uint32_t, uint32_t>> need(q.k);
-    for (auto& e : q.edges) {
-      need[e.first][q.labels[e.second]]++;
-      need[e.second][q.labels[e.first]]++;
+    // per query vertex: neighbours needed per (edge label, vertex label)
+    std::vector<std::map<std::pair<uint32_t, uint32_t>, uint32_t>> need(q.k);
+    for (size_t i = 0; i < q.edges.size(); ++i) {
+      const auto& e = q.edges[i];
+      const uint32_t el = i < q.elabels.size() ? q.elabels[i] : 0u;
+      need[e.first][{el, q.labels[e.second]}]++;
+      need[e.second][{el, q.labels[e.first]}]++;
     }
     for (uint32_t u = 0; u < q.k; ++u) {
       uint32_t lab = q.labels[u];
@@ -253,7 +271,8 @@ void build_filter_tables(const std::vector<HostQuery>& qs, uint32_t label_slots,
       fe.u = u;
       fe.req_off = (uint32_t)reqs.size();
       fe.req_n = (uint32_t)need[u].size();
-      for (auto& kv : need[u]) reqs.push_back(GmReq{(uint16_t)kv.first, (uint16_t)kv.second});
+      for (auto& kv : need[u])
+        reqs.push_back(GmReq{(uint16_t)kv.first.second, (uint16_t)kv.second, (uint16_t)kv.first.first, 0});
       per_label[lab].push_back(fe);
     }
   }
@@ -264,7 +283,7 @@ void build_filter_tables(const std::vector<HostQuery>& qs, uint32_t label_slots,
     for (auto& fe : per_label[l]) entries.push_back(fe);
   }
   lab_fstart[label_slots] = (uint32_t)entries.size();
-  if (reqs.empty()) reqs.push_back(GmReq{0, 0});
+  if (reqs.empty()) reqs.push_back(GmReq{0, 0, 0, 0});
   if (entries.empty()) entries.push_back(GmFilterEntry{0, 0, 0, 0});
 }
 

@@ -15,6 +15,7 @@ struct HostQuery {
   uint32_t k = 0;
   std::vector<uint32_t> labels;                       // [k]
   std::vector<std::pair<uint32_t, uint32_t>> edges;   // undirected, as given
+  std::vector<uint32_t> elabels;                      // [m] edge label per edge (0 without labels)
   std::vector<GmPlan> plans;                          // one per directed edge
   std::vector<GmPerm> perms;                          // coalesced search, referenced by plans
 };

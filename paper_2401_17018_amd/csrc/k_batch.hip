@@ -5,7 +5,13 @@
 // are rejected and no-ops (+e with e in E, -e with e not in E) are skipped.
 // The survivors get ord = rank in ascending (lo, hi) order, the total order
 // that the rule after Algorithm 1 (Sec. IV-C) needs.  The batch hash maps an
-// undirected internal edge to (ord, sign).
+// undirected internal edge to (ord, sign).  With edge labels an update
+// names (lo, hi, e): the key holds e between the pair and the op, two
+// updates of one pair must agree in e and op (else the batch conflicts), so
+// a pair occurs at most once in the canonical batch and the hash stays keyed
+// by the pair; presence is tested in the row of label e, and the directed
+// entries go to rows (v << elb) | e.  The graph stays simple: inserting a
+// pair that is present under another label is an error.
 //
 // Delta-merge (the update step of Sec. IV-A): every touched row is written
 // twice into fresh arena space: R1 = the row of G u I with batch entries
@@ -31,12 +37,14 @@ __device__ inline uint64_t lb_row(const uint32_t* col, uint64_t a, uint64_t len,
 }
 
 __global__ void k_canon_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
-                             const uint8_t* __restrict__ op, uint32_t n_upd, uint32_t n, int eb,
-                             uint64_t* __restrict__ keys, GmCounters* ctr) {
+                             const uint8_t* __restrict__ op, const uint32_t* __restrict__ elab, uint32_t n_upd,
+                             uint32_t n, int eb, uint32_t elb, uint32_t n_el, uint64_t* __restrict__ keys,
+                             GmCounters* ctr) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_upd; i += gridDim.x * blockDim.x) {
     uint32_t s = src[i], d = dst[i];
+    const uint32_t el = elab ? elab[i] : 0u;
     uint32_t e = 0;
-    if (s >= n || d >= n) e |= GM_ERR_RANGE;
+    if (s >= n || d >= n || el >= n_el) e |= GM_ERR_RANGE;
     if (s == d) e |= GM_ERR_SELFLOOP;
     if (e) {
       atomicOr(&ctr->err, e);
@@ -44,28 +52,40 @@ __global__ void k_canon_keys(const uint32_t* __restrict__ src, const uint32_t* _
       continue;
     }
     uint64_t lo = s < d ? s : d, hi = s < d ? d : s;
-    keys[i] = (lo << (eb + 1)) | (hi << 1) | (uint64_t)(op[i] ? 1 : 0);
+    keys[i] = (((((lo << eb) | hi) << elb) | el) << 1) | (uint64_t)(op[i] ? 1 : 0);
   }
 }
 
 __global__ void k_canon_classify(const uint64_t* __restrict__ keys, uint32_t n_upd, int eb,
                                  GmGraphDev G, uint32_t* __restrict__ keep, GmCounters* ctr) {
+  const uint32_t elb = G.elb;
+  const uint64_t tail = (2ull << elb) - 1;  // label and op bits
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_upd; j += gridDim.x * blockDim.x) {
     uint64_t key = keys[j];
-    uint64_t pair = key >> 1;
+    uint64_t pair = key >> (elb + 1);
     uint32_t op = (uint32_t)(key & 1);
     uint32_t k = 0;
-    if (j > 0 && (keys[j - 1] >> 1) == pair) {
-      if ((uint32_t)(keys[j - 1] & 1) != op)
+    if (j > 0 && (keys[j - 1] >> (elb + 1)) == pair) {
+      if ((keys[j - 1] & tail) != (key & tail))
         atomicOr(&ctr->err, GM_ERR_CONFLICT);
       else
         atomicAdd(&ctr->n_dup, 1u);
     } else {
       uint32_t lo = (uint32_t)(pair >> eb), hi = (uint32_t)(pair & ((1ull << eb) - 1));
       uint32_t a = G.new_of_old[lo], b = G.new_of_old[hi];
-      uint64_t off = G.row_off[a], len = G.row_len[a];
+      const uint32_t ra = (a << elb) | (uint32_t)((key >> 1) & ((1ull << elb) - 1));
+      uint64_t off = G.row_off[ra], len = G.row_len[ra];
       uint64_t p = lb_row(G.col, off, len, b);
       bool present = p < len && (G.col[off + p] & GM_IDMASK) == b;
+      // the graph stays simple: an insertion of a pair that another label's
+      // row already holds is rejected
+      for (uint32_t e2 = 0; op && !present && elb && e2 < G.n_el; ++e2) {
+        const uint32_t r2 = (a << elb) | e2;
+        if (r2 == ra) continue;
+        const uint64_t o2 = G.row_off[r2], l2 = G.row_len[r2];
+        const uint64_t p2 = lb_row(G.col, o2, l2, b);
+        if (p2 < l2 && (G.col[o2 + p2] & GM_IDMASK) == b) atomicOr(&ctr->err, GM_ERR_RELABEL);
+      }
       bool noop = op ? present : !present;
       if (noop)
         atomicAdd(&ctr->n_noop, 1u);
@@ -93,15 +113,17 @@ __global__ void k_canon_emit(const uint64_t* __restrict__ keys, const uint32_t* 
                              const uint32_t* __restrict__ ords, uint32_t n_upd, int eb, GmGraphDev G,
                              uint32_t* __restrict__ canon_lo, uint32_t* __restrict__ canon_hi,
                              uint8_t* __restrict__ canon_sign, uint32_t* __restrict__ canon_a,
-                             uint32_t* __restrict__ canon_b, GmBatchHash H,
+                             uint32_t* __restrict__ canon_b, uint32_t* __restrict__ canon_e, GmBatchHash H,
                              uint64_t* __restrict__ dkeys) {
   const int ib = G.idbits;
+  const uint32_t elb = G.elb;
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_upd; j += gridDim.x * blockDim.x) {
     if (!keep[j]) continue;
     uint64_t key = keys[j];
     uint32_t o = ords[j];
     uint32_t op = (uint32_t)(key & 1);
-    uint64_t pair = key >> 1;
+    const uint32_t el = (uint32_t)((key >> 1) & ((1ull << elb) - 1));
+    uint64_t pair = key >> (elb + 1);
     uint32_t lo = (uint32_t)(pair >> eb), hi = (uint32_t)(pair & ((1ull << eb) - 1));
     uint32_t a = G.new_of_old[lo], b = G.new_of_old[hi];
     canon_lo[o] = lo;
@@ -109,9 +131,12 @@ __global__ void k_canon_emit(const uint64_t* __restrict__ keys, const uint32_t* 
     canon_sign[o] = (uint8_t)op;
     canon_a[o] = a;
     canon_b[o] = b;
+    if (canon_e) canon_e[o] = el;
     hash_insert(H, gm_edge_key(a, b), (o << 1) | op);
-    dkeys[2 * (uint64_t)o] = ((uint64_t)a << (ib + 1)) | ((uint64_t)b << 1) | op;
-    dkeys[2 * (uint64_t)o + 1] = ((uint64_t)b << (ib + 1)) | ((uint64_t)a << 1) | op;
+    // directed entries keyed by (row, neighbour, op); the row of a for label el
+    const uint64_t ra = ((uint64_t)a << elb) | el, rb = ((uint64_t)b << elb) | el;
+    dkeys[2 * (uint64_t)o] = (ra << (ib + 1)) | ((uint64_t)b << 1) | op;
+    dkeys[2 * (uint64_t)o + 1] = (rb << (ib + 1)) | ((uint64_t)a << 1) | op;
   }
 }
 
@@ -293,10 +318,11 @@ unsigned grid_for(uint64_t work, unsigned per_block) {
 
 namespace gm {
 
-void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd,
-                       uint32_t n, int eb, uint64_t* keys, GmCounters* ctr, hipStream_t s) {
+void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, const uint32_t* elab,
+                       uint32_t n_upd, uint32_t n, int eb, uint32_t elb, uint32_t n_el, uint64_t* keys,
+                       GmCounters* ctr, hipStream_t s) {
   if (!n_upd) return;
-  k_canon_keys<<<grid_for(n_upd, 256), 256, 0, s>>>(src, dst, op, n_upd, n, eb, keys, ctr);
+  k_canon_keys<<<grid_for(n_upd, 256), 256, 0, s>>>(src, dst, op, elab, n_upd, n, eb, elb, n_el, keys, ctr);
 }
 
 void launch_canon_classify(const uint64_t* keys, uint32_t n_upd, int eb, GmGraphDev G,
@@ -307,11 +333,11 @@ void launch_canon_classify(const uint64_t* keys, uint32_t n_upd, int eb, GmGraph
 
 void launch_canon_emit(const uint64_t* keys, const uint32_t* keep, const uint32_t* ords,
                        uint32_t n_upd, int eb, GmGraphDev G, uint32_t* canon_lo, uint32_t* canon_hi,
-                       uint8_t* canon_sign, uint32_t* canon_a, uint32_t* canon_b, GmBatchHash H,
-                       uint64_t* dkeys, hipStream_t s) {
+                       uint8_t* canon_sign, uint32_t* canon_a, uint32_t* canon_b, uint32_t* canon_e,
+                       GmBatchHash H, uint64_t* dkeys, hipStream_t s) {
   if (!n_upd) return;
   k_canon_emit<<<grid_for(n_upd, 256), 256, 0, s>>>(keys, keep, ords, n_upd, eb, G, canon_lo, canon_hi,
-                                                   canon_sign, canon_a, canon_b, H, dkeys);
+                                                   canon_sign, canon_a, canon_b, canon_e, H, dkeys);
 }
 
 void launch_runs_flags(const uint64_t* dkeys, uint32_t N, int ib, uint64_t* vals, hipStream_t s) {

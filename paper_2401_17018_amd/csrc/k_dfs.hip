@@ -536,9 +536,19 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       uint32_t v = 0, sub = 0;
       uint64_t base = 0;
       if (act) {
-        v = S.f[__ffs(t) - 1];
-        const uint64_t off = P.G.row_off[v];
-        const uint64_t li = P.lix[(uint64_t)v * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
+        const uint32_t w = __ffs(t) - 1;
+        v = S.f[w];
+        // with edge labels the list is the row of f(w) for the label of
+        // the query edge between w and the vertex being matched
+        uint32_t row = v;
+        if (P.G.elb) {
+          // lanes 32-63 serve the last vertex: select per lane between the
+          // two wave-uniform query vertices
+          const uint32_t ut = hi ? uni(pl->order[k - 1]) : uni(pl->order[l]);
+          row = (v << P.G.elb) | P.qel[(q * GM_MAX_K + ut) * GM_MAX_K + w];
+        }
+        const uint64_t off = P.G.row_off[row];
+        const uint64_t li = P.lix[(uint64_t)row * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
         base = off + (uint32_t)li;
         sub = (uint32_t)(li >> 32);
       }
@@ -620,8 +630,10 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         uint64_t base = 0;
         uint32_t sub = 0;
         if (dyn) {
-          const uint64_t off = P.G.row_off[c];
-          const uint64_t li = P.lix[(uint64_t)c * P.lix_slots + ls1];
+          uint32_t row = c;
+          if (P.G.elb) row = (c << P.G.elb) | P.qel[(q * GM_MAX_K + uni(pl->order[k - 1])) * GM_MAX_K + u];
+          const uint64_t off = P.G.row_off[row];
+          const uint64_t li = P.lix[(uint64_t)row * P.lix_slots + ls1];
           base = off + (uint32_t)li;
           sub = (uint32_t)(li >> 32);
           st_bytes += 16;

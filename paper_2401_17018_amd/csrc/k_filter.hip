@@ -10,12 +10,15 @@
 // binary searches, no scan.  One bit per query vertex, one uint16 per
 // (query, data vertex): the candidate table of Sec. IV-B.  During a batch the
 // touched rows hold G u I, whose counts bound those of G and of G' from
-// above, so the filter stays sound for both search passes.
+// above, so the filter stays sound for both search passes.  With edge
+// labels a requirement names the edge label too and counts in the row of
+// that label; a label the graph has no row for counts zero.
 //
 // Seeds (Algorithm 1, the loop over query edges and its label test): for
 // every canonical batch edge (a, b) and every directed query edge (x, y) of
 // every query, (x -> a, y -> b) is a seed when a is a candidate of x and b of
-// y.  Both orientations of each query edge are plans of their own.
+// y (and, with edge labels, the batch edge carries the query edge's label).
+// Both orientations of each query edge are plans of their own.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -33,17 +36,17 @@ __device__ inline uint32_t lb_masked(const uint32_t* col, uint64_t a, uint32_t l
   return lo;
 }
 
-__global__ void k_filter(GmGraphDev G, const uint32_t* __restrict__ verts, uint32_t nv,
+// verts: vertex ids, or row ids (vertex = row >> elb) when rows != 0; a
+// vertex listed twice is recomputed to the same mask.
+__global__ void k_filter(GmGraphDev G, const uint32_t* __restrict__ verts, uint32_t nv, uint32_t rows,
                          const uint32_t* __restrict__ lab_fstart, const GmFilterEntry* __restrict__ fe,
                          const GmReq* __restrict__ reqs, uint16_t* __restrict__ cand, uint32_t only_q) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
-    const uint32_t v = verts ? verts[i] : i;
+    const uint32_t v = verts ? (rows ? verts[i] >> G.elb : verts[i]) : i;
     const uint32_t lab = G.vlabel[v];
     if (lab >= G.label_slots) continue;
     const uint32_t e0 = lab_fstart[lab], e1 = lab_fstart[lab + 1];
     if (e0 == e1) continue;
-    const uint64_t off = G.row_off[v];
-    const uint32_t len = G.row_len[v];
     uint32_t cur_q = 0xFFFFFFFFu;
     uint32_t mask = 0;
     for (uint32_t e = e0; e < e1; ++e) {
@@ -58,7 +61,10 @@ __global__ void k_filter(GmGraphDev G, const uint32_t* __restrict__ verts, uint3
       for (uint32_t r = 0; r < E.req_n && ok; ++r) {
         const GmReq R = reqs[E.req_off + r];
         uint32_t have = 0;
-        if (R.lab < G.label_slots) {
+        if (R.lab < G.label_slots && R.el < G.n_el) {
+          const uint32_t row = (v << G.elb) | R.el;
+          const uint64_t off = G.row_off[row];
+          const uint32_t len = G.row_len[row];
           uint32_t s0 = lb_masked(G.col, off, len, G.label_start[R.lab]);
           uint32_t s1 = lb_masked(G.col, off, len, G.label_start[R.lab + 1]);
           have = s1 - s0;
@@ -73,7 +79,8 @@ __global__ void k_filter(GmGraphDev G, const uint32_t* __restrict__ verts, uint3
 
 // Thread per (canonical batch edge, query).
 __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __restrict__ canon_b,
-                        const uint8_t* __restrict__ canon_sign, uint32_t n_canon,
+                        const uint8_t* __restrict__ canon_sign, const uint32_t* __restrict__ canon_e,
+                        uint32_t n_canon,
                         const GmQueryDev* __restrict__ qs, uint32_t nq, const GmPlan* __restrict__ plans,
                         const uint16_t* __restrict__ cand, uint32_t n, GmSeed* __restrict__ seeds,
                         uint64_t cap, GmCounters* ctr, uint32_t only_q, uint32_t coalesce) {
@@ -82,14 +89,14 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
        w += (uint64_t)gridDim.x * blockDim.x) {
     const uint32_t o = (uint32_t)(w / nqs), q = only_q < nq ? only_q : (uint32_t)(w % nqs);
-    const uint32_t a = canon_a[o], b = canon_b[o];
+    const uint32_t a = canon_a[o], b = canon_b[o], el = canon_e ? canon_e[o] : 0u;
     const uint32_t ca = cand[(uint64_t)q * n + a], cb = cand[(uint64_t)q * n + b];
     if (!ca || !cb) continue;
     const GmQueryDev Q = qs[q];
     for (uint32_t d = 0; d < Q.n_plans; ++d) {
       const GmPlan& P = plans[Q.plan_base + d];
       if (coalesce && P.n_perm == 0) continue;  // another plan's matches stand for this one's
-      if (((ca >> P.x) & 1u) && ((cb >> P.y) & 1u)) {
+      if (((ca >> P.x) & 1u) && ((cb >> P.y) & 1u) && P.el == el) {
         unsigned long long pos = atomicAdd(&ctr->n_seeds, 1ull);
         if (pos < cap) {
           GmSeed sd;
@@ -106,7 +113,8 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
 
 // Label index (thread per (row, indexed label)): the subrange [start,
 // start + len) of the row holding neighbours with that label.  Rows are
-// sorted by label-grouped ids, so this is two binary searches.
+// sorted by label-grouped ids, so this is two binary searches.  verts holds
+// row ids (nullptr: rows 0 .. nv-1).
 __global__ void k_label_index(GmGraphDev G, const uint32_t* __restrict__ verts, uint32_t nv,
                               const uint32_t* __restrict__ slot_labels, uint32_t n_slots,
                               unsigned long long* __restrict__ lix) {
@@ -148,11 +156,11 @@ unsigned grid_for(uint64_t work, unsigned per_block) {
 
 namespace gm {
 
-void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,
+void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, uint32_t rows, const uint32_t* lab_fstart,
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s) {
   if (!nv) return;
-  k_filter<<<grid_for(nv, 256), 256, 0, s>>>(G, verts, nv, lab_fstart, fe, reqs, cand, only_q);
+  k_filter<<<grid_for(nv, 256), 256, 0, s>>>(G, verts, nv, rows, lab_fstart, fe, reqs, cand, only_q);
 }
 
 void launch_pending_init(GmCounters* ctr, hipStream_t s) { k_pending_init<<<1, 1, 0, s>>>(ctr); }
@@ -165,12 +173,12 @@ void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const 
 }
 
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
-                  uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
+                  const uint32_t* canon_e, uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
                   uint32_t only_q, uint32_t coalesce, hipStream_t s) {
   if (!n_canon || !nq) return;
   const uint64_t work = (uint64_t)n_canon * (only_q < nq ? 1u : nq);
-  k_seeds<<<grid_for(work, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, n_canon, qs, nq, plans, cand, n,
+  k_seeds<<<grid_for(work, 256), 256, 0, s>>>(canon_a, canon_b, canon_sign, canon_e, n_canon, qs, nq, plans, cand, n,
                                               seeds, cap, ctr, only_q, coalesce);
 }
 

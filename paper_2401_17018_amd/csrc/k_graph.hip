@@ -9,7 +9,9 @@
 //   candidate filter (Sec. IV-B) are found by binary search instead of a scan.
 //   Row v lives at col[row_off[v] .. row_off[v] + row_len[v]) in an arena; a
 //   batch writes the rows it changes to fresh arena space (Sec. V-C replaces
-//   the paper's packed memory array).
+//   the paper's packed memory array).  With edge labels (Sec. II-A) vertex v
+//   has one row per label e, row id (v << elb) | e, so the neighbours of one
+//   vertex label through one edge label are again one contiguous subrange.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -27,9 +29,12 @@ __device__ inline uint64_t lower_bound_u32(const uint32_t* p, uint64_t lo, uint6
 }
 
 // One wave per vertex: offsets, order, range, self loops, symmetry, labels.
+// With edge labels (elab != nullptr) the mirror entry must carry the same
+// label (the graph stays simple: one edge, with one label, per pair).
 __global__ __launch_bounds__(256) void k_validate_csr(const uint64_t* __restrict__ rp,
                                                       const uint32_t* __restrict__ col,
                                                       const uint32_t* __restrict__ labels,
+                                                      const uint32_t* __restrict__ elab, uint32_t n_el,
                                                       uint32_t n, uint64_t nnz,
                                                       uint32_t* __restrict__ err) {
   const int lane = threadIdx.x & 63;
@@ -48,8 +53,9 @@ __global__ __launch_bounds__(256) void k_validate_csr(const uint64_t* __restrict
     }
     for (uint64_t j = a + lane; j < b; j += 64) {
       uint32_t x = col[j];
+      const uint32_t el = elab ? elab[j] : 0u;
       uint32_t e = 0;
-      if (x >= n) {
+      if (x >= n || el >= n_el) {
         e |= GM_ERR_RANGE;
       } else {
         if (x == v) e |= GM_ERR_SELFLOOP;
@@ -59,7 +65,7 @@ __global__ __launch_bounds__(256) void k_validate_csr(const uint64_t* __restrict
           e |= GM_ERR_CSR;
         } else {
           uint64_t p = lower_bound_u32(col, xa, xb, (uint32_t)v);
-          if (p >= xb || col[p] != (uint32_t)v) e |= GM_ERR_CSR;
+          if (p >= xb || col[p] != (uint32_t)v || (elab && elab[p] != el)) e |= GM_ERR_CSR;
         }
       }
       if (e) atomicOr(err, e);
@@ -105,13 +111,16 @@ __global__ void k_label_start(const uint16_t* __restrict__ vlabel, uint32_t n, u
 
 // Keys map[src] << idbits | map[dst] for every entry of a CSR (one wave per row).
 // With flag_aware, entries carry the batch flag bit, which is stripped.
+// With edge labels (elab, elb > 0) the source part is the row id
+// (map[src] << elb | label).
 __global__ __launch_bounds__(256) void k_csr_keys(const uint64_t* __restrict__ row_off,
                                                   const uint32_t* __restrict__ row_len,
                                                   const uint64_t* __restrict__ rp,
                                                   const uint32_t* __restrict__ col,
                                                   const uint32_t* __restrict__ map, uint32_t n,
                                                   int idbits, const uint64_t* __restrict__ out_off,
-                                                  uint64_t* __restrict__ keys) {
+                                                  uint64_t* __restrict__ keys, const uint32_t* __restrict__ elab,
+                                                  uint32_t elb) {
   const int lane = threadIdx.x & 63;
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -126,7 +135,58 @@ __global__ __launch_bounds__(256) void k_csr_keys(const uint64_t* __restrict__ r
     }
     uint64_t src = (uint64_t)map[v] << idbits;
     uint64_t o = out_off ? out_off[v] : a;
-    for (uint64_t j = lane; j < len; j += 64) keys[o + j] = src | map[col[a + j] & GM_IDMASK];
+    if (elab) {
+      for (uint64_t j = lane; j < len; j += 64)
+        keys[o + j] = ((((uint64_t)map[v] << elb) | elab[a + j]) << idbits) | map[col[a + j] & GM_IDMASK];
+    } else {
+      for (uint64_t j = lane; j < len; j += 64) keys[o + j] = src | map[col[a + j] & GM_IDMASK];
+    }
+  }
+}
+
+// Row lengths from sorted keys (row << idbits | neighbour): deg[row] += 1.
+__global__ void k_row_hist(const uint64_t* __restrict__ keys, uint64_t nnz, int idbits, uint64_t* __restrict__ deg) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd((unsigned long long*)&deg[keys[i] >> idbits], 1ull);
+}
+
+// Export keys of every row r = (v << elb) | e (one wave per row):
+// old[v] << (idbits + elb) | old[w] << elb | e, placed at out_off[r].
+__global__ __launch_bounds__(256) void k_row_keys_el(const uint64_t* __restrict__ row_off,
+                                                     const uint32_t* __restrict__ row_len,
+                                                     const uint32_t* __restrict__ col,
+                                                     const uint32_t* __restrict__ old_of_new, uint32_t rows,
+                                                     uint32_t elb, int idbits, const uint64_t* __restrict__ out_off,
+                                                     uint64_t* __restrict__ keys) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t r = gw; r < rows; r += nw) {
+    const uint64_t a = row_off[r], o = out_off[r];
+    const uint32_t len = row_len[r];
+    const uint64_t e = r & ((1ull << elb) - 1);
+    const uint64_t src = (uint64_t)old_of_new[r >> elb] << (idbits + elb);
+    for (uint32_t j = lane; j < len; j += 64)
+      keys[o + j] = src | ((uint64_t)old_of_new[col[a + j] & GM_IDMASK] << elb) | e;
+  }
+}
+
+__global__ void k_keys_split_el(const uint64_t* __restrict__ keys, uint64_t nnz, int idbits, uint32_t elb,
+                                uint32_t* __restrict__ col_out, uint32_t* __restrict__ elab_out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    col_out[i] = (uint32_t)((k >> elb) & ((1ull << idbits) - 1));
+    elab_out[i] = (uint32_t)(k & ((1ull << elb) - 1));
+  }
+}
+
+// deg_out[map[v]] = sum of the lengths of v's 2^elb rows.
+__global__ void k_deg_rows(const uint32_t* __restrict__ row_len, const uint32_t* __restrict__ map, uint32_t n,
+                           uint32_t elb, uint64_t* __restrict__ deg_out) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t d = 0;
+    for (uint32_t e = 0; e < (1u << elb); ++e) d += row_len[(v << elb) | e];
+    deg_out[map ? map[v] : v] = d;
   }
 }
 
@@ -199,7 +259,10 @@ __global__ void k_vdel_len(GmGraphDev G, const uint32_t* __restrict__ vdel, uint
       atomicOr(err, GM_ERR_RANGE);
       len[i] = 0;
     } else {
-      len[i] = G.row_len[G.new_of_old[v]];
+      const uint32_t vi = G.new_of_old[v];
+      uint64_t d = 0;
+      for (uint32_t e = 0; e < (1u << G.elb); ++e) d += G.row_len[(vi << G.elb) | e];
+      len[i] = d;
       atomicOr(&mark[v >> 5], 1u << (v & 31));
     }
   }
@@ -221,19 +284,25 @@ __global__ void k_vdel_check(const uint32_t* __restrict__ src, const uint32_t* _
 
 __global__ void k_vdel_expand(GmGraphDev G, const uint32_t* __restrict__ vdel, uint32_t nv,
                               const uint64_t* __restrict__ offs, uint32_t* __restrict__ src,
-                              uint32_t* __restrict__ dst, uint8_t* __restrict__ op) {
-  // one wave per deleted vertex, lanes over its row
+                              uint32_t* __restrict__ dst, uint8_t* __restrict__ op, uint32_t* __restrict__ elab) {
+  // one wave per deleted vertex, lanes over its rows (one per edge label)
   const uint32_t lane = threadIdx.x & 63;
   for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < nv; i += (gridDim.x * blockDim.x) >> 6) {
     const uint32_t v = vdel[i];
     if (v >= G.n) continue;
     const uint32_t vi = G.new_of_old[v];
-    const uint64_t base = G.row_off[vi], o = offs[i];
-    const uint32_t len = G.row_len[vi];
-    for (uint32_t j = lane; j < len; j += 64) {
-      src[o + j] = v;
-      dst[o + j] = G.ext[base + j];
-      op[o + j] = 0;
+    uint64_t o = offs[i];
+    for (uint32_t e = 0; e < (1u << G.elb); ++e) {
+      const uint32_t r = (vi << G.elb) | e;
+      const uint64_t base = G.row_off[r];
+      const uint32_t len = G.row_len[r];
+      for (uint32_t j = lane; j < len; j += 64) {
+        src[o + j] = v;
+        dst[o + j] = G.ext[base + j];
+        op[o + j] = 0;
+        if (elab) elab[o + j] = e;
+      }
+      o += len;
     }
   }
 }
@@ -249,9 +318,32 @@ unsigned grid_for(uint64_t work, unsigned per_block) {
 
 namespace gm {
 
-void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, uint32_t n,
-                         uint64_t nnz, uint32_t* err, hipStream_t s) {
-  k_validate_csr<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(rp, col, labels, n, nnz, err);
+void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, const uint32_t* elab,
+                         uint32_t n_el, uint32_t n, uint64_t nnz, uint32_t* err, hipStream_t s) {
+  k_validate_csr<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(rp, col, labels, elab, n_el, n, nnz, err);
+}
+
+void launch_row_hist(const uint64_t* keys, uint64_t nnz, int idbits, uint64_t* deg, hipStream_t s) {
+  if (!nnz) return;
+  k_row_hist<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, idbits, deg);
+}
+
+void launch_row_keys_el(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* col,
+                        const uint32_t* old_of_new, uint32_t rows, uint32_t elb, int idbits, const uint64_t* out_off,
+                        uint64_t* keys, hipStream_t s) {
+  k_row_keys_el<<<grid_for((uint64_t)rows * 64, 256), 256, 0, s>>>(row_off, row_len, col, old_of_new, rows, elb,
+                                                                   idbits, out_off, keys);
+}
+
+void launch_keys_split_el(const uint64_t* keys, uint64_t nnz, int idbits, uint32_t elb, uint32_t* col_out,
+                          uint32_t* elab_out, hipStream_t s) {
+  if (!nnz) return;
+  k_keys_split_el<<<grid_for(nnz, 256), 256, 0, s>>>(keys, nnz, idbits, elb, col_out, elab_out);
+}
+
+void launch_deg_rows(const uint32_t* row_len, const uint32_t* map, uint32_t n, uint32_t elb, uint64_t* deg_out,
+                     hipStream_t s) {
+  k_deg_rows<<<grid_for(n, 256), 256, 0, s>>>(row_len, map, n, elb, deg_out);
 }
 
 void launch_relabel_keys(const uint32_t* labels, uint32_t n, uint64_t* keys, hipStream_t s) {
@@ -270,9 +362,9 @@ void launch_label_start(const uint16_t* vlabel, uint32_t n, uint32_t slots, uint
 
 void launch_csr_keys(const uint64_t* row_off, const uint32_t* row_len, const uint64_t* rp,
                      const uint32_t* col, const uint32_t* map, uint32_t n, int idbits,
-                     const uint64_t* out_off, uint64_t* keys, hipStream_t s) {
+                     const uint64_t* out_off, uint64_t* keys, hipStream_t s, const uint32_t* elab, uint32_t elb) {
   k_csr_keys<<<grid_for((uint64_t)n * 64, 256), 256, 0, s>>>(row_off, row_len, rp, col, map, n, idbits,
-                                                            out_off, keys);
+                                                            out_off, keys, elab, elb);
 }
 
 void launch_csr_extract(const uint64_t* keys, uint64_t nnz, uint64_t idmask, uint32_t* col_out,
@@ -308,9 +400,9 @@ void launch_vdel_check(const uint32_t* src, const uint32_t* dst, const uint8_t* 
 }
 
 void launch_vdel_expand(GmGraphDev G, const uint32_t* vdel, uint32_t nv, const uint64_t* offs, uint32_t* src,
-                        uint32_t* dst, uint8_t* op, hipStream_t s) {
+                        uint32_t* dst, uint8_t* op, uint32_t* elab, hipStream_t s) {
   if (!nv) return;
-  k_vdel_expand<<<grid_for((uint64_t)nv * 64, 256), 256, 0, s>>>(G, vdel, nv, offs, src, dst, op);
+  k_vdel_expand<<<grid_for((uint64_t)nv * 64, 256), 256, 0, s>>>(G, vdel, nv, offs, src, dst, op, elab);
 }
 
 void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,

@@ -5,11 +5,14 @@
 #include "dev_common.h"
 
 // The dynamic graph as the kernels see it (internal, label-grouped ids).
+// Rows: with edge labels, vertex v has one row per edge label e, row id
+// (v << elb) | e, holding its neighbours through edges of label e (sorted by
+// internal id).  Without edge labels elb = 0 and the row id is v.
 struct GmGraphDev {
   uint32_t n;
   int32_t idbits;                 // bits needed for an id < n
-  uint64_t* row_off;              // [n]
-  uint32_t* row_len;              // [n]
+  uint64_t* row_off;              // [n << elb]
+  uint32_t* row_len;              // [n << elb]
   uint32_t* col;                  // arena; bit 31 marks batch entries
   uint32_t* ext;                  // parallel arena: external id of each col entry
   const uint16_t* vlabel;         // [n]
@@ -17,6 +20,8 @@ struct GmGraphDev {
   uint32_t label_slots;           // labels >= label_slots occur nowhere
   const uint32_t* new_of_old;     // [n] external -> internal
   const uint32_t* old_of_new;     // [n] internal -> external
+  uint32_t elb;                   // edge-label bits of a row id (0: no edge labels)
+  uint32_t n_el;                  // edge labels are < n_el (1: no edge labels)
 };
 
 // The batch hash: undirected internal edge key -> ord << 1 | sign.
@@ -50,7 +55,7 @@ struct GmCounters {
 
 struct GmDfsParams {
   GmGraphDev G;
-  const unsigned long long* lix;  // [n][lix_slots]: label subrange of each row, start | len << 32
+  const unsigned long long* lix;  // [rows][lix_slots]: label subrange of each row, start | len << 32
   uint32_t lix_slots;
   const GmPlan* plans;
   const GmQueryDev* queries;
@@ -81,21 +86,35 @@ struct GmDfsParams {
   const GmPerm* perms;            // coalesced search: permutation table referenced by plans
   uint32_t coalesce;              // 1: search representative plans only and permute their matches
   uint32_t pad3;
+  const uint8_t* qel;             // [nq][16][16] edge label of query edge {u, w} (used when G.elb > 0)
 };
 
 namespace gm {
 
 // graph (k_graph.hip)
-void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, uint32_t n,
-                         uint64_t nnz, uint32_t* err, hipStream_t s);
+void launch_validate_csr(const uint64_t* rp, const uint32_t* col, const uint32_t* labels, const uint32_t* elab,
+                         uint32_t n_el, uint32_t n, uint64_t nnz, uint32_t* err, hipStream_t s);
 void launch_relabel_keys(const uint32_t* labels, uint32_t n, uint64_t* keys, hipStream_t s);
 void launch_relabel_apply(const uint64_t* sorted, uint32_t n, uint32_t* new_of_old,
                           uint32_t* old_of_new, uint16_t* vlabel, hipStream_t s);
 void launch_label_start(const uint16_t* vlabel, uint32_t n, uint32_t slots, uint32_t* label_start,
                         hipStream_t s);
+// elab (per CSR entry, with elb > 0): the source part becomes the row id map[v] << elb | label
 void launch_csr_keys(const uint64_t* row_off, const uint32_t* row_len, const uint64_t* rp,
                      const uint32_t* col, const uint32_t* map, uint32_t n, int idbits,
-                     const uint64_t* out_off, uint64_t* keys, hipStream_t s);
+                     const uint64_t* out_off, uint64_t* keys, hipStream_t s, const uint32_t* elab = nullptr,
+                     uint32_t elb = 0);
+// row lengths from sorted (row << idbits | neighbour) keys; deg zeroed by the caller
+void launch_row_hist(const uint64_t* keys, uint64_t nnz, int idbits, uint64_t* deg, hipStream_t s);
+// labelled export: keys old[v] << (idbits + elb) | old[w] << elb | e per row entry, and their split
+void launch_row_keys_el(const uint64_t* row_off, const uint32_t* row_len, const uint32_t* col,
+                        const uint32_t* old_of_new, uint32_t rows, uint32_t elb, int idbits, const uint64_t* out_off,
+                        uint64_t* keys, hipStream_t s);
+void launch_keys_split_el(const uint64_t* keys, uint64_t nnz, int idbits, uint32_t elb, uint32_t* col_out,
+                          uint32_t* elab_out, hipStream_t s);
+// deg_out[map[v]] = total length of v's rows
+void launch_deg_rows(const uint32_t* row_len, const uint32_t* map, uint32_t n, uint32_t elb, uint64_t* deg_out,
+                     hipStream_t s);
 void launch_csr_extract(const uint64_t* keys, uint64_t nnz, uint64_t idmask, uint32_t* col_out,
                         hipStream_t s);
 void launch_deg_mapped(const uint64_t* rp, const uint32_t* row_len, const uint32_t* map, uint32_t n,
@@ -114,19 +133,21 @@ void launch_vdel_len(GmGraphDev G, const uint32_t* vdel, uint32_t nv, uint64_t* 
 void launch_vdel_check(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd, uint32_t n,
                        const uint32_t* mark, uint32_t* err, hipStream_t s);
 void launch_vdel_expand(GmGraphDev G, const uint32_t* vdel, uint32_t nv, const uint64_t* offs, uint32_t* src,
-                        uint32_t* dst, uint8_t* op, hipStream_t s);
+                        uint32_t* dst, uint8_t* op, uint32_t* elab, hipStream_t s);
 void launch_gather_ext(const uint32_t* col, const uint32_t* old_of_new, uint64_t nnz, uint32_t* ext,
                        hipStream_t s);
 
 // batch (k_batch.hip)
-void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, uint32_t n_upd,
-                       uint32_t n, int eb, uint64_t* keys, GmCounters* ctr, hipStream_t s);
+// keys (lo, hi, e, op) packed as ((lo << eb | hi) << elb | e) << 1 | op; elab may be nullptr
+void launch_canon_keys(const uint32_t* src, const uint32_t* dst, const uint8_t* op, const uint32_t* elab,
+                       uint32_t n_upd, uint32_t n, int eb, uint32_t elb, uint32_t n_el, uint64_t* keys,
+                       GmCounters* ctr, hipStream_t s);
 void launch_canon_classify(const uint64_t* keys, uint32_t n_upd, int eb, GmGraphDev G,
                            uint32_t* keep, GmCounters* ctr, hipStream_t s);
 void launch_canon_emit(const uint64_t* keys, const uint32_t* keep, const uint32_t* ords,
                        uint32_t n_upd, int eb, GmGraphDev G, uint32_t* canon_lo, uint32_t* canon_hi,
-                       uint8_t* canon_sign, uint32_t* canon_a, uint32_t* canon_b, GmBatchHash H,
-                       uint64_t* dkeys, hipStream_t s);
+                       uint8_t* canon_sign, uint32_t* canon_a, uint32_t* canon_b, uint32_t* canon_e,
+                       GmBatchHash H, uint64_t* dkeys, hipStream_t s);
 void launch_runs_flags(const uint64_t* dkeys, uint32_t N, int ib, uint64_t* vals, hipStream_t s);
 void launch_runs_fill(const uint64_t* dkeys, const uint64_t* runscan, uint32_t N, int ib,
                       uint32_t* touched, uint32_t* run_start, uint32_t* run_end, hipStream_t s);
@@ -150,7 +171,9 @@ void launch_rows_save(const uint32_t* touched, uint32_t n_touched, GmGraphDev G,
                       uint32_t* r0_len, hipStream_t s);
 
 // filter and seeds (k_filter.hip)
-void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* lab_fstart,
+// candidate masks of vertices `verts` (or all nv vertices); rows != 0: verts
+// holds row ids and each names its vertex
+void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, uint32_t rows, const uint32_t* lab_fstart,
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s);
 void launch_pending_init(GmCounters* ctr, hipStream_t s);
@@ -160,8 +183,9 @@ void launch_seed_window(GmCounters* ctr, hipStream_t s);
 // label index: for rows `verts` (or all rows), the subrange of each indexed label
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
                         uint32_t n_slots, unsigned long long* lix, hipStream_t s);
+// canon_e: edge label per canonical edge (nullptr: all 0)
 void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_t* canon_sign,
-                  uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
+                  const uint32_t* canon_e, uint32_t n_canon, const GmQueryDev* qs, uint32_t nq, const GmPlan* plans,
                   const uint16_t* cand, uint32_t n, GmSeed* seeds, uint64_t cap, GmCounters* ctr,
                   uint32_t only_q, uint32_t coalesce, hipStream_t s);  // only_q = 0xFFFFFFFF: every query
 

@@ -70,6 +70,7 @@ struct gamma_ctx {
   uint64_t live = 0;
   uint64_t arena_cap = 0, arena_top = 0;
   uint32_t label_slots = 1;
+  uint32_t n_el = 1, elb = 0;         // edge labels < n_el; row id = v << elb | label
   std::vector<uint64_t> label_count;  // data vertices per label
   DevBuf row_off, row_len, vlabel, label_start, new_of_old, old_of_new, arena, arena_ext;
 
@@ -80,14 +81,14 @@ struct gamma_ctx {
   DevBuf plans, qdev, cand, lab_fstart, fentries, reqs;
 
   // batch scratch
-  DevBuf b_src, b_dst, b_op, keys, keys_tmp, hist, hist_scan, scan_tmp, keep, ords;
-  DevBuf canon_lo, canon_hi, canon_sign, canon_a, canon_b, hkeys, hvals, dkeys, dkeys_tmp;
+  DevBuf b_src, b_dst, b_op, b_el, keys, keys_tmp, hist, hist_scan, scan_tmp, keep, ords;
+  DevBuf canon_lo, canon_hi, canon_sign, canon_a, canon_b, canon_e, hkeys, hvals, dkeys, dkeys_tmp;
   DevBuf runvals, runscan, touched, run_start, run_end, sizes, r1off, r2_off, r2_len;
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
-  DevBuf lix, lix_lab, r0_off, r0_len, permtab;
-  DevBuf vx_src, vx_dst, vx_op, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
+  DevBuf lix, lix_lab, r0_off, r0_len, permtab, qeltab;
+  DevBuf vx_src, vx_dst, vx_op, vx_el, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
   uint32_t wall_khz = 100000;
   gamma_tuning tun{};                // search tunables (never change results)
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
@@ -109,10 +110,10 @@ struct gamma_ctx {
 
   gamma_ctx() {
     DevBuf* list[] = {&row_off, &row_len, &vlabel, &label_start, &new_of_old, &old_of_new, &arena,
-                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len, &permtab,
-                      &vx_src, &vx_dst, &vx_op, &vx_del, &vx_len, &vx_off, &vx_mark,
-                      &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op,
-                      &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo,
+                      &arena_ext, &mbox, &mflag, &idle_bits, &idle_rep, &lix, &lix_lab, &r0_off, &r0_len, &permtab, &qeltab,
+                      &vx_src, &vx_dst, &vx_op, &vx_el, &vx_del, &vx_len, &vx_off, &vx_mark,
+                      &plans, &qdev, &cand, &lab_fstart, &fentries, &reqs, &b_src, &b_dst, &b_op, &b_el,
+                      &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo, &canon_e,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
                       &runvals, &runscan, &touched, &run_start, &run_end, &sizes, &r1off, &r2_off,
                       &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &tmp64a,
@@ -186,8 +187,11 @@ struct gamma_ctx {
     g.label_slots = label_slots;
     g.new_of_old = (const uint32_t*)new_of_old.p;
     g.old_of_new = (const uint32_t*)old_of_new.p;
+    g.elb = elb;
+    g.n_el = n_el;
     return g;
   }
+  uint32_t rows() const { return n << elb; }
 
   void sort_keys(uint64_t* k, uint64_t* tmp, size_t cnt, int bits) {
     if (cnt < 2) return;
@@ -224,6 +228,7 @@ struct gamma_ctx {
   void upload_plans() {
     std::vector<GmPlan> all_plans;
     std::vector<GmQueryDev> qd;
+    std::vector<uint8_t> qel;  // [nq][16][16]
     lix_labels.clear();
     for (auto& q : queries)
       for (uint32_t l : q.labels) lix_labels.push_back(l);
@@ -244,7 +249,18 @@ struct gamma_ctx {
       d.k = q.k;
       d.plan_base = (uint32_t)all_plans.size();
       d.n_plans = (uint32_t)q.plans.size();
+      // a query edge label the graph has no rows for: no match can exist,
+      // and the query gets no seeds (its rows would not be addressable)
+      uint32_t max_el = 0;
+      for (uint32_t e : q.elabels) max_el = std::max(max_el, e);
+      if (has_graph && max_el >= n_el) d.n_plans = 0;
       qd.push_back(d);
+      const size_t t0 = qel.size();
+      qel.resize(t0 + GM_MAX_K * GM_MAX_K, 0);
+      for (size_t e = 0; e < q.edges.size(); ++e) {
+        const uint32_t a = q.edges[e].first, b = q.edges[e].second;
+        qel[t0 + a * GM_MAX_K + b] = qel[t0 + b * GM_MAX_K + a] = (uint8_t)q.elabels[e];
+      }
       const uint32_t pofs = (uint32_t)all_perms.size();
       for (auto& p : q.plans) {
         GmPlan pp = p;
@@ -260,6 +276,8 @@ struct gamma_ctx {
           "h2d");
     }
     total_plans = (uint32_t)all_plans.size();
+    uint8_t* dqel = ensure<uint8_t>(qeltab, std::max<size_t>(qel.size(), 1));
+    if (!qel.empty()) chk(hipMemcpyAsync(dqel, qel.data(), qel.size(), hipMemcpyHostToDevice, stream), "h2d");
     GmPlan* dp = ensure<GmPlan>(plans, std::max<size_t>(all_plans.size(), 1));
     GmQueryDev* dq = ensure<GmQueryDev>(qdev, std::max<size_t>(qd.size(), 1));
     if (!all_plans.empty())
@@ -275,8 +293,9 @@ struct gamma_ctx {
   // Label index of every row for the current label-index slots.
   void full_label_index() {
     if (!has_graph || lix_labels.empty()) return;
-    unsigned long long* L = (unsigned long long*)ensure<uint64_t>(lix, (size_t)n * lix_labels.size());
-    gm::launch_label_index(G(), nullptr, n, (const uint32_t*)lix_lab.p, (uint32_t)lix_labels.size(), L, stream);
+    unsigned long long* L = (unsigned long long*)ensure<uint64_t>(lix, (size_t)rows() * lix_labels.size());
+    gm::launch_label_index(G(), nullptr, rows(), (const uint32_t*)lix_lab.p, (uint32_t)lix_labels.size(), L,
+                           stream);
     chk(hipGetLastError(), "label index launch");
     chk(hipStreamSynchronize(stream), "sync");
   }
@@ -296,7 +315,7 @@ struct gamma_ctx {
     } else {
       chk(hipMemsetAsync(c + (size_t)only_q * n, 0, (size_t)n * 2, stream), "memset");
     }
-    gm::launch_filter(G(), nullptr, n, (const uint32_t*)lab_fstart.p, (const GmFilterEntry*)fentries.p,
+    gm::launch_filter(G(), nullptr, n, 0, (const uint32_t*)lab_fstart.p, (const GmFilterEntry*)fentries.p,
                       (const GmReq*)reqs.p, c, only_q, stream);
     chk(hipGetLastError(), "filter launch");
     chk(hipStreamSynchronize(stream), "sync");
@@ -429,26 +448,34 @@ gamma_status gamma_destroy(gamma_ctx* c) {
   return GAMMA_OK;
 }
 
-gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
-                              const uint32_t* col, const uint32_t* labels, gamma_mem where) {
+static gamma_status load_graph_impl(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                             const uint32_t* col, const uint32_t* labels, const uint32_t* elabels, uint32_t n_el,
+                             gamma_mem where) {
   return guarded(c, [&]() -> gamma_status {
     if (n == 0 || n >= 0x80000000u || !row_ptr || !labels || (nnz && !col))
       return fail(c, GAMMA_EINVAL, "load_graph: bad sizes or null arrays");
     if (nnz >= 0xFFFFFFFFull) return fail(c, GAMMA_EUNSUPPORTED, "load_graph: nnz must be < 2^32");
+    if (n_el == 0 || n_el > GAMMA_MAX_EDGE_LABELS || (!elabels && n_el != 1))
+      return fail(c, GAMMA_EINVAL, "load_graph: edge label count must be 1 without labels, 1..256 with them");
+    const uint32_t elb = n_el > 1 ? (uint32_t)bits_for(n_el) : 0u;
+    const int ib = bits_for(n);
+    if (((uint64_t)n << elb) >= 0x80000000ull || 2 * ib + (int)elb + 1 > 64)
+      return fail(c, GAMMA_EUNSUPPORTED, "load_graph: n times the edge-label count is too large");
     chk(hipSetDevice(c->device), "set device");
     hipStream_t s = c->stream;
     // stage inputs
-    DevBuf in_rp, in_col, in_lab;
+    DevBuf in_rp, in_col, in_lab, in_el;
     struct Tmp {
       gamma_ctx* c;
-      DevBuf* b[3];
+      DevBuf* b[4];
       ~Tmp() {
         for (DevBuf* x : b) c->release(*x);
       }
-    } tmp{c, {&in_rp, &in_col, &in_lab}};
+    } tmp{c, {&in_rp, &in_col, &in_lab, &in_el}};
     const uint64_t* d_rp = stage_in<uint64_t>(c, in_rp, row_ptr, (size_t)n + 1, where);
     const uint32_t* d_col = nnz ? stage_in<uint32_t>(c, in_col, col, nnz, where) : nullptr;
     const uint32_t* d_lab = stage_in<uint32_t>(c, in_lab, labels, n, where);
+    const uint32_t* d_el = (elabels && nnz) ? stage_in<uint32_t>(c, in_el, elabels, nnz, where) : nullptr;
     uint32_t* ctrw = (uint32_t*)c->ensure<GmCounters>(c->ctr, 1);
     gm::fill_u32(ctrw, 0, sizeof(GmCounters) / 4, s);
     uint32_t* dummy_col = nullptr;
@@ -456,7 +483,7 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
       dummy_col = c->ensure<uint32_t>(c->tmp32a, 1);
       d_col = dummy_col;
     }
-    gm::launch_validate_csr(d_rp, d_col, d_lab, n, nnz, ctrw, s);
+    gm::launch_validate_csr(d_rp, d_col, d_lab, d_el, n_el, n, nnz, ctrw, s);
     chk(hipGetLastError(), "validate launch");
     uint32_t err = 0;
     chk(hipMemcpyAsync(&err, ctrw, 4, hipMemcpyDeviceToHost, s), "d2h");
@@ -467,7 +494,7 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
     // new graph buffers (built aside, swapped in at the end)
     gamma_ctx& C = *c;
     DevBuf n_row_off, n_row_len, n_vlabel, n_label_start, n_n2o, n_o2n, n_arena, n_ext;
-    const int ib = bits_for(n);
+    const uint32_t rows = n << elb;
     {
       uint64_t* keys = C.ensure<uint64_t>(C.keys, n);
       uint64_t* kt = C.ensure<uint64_t>(C.keys_tmp, n);
@@ -489,25 +516,32 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
       C.label_slots = slots;
       C.label_count.assign(slots, 0);
       for (uint32_t l = 0; l < slots; ++l) C.label_count[l] = hls[l + 1] - hls[l];
-      // rows in internal ids
-      uint64_t* deg = C.ensure<uint64_t>(C.tmp64a, (size_t)n + 1);
-      gm::launch_deg_mapped(d_rp, nullptr, n2o, n, deg, s);
-      uint64_t* offs = C.ensure<uint64_t>(C.sizes, (size_t)n + 1);
-      C.scan64(deg, offs, n);
-      uint64_t* ro = C.ensure<uint64_t>(n_row_off, n);
-      uint32_t* rl = C.ensure<uint32_t>(n_row_len, n);
-      gm::launch_rows_from_scan(offs, deg, n, 0, ro, rl, s);
+      // rows in internal ids (with edge labels, rows (v << elb) | label:
+      // their lengths come from the sorted entry keys)
+      uint64_t* deg = C.ensure<uint64_t>(C.tmp64a, (size_t)rows + 1);
+      uint64_t* offs = C.ensure<uint64_t>(C.sizes, (size_t)rows + 1);
+      uint64_t* ro = C.ensure<uint64_t>(n_row_off, rows);
+      uint32_t* rl = C.ensure<uint32_t>(n_row_len, rows);
       uint64_t cap = nnz + std::max<uint64_t>(nnz / 2, 1u << 20);
       uint32_t* ar = C.ensure<uint32_t>(n_arena, cap);
       uint32_t* ax = C.ensure<uint32_t>(n_ext, cap);
+      if (elb == 0) gm::launch_deg_mapped(d_rp, nullptr, n2o, n, deg, s);
       if (nnz) {
         uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
         uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
-        gm::launch_csr_keys(nullptr, nullptr, d_rp, d_col, n2o, n, ib, nullptr, ek, s);
-        C.sort_keys(ek, et, nnz, 2 * ib);
+        gm::launch_csr_keys(nullptr, nullptr, d_rp, d_col, n2o, n, ib, nullptr, ek, s, d_el, elb);
+        C.sort_keys(ek, et, nnz, 2 * ib + (int)elb);
+        if (elb) {
+          gm::fill_u64(deg, 0, rows, s);
+          gm::launch_row_hist(ek, nnz, ib, deg, s);
+        }
         gm::launch_csr_extract(ek, nnz, (1ull << ib) - 1, ar, s);
         gm::launch_gather_ext(ar, o2n, nnz, ax, s);
+      } else if (elb) {
+        gm::fill_u64(deg, 0, rows, s);
       }
+      C.scan64(deg, offs, rows);
+      gm::launch_rows_from_scan(offs, deg, rows, 0, ro, rl, s);
       chk(hipGetLastError(), "load launch");
       chk(hipStreamSynchronize(s), "sync");
       // the load-time sort buffers are sized by nnz; batches need far less
@@ -532,6 +566,8 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
     swap_in(C.arena_ext, n_ext);
     C.n = n;
     C.idbits = ib;
+    C.n_el = n_el;
+    C.elb = elb;
     C.live = nnz;
     C.has_graph = true;
     C.has_result = false;
@@ -549,18 +585,33 @@ gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint
   });
 }
 
-gamma_status gamma_register_query(gamma_ctx* c, uint32_t k, const uint32_t* qlabels, uint32_t m,
-                                  const uint32_t* qedges, uint32_t* out_qid) {
+gamma_status gamma_load_graph(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                              const uint32_t* col, const uint32_t* labels, gamma_mem where) {
+  return load_graph_impl(c, n, nnz, row_ptr, col, labels, nullptr, 1, where);
+}
+
+gamma_status gamma_load_graph_el(gamma_ctx* c, uint32_t n, uint64_t nnz, const uint64_t* row_ptr,
+                                 const uint32_t* col, const uint32_t* labels, const uint32_t* elabels,
+                                 uint32_t n_elabels, gamma_mem where) {
+  return load_graph_impl(c, n, nnz, row_ptr, col, labels, elabels, n_elabels, where);
+}
+
+gamma_status gamma_register_query_el(gamma_ctx* c, uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                     const uint32_t* qedges, const uint32_t* qelabels, uint32_t* out_qid) {
   return guarded(c, [&]() -> gamma_status {
     std::string msg;
     int st = gm::validate_query(k, qlabels, m, qedges, &msg);
     if (st != GAMMA_OK) return fail(c, (gamma_status)st, "register_query: " + msg);
+    for (uint32_t e = 0; qelabels && e < m; ++e)
+      if (qelabels[e] >= GAMMA_MAX_EDGE_LABELS) return fail(c, GAMMA_EINVAL, "register_query: edge label >= 256");
     if (c->queries.size() >= 4096) return fail(c, GAMMA_EUNSUPPORTED, "register_query: too many queries");
     chk(hipSetDevice(c->device), "set device");
     gm::HostQuery q;
     q.k = k;
     q.labels.assign(qlabels, qlabels + k);
     for (uint32_t e = 0; e < m; ++e) q.edges.push_back({qedges[2 * e], qedges[2 * e + 1]});
+    q.elabels.assign(m, 0);
+    if (qelabels) q.elabels.assign(qelabels, qelabels + m);
     uint32_t qi = (uint32_t)c->queries.size();
     gm::plan_query(q, qi, c->label_count);
     c->queries.push_back(q);
@@ -581,12 +632,17 @@ gamma_status gamma_register_query(gamma_ctx* c, uint32_t k, const uint32_t* qlab
   });
 }
 
+gamma_status gamma_register_query(gamma_ctx* c, uint32_t k, const uint32_t* qlabels, uint32_t m,
+                                  const uint32_t* qedges, uint32_t* out_qid) {
+  return gamma_register_query_el(c, k, qlabels, m, qedges, nullptr, out_qid);
+}
+
 namespace {
 
 // Move every row into a fresh, larger arena (rows contiguous, no garbage).
 void compact_arena(gamma_ctx* c, uint64_t need) {
   hipStream_t s = c->stream;
-  const uint32_t n = c->n;
+  const uint32_t n = c->rows();  // every row, one per (vertex, edge label)
   uint64_t cap = std::max<uint64_t>(c->arena_cap, 2 * (c->live + need) + (1u << 20));
   DevBuf na, nx;
   uint32_t* dst = c->ensure<uint32_t>(na, cap);
@@ -612,9 +668,9 @@ void compact_arena(gamma_ctx* c, uint64_t need) {
 
 }  // namespace
 
-gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
-                               const uint8_t* op, gamma_mem where, uint32_t flags,
-                               gamma_batch_result* out) {
+gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                  const uint8_t* op, const uint32_t* elab, gamma_mem where, uint32_t flags,
+                                  gamma_batch_result* out) {
   return guarded(c, [&]() -> gamma_status {
     if (!out) return fail(c, GAMMA_EINVAL, "apply_batch: null result");
     if (!c->has_graph) return fail(c, GAMMA_ESTATE, "apply_batch: no graph loaded");
@@ -636,6 +692,8 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     const uint32_t* d_src = stage_in<uint32_t>(c, C.b_src, src, n_upd, where);
     const uint32_t* d_dst = stage_in<uint32_t>(c, C.b_dst, dst, n_upd, where);
     const uint8_t* d_op = stage_in<uint8_t>(c, C.b_op, op, n_upd, where);
+    const uint32_t* d_el = (elab && n_upd) ? stage_in<uint32_t>(c, C.b_el, elab, n_upd, where) : nullptr;
+    const int elb = (int)C.elb;
     GmCounters* ctr = C.ensure<GmCounters>(C.ctr, 1);
     gm::fill_u32((uint32_t*)ctr, 0, sizeof(GmCounters) / 4, s);
     const size_t nu = std::max<uint32_t>(n_upd, 1);
@@ -644,8 +702,8 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     uint32_t* keep = C.ensure<uint32_t>(C.keep, nu);
     uint32_t* ords = C.ensure<uint32_t>(C.ords, nu + 1);
     GmGraphDev G = C.G();
-    gm::launch_canon_keys(d_src, d_dst, d_op, n_upd, n, eb, keys, ctr, s);
-    C.sort_keys(keys, kt, n_upd, 2 * eb + 1);
+    gm::launch_canon_keys(d_src, d_dst, d_op, d_el, n_upd, n, eb, C.elb, C.n_el, keys, ctr, s);
+    C.sort_keys(keys, kt, n_upd, 2 * eb + elb + 1);
     gm::launch_canon_classify(keys, n_upd, eb, G, keep, ctr, s);
     C.scan32(keep, ords, n_upd);
     uint32_t hcap = 64;
@@ -663,7 +721,8 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     const size_t N2 = 2 * nu;  // directed entries, padded
     uint64_t* dk = C.ensure<uint64_t>(C.dkeys, N2);
     uint64_t* dkt = C.ensure<uint64_t>(C.dkeys_tmp, N2);
-    gm::launch_canon_emit(keys, keep, ords, n_upd, eb, G, clo, chi, csg, ca, cb, H, dk, s);
+    uint32_t* cel = elb ? C.ensure<uint32_t>(C.canon_e, nu) : nullptr;
+    gm::launch_canon_emit(keys, keep, ords, n_upd, eb, G, clo, chi, csg, ca, cb, cel, H, dk, s);
     // the canonical count decides the directed sort length: one sync here,
     // before anything is mutated, also reports validation errors
     struct {
@@ -676,12 +735,14 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     chk(hipStreamSynchronize(s), "sync");
     chk(hipGetLastError(), "canon launch");
     if (hc.err & (GM_ERR_RANGE | GM_ERR_SELFLOOP))
-      return fail(c, GAMMA_EINVAL, "apply_batch: vertex id out of range or self loop");
+      return fail(c, GAMMA_EINVAL, "apply_batch: vertex id or edge label out of range, or self loop");
+    if (hc.err & GM_ERR_RELABEL)
+      return fail(c, GAMMA_EINVAL, "apply_batch: an inserted pair is present under another edge label");
     if (hc.err & GM_ERR_CONFLICT)
       return fail(c, GAMMA_ECONFLICT, "apply_batch: an edge is both inserted and deleted");
     const uint32_t n_canon = n_upd ? h1.n_canon : 0;
     const uint32_t N = 2 * n_canon;
-    C.sort_keys(dk, dkt, N, 2 * ib + 1);
+    C.sort_keys(dk, dkt, N, 2 * ib + elb + 1);
     uint64_t* rv = C.ensure<uint64_t>(C.runvals, std::max<uint32_t>(N, 1));
     uint64_t* rsc = C.ensure<uint64_t>(C.runscan, (size_t)N + 1);
     gm::launch_runs_flags(dk, N, ib, rv, s);
@@ -728,7 +789,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
 
     // ---------------------------------------------------------- filter refresh (G u I)
     if (nq)
-      gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
+      gm::launch_filter(G, tch, n_touched, 1, (const uint32_t*)C.lab_fstart.p,
                         (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
                         (uint16_t*)C.cand.p, 0xFFFFFFFFu, s);
     chk(hipEventRecord(C.ev[3], s), "event");
@@ -741,7 +802,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     const bool per_query = C.tun.query_launch == 2 && nq > 1;
     gm::launch_seed_window(ctr, s);
     if (nq && !per_query)
-      gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
+      gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                        (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu,
                        C.tun.coalesced_search == 2 ? 1u : 0u, s);
     chk(hipEventRecord(C.ev[4], s), "event");
@@ -798,10 +859,11 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
       P.gate = C.tun.handover_gate;
       P.perms = (const GmPerm*)C.permtab.p;
       P.coalesce = C.tun.coalesced_search == 2 ? 1u : 0u;
+      P.qel = (const uint8_t*)C.qeltab.p;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
-          gm::launch_seeds(ca, cb, csg, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
+          gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                            (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi,
                            C.tun.coalesced_search == 2 ? 1u : 0u, s);
         }
@@ -820,7 +882,7 @@ gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src
     gm::launch_rows_finish(tch, r2o, r2l, r0o, r0l, n_touched, G, ctr, dry ? 1u : 0u, s);
     C.touched_label_index(tch, n_touched);
     if (nq)
-      gm::launch_filter(G, tch, n_touched, (const uint32_t*)C.lab_fstart.p,
+      gm::launch_filter(G, tch, n_touched, 1, (const uint32_t*)C.lab_fstart.p,
                         (const GmFilterEntry*)C.fentries.p, (const GmReq*)C.reqs.p,
                         (uint16_t*)C.cand.p, 0xFFFFFFFFu, s);
     chk(hipEventRecord(C.ev[6], s), "event");
@@ -959,9 +1021,15 @@ bool ctx_has_graph(const gamma_ctx* c, uint32_t* n) {
 
 extern "C" {
 
+gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                               const uint8_t* op, gamma_mem where, uint32_t flags, gamma_batch_result* out) {
+  return gamma_apply_batch_el(c, n_upd, src, dst, op, nullptr, where, flags, out);
+}
+
 gamma_status gamma_apply_batch_vertices(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
-                                        const uint8_t* op, uint32_t n_vdel, const uint32_t* vdel, gamma_mem where,
-                                        uint32_t flags, gamma_batch_result* out) {
+                                        const uint8_t* op, const uint32_t* elab, uint32_t n_vdel,
+                                        const uint32_t* vdel, gamma_mem where, uint32_t flags,
+                                        gamma_batch_result* out) {
   size_t N = 0;  // explicit updates + expanded vertex deletions
   const gamma_status st = guarded(c, [&]() -> gamma_status {
     if (!out) return fail(c, GAMMA_EINVAL, "apply_batch_vertices: null result");
@@ -1000,21 +1068,30 @@ gamma_status gamma_apply_batch_vertices(gamma_ctx* c, uint32_t n_upd, const uint
     uint32_t* xs = C.ensure<uint32_t>(C.vx_src, std::max<size_t>(N, 1));
     uint32_t* xd = C.ensure<uint32_t>(C.vx_dst, std::max<size_t>(N, 1));
     uint8_t* xo = C.ensure<uint8_t>(C.vx_op, std::max<size_t>(N, 1));
+    // with edge labels the merged batch carries them: the explicit ones (0
+    // if none were given), then each expanded edge's own
+    uint32_t* xe = C.elb ? C.ensure<uint32_t>(C.vx_el, std::max<size_t>(N, 1)) : nullptr;
     const hipMemcpyKind kind = where == GAMMA_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (n_upd) {
       chk(hipMemcpyAsync(xs, src, (size_t)n_upd * 4, kind, s), "copy");
       chk(hipMemcpyAsync(xd, dst, (size_t)n_upd * 4, kind, s), "copy");
       chk(hipMemcpyAsync(xo, op, n_upd, kind, s), "copy");
+      if (xe && elab)
+        chk(hipMemcpyAsync(xe, elab, (size_t)n_upd * 4, kind, s), "copy");
+      else if (xe)
+        gm::fill_u32(xe, 0, n_upd, s);
     }
-    gm::launch_vdel_expand(C.G(), d_vdel, n_vdel, offs, xs + n_upd, xd + n_upd, xo + n_upd, s);
+    gm::launch_vdel_expand(C.G(), d_vdel, n_vdel, offs, xs + n_upd, xd + n_upd, xo + n_upd,
+                           xe ? xe + n_upd : nullptr, s);
     chk(hipGetLastError(), "vertex deletion launch");
     return GAMMA_OK;
   });
   if (st != GAMMA_OK) return st;
   // the merged batch is device-resident and ordered on the context stream
   // after the expansion
-  return gamma_apply_batch(c, (uint32_t)N, (const uint32_t*)c->vx_src.p, (const uint32_t*)c->vx_dst.p,
-                           (const uint8_t*)c->vx_op.p, GAMMA_MEM_DEVICE, flags, out);
+  return gamma_apply_batch_el(c, (uint32_t)N, (const uint32_t*)c->vx_src.p, (const uint32_t*)c->vx_dst.p,
+                              (const uint8_t*)c->vx_op.p, c->elb ? (const uint32_t*)c->vx_el.p : nullptr,
+                              GAMMA_MEM_DEVICE, flags, out);
 }
 
 gamma_status gamma_add_vertices(gamma_ctx* c, uint32_t count, const uint32_t* labels, uint32_t* first_id) {
@@ -1030,13 +1107,17 @@ gamma_status gamma_add_vertices(gamma_ctx* c, uint32_t count, const uint32_t* la
     const uint64_t nnz = c->live;
     std::vector<uint64_t> rp((size_t)n + count + 1);
     std::vector<uint32_t> col(std::max<uint64_t>(nnz, 1)), lab((size_t)n + count);
-    gamma_status st = gamma_export_graph(c, nullptr, nullptr, rp.data(), col.data(), lab.data());
+    std::vector<uint32_t> el(c->elb ? std::max<uint64_t>(nnz, 1) : 0);
+    const uint32_t n_el = c->n_el;
+    gamma_status st = gamma_export_graph_el(c, nullptr, nullptr, nullptr, rp.data(), col.data(), lab.data(),
+                                            el.empty() ? nullptr : el.data());
     if (st < 0) return st;
     for (uint32_t i = 0; i < count; ++i) {
       rp[(size_t)n + 1 + i] = nnz;
       lab[(size_t)n + i] = labels[i];
     }
-    st = gamma_load_graph(c, n + count, nnz, rp.data(), nnz ? col.data() : nullptr, lab.data(), GAMMA_MEM_HOST);
+    st = load_graph_impl(c, n + count, nnz, rp.data(), nnz ? col.data() : nullptr, lab.data(),
+                         el.empty() ? nullptr : el.data(), n_el, GAMMA_MEM_HOST);
     if (st < 0) return st;
     if (first_id) *first_id = n;
     return GAMMA_OK;
@@ -1189,26 +1270,49 @@ gamma_status gamma_result_release(gamma_ctx* c, gamma_batch_result* res) {
   });
 }
 
-gamma_status gamma_export_graph(gamma_ctx* c, uint32_t* n_out, uint64_t* nnz_out, uint64_t* row_ptr,
-                                uint32_t* col, uint32_t* labels) {
+gamma_status gamma_export_graph_el(gamma_ctx* c, uint32_t* n_out, uint64_t* nnz_out, uint32_t* n_elabels_out,
+                                   uint64_t* row_ptr, uint32_t* col, uint32_t* labels, uint32_t* elabels) {
   return guarded(c, [&]() -> gamma_status {
     if (!c->has_graph) return fail(c, GAMMA_ESTATE, "export_graph: no graph loaded");
     if (n_out) *n_out = c->n;
     if (nnz_out) *nnz_out = c->live;
-    if (!col && !row_ptr && !labels) return GAMMA_OK;
+    if (n_elabels_out) *n_elabels_out = c->n_el;
+    if (!col && !row_ptr && !labels && !elabels) return GAMMA_OK;
     gamma_ctx& C = *c;
     hipStream_t s = C.stream;
     const uint32_t n = C.n;
     const int ib = C.idbits;
     const uint64_t nnz = C.live;
+    const uint32_t elb = C.elb, rows = C.rows();
     uint64_t* deg = C.ensure<uint64_t>(C.tmp64a, (size_t)n + 1);
-    gm::launch_deg_mapped(nullptr, (const uint32_t*)C.row_len.p, (const uint32_t*)C.old_of_new.p, n, deg, s);
+    if (elb)
+      gm::launch_deg_rows((const uint32_t*)C.row_len.p, (const uint32_t*)C.old_of_new.p, n, elb, deg, s);
+    else
+      gm::launch_deg_mapped(nullptr, (const uint32_t*)C.row_len.p, (const uint32_t*)C.old_of_new.p, n, deg, s);
     uint64_t* offs = C.ensure<uint64_t>(C.sizes, (size_t)n + 1);
     C.scan64(deg, offs, n);
     if (row_ptr) {
       chk(hipMemcpyAsync(row_ptr, offs, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost, s), "d2h");
     }
-    if (col && nnz) {
+    if (elb && (col || elabels) && nnz) {
+      // rows (v, e) packed densely, keyed (old v, old w, e), sorted, split
+      uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
+      uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
+      uint64_t* ideg = C.ensure<uint64_t>(C.runvals, (size_t)rows + 1);
+      gm::launch_deg_mapped(nullptr, (const uint32_t*)C.row_len.p, nullptr, rows, ideg, s);
+      uint64_t* ioffs = C.ensure<uint64_t>(C.runscan, (size_t)rows + 1);
+      C.scan64(ideg, ioffs, rows);
+      gm::launch_row_keys_el((const uint64_t*)C.row_off.p, (const uint32_t*)C.row_len.p, (const uint32_t*)C.arena.p,
+                             (const uint32_t*)C.old_of_new.p, rows, elb, ib, ioffs, ek, s);
+      C.sort_keys(ek, et, nnz, 2 * ib + (int)elb);
+      uint32_t* oc = C.ensure<uint32_t>(C.tmp32a, 2 * nnz);
+      gm::launch_keys_split_el(ek, nnz, ib, elb, oc, oc + nnz, s);
+      if (col) chk(hipMemcpyAsync(col, oc, nnz * 4, hipMemcpyDeviceToHost, s), "d2h");
+      if (elabels) chk(hipMemcpyAsync(elabels, oc + nnz, nnz * 4, hipMemcpyDeviceToHost, s), "d2h");
+    } else if (elabels && nnz) {
+      std::fill(elabels, elabels + nnz, 0u);
+    }
+    if (!elb && col && nnz) {
       uint64_t* ek = C.ensure<uint64_t>(C.keys, nnz);
       uint64_t* et = C.ensure<uint64_t>(C.keys_tmp, nnz);
       // internal row offsets packed densely: scan of row_len in internal order
@@ -1234,6 +1338,11 @@ gamma_status gamma_export_graph(gamma_ctx* c, uint32_t* n_out, uint64_t* nnz_out
     chk(hipGetLastError(), "export launch");
     return GAMMA_OK;
   });
+}
+
+gamma_status gamma_export_graph(gamma_ctx* c, uint32_t* n_out, uint64_t* nnz_out, uint64_t* row_ptr,
+                                uint32_t* col, uint32_t* labels) {
+  return gamma_export_graph_el(c, n_out, nnz_out, nullptr, row_ptr, col, labels, nullptr);
 }
 
 // ------------------------------------------------------------------ host validators

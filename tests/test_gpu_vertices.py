@@ -104,7 +104,7 @@ class _DeviceArrays:
 
 def _c_counts(lib, ctx_ptr, n_upd, ptrs, n_vdel, flags):
     res = capi.BatchResult()
-    st = lib.gamma_apply_batch_vertices(ctx_ptr, n_upd, ptrs[0], ptrs[1], ptrs[2], n_vdel, ptrs[3],
+    st = lib.gamma_apply_batch_vertices(ctx_ptr, n_upd, ptrs[0], ptrs[1], ptrs[2], None, n_vdel, ptrs[3],
                                         capi.GAMMA_MEM_DEVICE, flags, ctypes.byref(res))
     assert st == capi.GAMMA_OK, st
     q = res.queries[0]

@@ -18,7 +18,7 @@ from oracle import brute as O1
 from oracle import plain as O2
 
 
-def _labelled_graph(rng, n, m_try, n_labels, n_el, multi):
+def _labelled_graph(rng, n, m_try, n_labels, n_el):
     tri = set()
     pairs = set()
     for _ in range(m_try):
@@ -27,7 +27,7 @@ def _labelled_graph(rng, n, m_try, n_labels, n_el, multi):
             continue
         p = (min(u, v), max(u, v))
         e = int(rng.integers(0, n_el))
-        if p in pairs and not multi:
+        if p in pairs:
             continue
         pairs.add(p)
         tri.add(p + (e,))
@@ -48,8 +48,10 @@ def _labelled_query(rng, k, n_labels, n_el):
 def _labelled_batch(rng, g, n_upd, adversarial):
     """Insertions and deletions of labelled triples, with duplicates and
     no-ops when adversarial (deletions of a pair under a label it does not
-    carry, insertions of present triples).  At most one triple per pair."""
+    carry, insertions of present triples).  At most one triple per pair;
+    new insertions go to absent pairs."""
     E = sorted(O1.edge_set_el(g))
+    pairs = {(a, b) for (a, b, _) in E}
     ups, used = [], {}
     for _ in range(n_upd * 3):
         if len(ups) >= n_upd:
@@ -57,11 +59,11 @@ def _labelled_batch(rng, g, n_upd, adversarial):
         if E and rng.random() < 0.4:
             a, b, e = E[int(rng.integers(0, len(E)))]
             op = 0 if not adversarial or rng.random() < 0.7 else 1
-            if adversarial and rng.random() < 0.3:
+            if adversarial and op == 0 and rng.random() < 0.3:
                 e = int(rng.integers(0, g.n_elabels))
         else:
             a, b = (int(x) for x in rng.integers(0, g.n, 2))
-            if a == b:
+            if a == b or (min(a, b), max(a, b)) in pairs:
                 continue
             e, op = int(rng.integers(0, g.n_elabels)), 1
         p = (min(a, b), max(a, b))
@@ -95,10 +97,10 @@ def _check_o2_equals_o1(g, q, b, threads=1):
 
 @settings(max_examples=300, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(seed=st.integers(0, 2**31 - 1), n=st.integers(3, 8), k=st.integers(2, 4), extra=st.integers(0, 14),
-       n_labels=st.integers(1, 2), n_el=st.integers(1, 3), multi=st.booleans(), adversarial=st.booleans())
-def test_o2_equals_o1_labelled(seed, n, k, extra, n_labels, n_el, multi, adversarial):
+       n_labels=st.integers(1, 2), n_el=st.integers(1, 3), adversarial=st.booleans())
+def test_o2_equals_o1_labelled(seed, n, k, extra, n_labels, n_el, adversarial):
     rng = np.random.Generator(np.random.PCG64(seed))
-    g = _labelled_graph(rng, n, 2 * n + extra, n_labels, n_el, multi)
+    g = _labelled_graph(rng, n, 2 * n + extra, n_labels, n_el)
     q = _labelled_query(rng, k, n_labels, n_el)
     b = _labelled_batch(rng, g, 10, adversarial)
     _check_o2_equals_o1(g, q, b)
@@ -139,10 +141,10 @@ def _subdivide(g, q, b):
 
 @settings(max_examples=60, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(seed=st.integers(0, 2**31 - 1), n=st.integers(3, 7), k=st.integers(2, 4), extra=st.integers(0, 8),
-       n_el=st.integers(1, 3), multi=st.booleans())
-def test_subdivision_identity(seed, n, k, extra, n_el, multi):
+       n_el=st.integers(1, 3))
+def test_subdivision_identity(seed, n, k, extra, n_el):
     rng = np.random.Generator(np.random.PCG64(seed))
-    g = _labelled_graph(rng, n, n + extra, 2, n_el, multi)
+    g = _labelled_graph(rng, n, n + extra, 2, n_el)
     q = _labelled_query(rng, k, 2, n_el)
     b = _labelled_batch(rng, g, 4, False)
     gs, qs, bs = _subdivide(g, q, b)
@@ -168,7 +170,7 @@ def test_one_edge_label_is_unlabelled(seed):
     """With every label 0 the labelled oracles give the unlabelled results
     (tuples, checksums, attribution)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    g = _labelled_graph(rng, 30, 120, 2, 1, False)
+    g = _labelled_graph(rng, 30, 120, 2, 1)
     gu = W.Graph(g.n, g.row_ptr, g.col, g.labels)
     q = _labelled_query(rng, 4, 2, 1)
     qu = W.Query(q.k, q.labels, q.edges)
@@ -184,22 +186,22 @@ def test_one_edge_label_is_unlabelled(seed):
 
 def test_labels_restrict_matches():
     """A triangle whose edges carry labels 0, 1, 2: the query with the same
-    labels (in any rotation that fits) matches it, a query asking for a label
-    the triangle lacks does not; parallel edges of two labels on one pair
-    serve two different query labels."""
+    labels matches it once per rotation that fits, a query asking for a
+    label the triangle lacks does not."""
     g = W.graph_from_labelled_edges(3, [(0, 1, 0), (1, 2, 1), (0, 2, 2)], [0, 0, 0], 3)
     tri = [(0, 1), (1, 2), (2, 0)]
     E = O1.edge_set_el(g)
-    want = O1.all_matches_el(3, g.labels, E, 3, [0, 0, 0], tri, [0, 1, 2])
-    assert want == {(0, 1, 2)}
+    assert O1.all_matches_el(3, g.labels, E, 3, [0, 0, 0], tri, [0, 1, 2]) == {(0, 1, 2)}
     assert O1.all_matches_el(3, g.labels, E, 3, [0, 0, 0], tri, [0, 0, 0]) == set()
-    g2 = W.graph_from_labelled_edges(2, [(0, 1, 0), (0, 1, 1)], [0, 0], 2)
-    q = W.query_from_edges(2, [(0, 1)], [0, 0], elabels=[1])
-    b = W.Batch(np.array([1], np.uint32), np.array([0], np.uint32), np.array([0], np.uint8),
-                np.array([1], np.uint32))
-    r1, r2 = _check_o2_equals_o1(g2, q, b)
-    assert r1["minus"] == {(0, 1), (1, 0)} and r1["D"] == [(0, 1, 1)]
-    assert (0, 1, 0) in r1["E2"]
+    # deleting the label-1 edge removes the match; deleting it under label 0 is a no-op
+    q = W.query_from_edges(3, tri, [0, 0, 0], elabels=[0, 1, 2])
+    b = W.Batch(np.array([2], np.uint32), np.array([1], np.uint32), np.array([0], np.uint8), np.array([1], np.uint32))
+    r1, r2 = _check_o2_equals_o1(g, q, b)
+    assert r1["minus"] == {(0, 1, 2)} and r1["D"] == [(1, 2, 1)]
+    wrong = W.Batch(np.array([2], np.uint32), np.array([1], np.uint32), np.array([0], np.uint8),
+                    np.array([0], np.uint32))
+    r1, r2 = _check_o2_equals_o1(g, q, wrong)
+    assert r1["minus"] == set() and r2.n_noop == 1
 
 
 def test_label_conflicts():
@@ -212,18 +214,27 @@ def test_label_conflicts():
     bad = W.Batch(np.array([2], np.uint32), np.array([3], np.uint32), np.array([1], np.uint8), np.array([2], np.uint32))
     assert O1.bdsm_el(g, q, bad)["status"] == "invalid"
     assert O2.run(g, q, bad).status == -1
+    # inserting a present pair under another label is invalid (the graph is simple)
+    relabel = W.Batch(np.array([1], np.uint32), np.array([0], np.uint32), np.array([1], np.uint8),
+                      np.array([1], np.uint32))
+    assert O1.bdsm_el(g, q, relabel)["status"] == "invalid"
+    assert O2.run(g, q, relabel).status == -1
     # deleting a pair under a label it does not carry is a no-op
     wrong = W.Batch(np.array([1], np.uint32), np.array([2], np.uint32), np.array([0], np.uint8),
                     np.array([0], np.uint32))
     r = O2.run(g, q, wrong)
     assert r.status == 0 and r.n_noop == 1 and r.n_canonical == 0
+    # a graph with two edges on one pair is not accepted
+    multi = W.graph_from_labelled_edges(2, [(0, 1, 0), (0, 1, 1)], [0, 0], 2)
+    with pytest.raises(ValueError):
+        O2.run(multi, q, wrong)
 
 
 def test_planted_edge_label_mistake_is_caught():
     caught = False
     for seed in range(40):
         rng = np.random.Generator(np.random.PCG64(1000 + seed))
-        g = _labelled_graph(rng, 7, 16, 1, 3, True)
+        g = _labelled_graph(rng, 7, 16, 1, 3)
         q = _labelled_query(rng, 3, 1, 3)
         b = _labelled_batch(rng, g, 6, False)
         r1 = O1.bdsm_el(g, q, b)

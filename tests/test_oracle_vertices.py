@@ -129,3 +129,19 @@ def test_vertex_insertion(seed):
     assert all(set(f) & {g.n, g.n + 1, g.n + 2} for f in r["plus"])
     o = O2.run(g2, q, b, want_tuples=True)
     assert o.status == 0 and o.tuple_set(1) == r["plus"]
+
+
+def test_vertex_deletion_on_labelled_graph():
+    """On an edge-labelled graph a deleted vertex takes each of its edges
+    with that edge's label."""
+    g = W.graph_from_labelled_edges(5, [(0, 1, 0), (1, 3, 1), (1, 2, 1), (2, 3, 0), (3, 4, 2)], [0] * 5, 3)
+    q = W.query_from_edges(2, [(0, 1)], (0, 0), elabels=[1])
+    empty = W.Batch(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint8), np.zeros(0, np.uint32))
+    status, merged = OV.deletion_batch(g, empty, [1])
+    assert status == "ok" and len(merged) == 3 and sorted(merged.elab.tolist()) == [0, 1, 1]
+    r = O1.bdsm_el(g, q, merged)
+    assert r["status"] == "ok" and r["plus"] == set()
+    assert r["minus"] == {(1, 3), (3, 1), (1, 2), (2, 1)}
+    assert r["E2"] == {(2, 3, 0), (3, 4, 2)}
+    o = O2.run(g, q, merged)
+    assert o.tuple_set(0) == r["minus"]
