@@ -64,13 +64,13 @@ def percentile(xs, p):
     return float(np.percentile(np.array(xs, dtype=float), p)) if xs else 0.0
 
 
-def cpu_baseline(w, queries, budget_s: float = 20.0):
+def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     """Time the oracle on a deterministic 1-in-M sample of the first batch's
     seeds (by canonical ord), shrinking M until the run takes a few seconds
     and has found matches (or the time budget is spent)."""
     from oracle import plain as O2
     threads = min(os.cpu_count() or 1, 16)
-    g, b = w.graph, w.batches[0]
+    g, b = w.graph, (w.batches[0] if batch is None else batch)
     M = 2048
     best = None
     spent = 0.0
@@ -125,7 +125,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "large", "batched", "served", "symmetric"])
+    ap.add_argument("--workload", default="mid",
+                    choices=["tiny", "mid", "large", "batched", "served", "symmetric", "elabel", "vertices"])
+    ap.add_argument("--vertex-deletions", type=int, default=64, help="vertices deleted per batch (vertices workload)")
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="offered loads (x capacity) for the served workload")
     ap.add_argument("--tune-points", type=int, default=24, help="autotuner evaluations (batched workload)")
     ap.add_argument("--unsolved-deadline-s", type=int, default=30,
@@ -166,8 +168,22 @@ def main():
         return run_served(args)
     if args.workload == "symmetric":
         return run_symmetric(args)
+    vdels = None
     if args.workload == "mid":
         w = W.mid(n_batches=n_batches)
+    elif args.workload == "elabel":
+        w = W.edge_labelled(n_batches=n_batches)
+    elif args.workload == "vertices":
+        # the mid stream plus vertex deletions in every batch (explicit
+        # insertions at a deleted vertex are left out: they would conflict)
+        w = W.mid(n_batches=n_batches)
+        w.name = "vertices-rmat20"
+        vdels = []
+        for i, b in enumerate(w.batches):
+            vd = W.vertex_deletions(w.graph, args.vertex_deletions, 1000 + i)
+            keep = ~((b.op == 1) & (np.isin(b.src, vd) | np.isin(b.dst, vd)))
+            w.batches[i] = W.Batch(b.src[keep], b.dst[keep], b.op[keep])
+            vdels.append(vd)
     elif args.workload == "large":
         w = W.large(n_batches=n_batches)
     else:
@@ -185,19 +201,20 @@ def main():
     unsolved_queries = [q for q, lo in zip(w.queries, left_out) if lo]
     ctx = Context(device=0, steal=not args.no_steal, waves_per_cu=args.waves_per_cu)
     t0 = time.time()
-    ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
+    ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels, elabels=w.graph.elab, n_elabels=w.graph.n_elabels)
     load_s = time.time() - t0
     for q in timed_queries:
-        ctx.register_query(q.k, q.labels, q.edges)
+        ctx.register_query(q.k, q.labels, q.edges, elabels=q.elabels)
     print("[bench] graph loaded in %.2fs" % load_s, file=sys.stderr, flush=True)
 
     batches = w.batches
     if args.workload == "tiny":
         # the tiny stream repeats one insert-only batch: alternate it with its inverse
         batches = [w.batches[0] if i % 2 == 0 else w.batches[0].inverse() for i in range(n_batches)]
+    vd_of = (lambda i: vdels[i]) if vdels is not None else (lambda i: None)
     for i in range(args.warmup):
         b = batches[i]
-        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True)
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(i))
         print("[bench] warmup %d: %.1f ms, matches %d" % (i, r.stats["ms_total"], int(r.counts.sum())),
               file=sys.stderr, flush=True)
 
@@ -206,7 +223,7 @@ def main():
     for i in range(args.steps):
         b = batches[args.warmup + i]
         t1 = time.perf_counter()
-        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True)
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(args.warmup + i))
         t2 = time.perf_counter()
         lat.append((t2 - t1) * 1e3)
         upd += r.stats["n_canonical"]
@@ -250,6 +267,10 @@ def main():
             "queries": [{"k": q.k, "edges": q.m, "kind": q.kind} for q in timed_queries],
             "batch_updates": len(batches[args.warmup]),
             "mode": "counts + hash (every match enumerated)",
+            **({"edge_labels": w.graph.n_elabels,
+                "query_edge_labels": [q.elabels.tolist() for q in timed_queries]} if w.graph.elab is not None else {}),
+            **({"vertex_deletions_per_batch": args.vertex_deletions,
+                "updates": "canonical edge updates incl. the deleted vertices' edges"} if vdels is not None else {}),
         },
         "phases_ms": phases,
         **({"unsolved": unsolved} if unsolved else {}),
@@ -267,7 +288,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, timed_queries)
+        first = None
+        if vdels is not None:
+            from oracle import vertices as OV
+            first = OV.deletion_batch(w.graph, w.batches[0], vdels[0])[1]
+        out["cpu_baseline"] = cpu_baseline(w, timed_queries, batch=first)
     print(json.dumps(out))
 
 

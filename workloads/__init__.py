@@ -767,6 +767,67 @@ def with_edge_labels(g: Graph, n_el: int, seed: int, skew: float = 1.0) -> Graph
     return Graph(g.n, g.row_ptr, g.col, g.labels, g.name, elab=elab, n_elabels=n_el)
 
 
+def pair_edge_labels(keys: np.ndarray, n_el: int, seed: int, skew: float = 1.0) -> np.ndarray:
+    """A label for every vertex pair (key lo << 32 | hi), a function of the
+    pair alone (splitmix64 of the key and seed, through the skewed
+    distribution of skewed_edge_label_draws): an edge keeps its label across
+    the graph, the batches that insert or delete it and a query planted on it."""
+    w = 1.0 / np.power(np.arange(1, n_el + 1, dtype=np.float64), skew)
+    cdf = np.cumsum(w / w.sum())
+    z = np.asarray(keys, dtype=np.uint64) ^ np.uint64(sub_seed(seed, 0xE1AB))
+    with np.errstate(over="ignore"):
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    return np.minimum(np.searchsorted(cdf, u, side="right"), n_el - 1).astype(np.uint32)
+
+
+def _pair_keys(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a = np.asarray(a, dtype=np.uint64)
+    b = np.asarray(b, dtype=np.uint64)
+    return (np.minimum(a, b) << np.uint64(32)) | np.maximum(a, b)
+
+
+def edge_labelled(seed: int = 0, n_batches: int = 1, n_el: int = 7, skew: float = 1.0, threads: int = 0) -> Workload:
+    """The mid workload with edge labels: every pair carries one of n_el
+    labels, skewed (a few frequent labels and a tail, like edge-labelled
+    graphs with uneven label counts); batch updates carry their pair's
+    label and the query's edges the labels of its planted match's edges."""
+    w = mid(seed, n_batches=n_batches, threads=threads)
+    g = w.graph
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr).astype(np.int64))
+    g.elab = pair_edge_labels(_pair_keys(src, g.col), n_el, seed, skew)
+    g.n_elabels = n_el
+    for b in w.batches:
+        b.elab = pair_edge_labels(_pair_keys(b.src, b.dst), n_el, seed, skew)
+    for q in w.queries:
+        pv = np.array(q.planted, dtype=np.uint64)
+        q.elabels = pair_edge_labels(_pair_keys(pv[q.edges[:, 0]], pv[q.edges[:, 1]]), n_el, seed, skew)
+    w.name = "elabel-rmat20"
+    w.meta["n_elabels"] = n_el
+    return w
+
+
+def vertex_deletions(g: Graph, count: int, seed: int, exclude=(), by_degree: bool = False) -> np.ndarray:
+    """`count` distinct vertices, uniformly (a removed account is a typical
+    vertex) or, with by_degree, with probability proportional to degree + 1
+    (on a power-law graph that picks hubs, whose deletion destroys most of
+    the matches through them)."""
+    d = Draws(sub_seed(seed, 0xDE1), 0xDE1)
+    deg = np.diff(g.row_ptr).astype(np.float64) + 1.0 if by_degree else np.ones(g.n)
+    cdf = np.cumsum(deg / deg.sum())
+    out, seen = [], set(int(x) for x in exclude)
+    while len(out) < count:
+        u = float(d.u64() >> 11) * (1.0 / (1 << 53))
+        v = int(min(np.searchsorted(cdf, u, side="right"), g.n - 1))
+        if v not in seen:
+            seen.add(v)
+            out.append(v)
+    return np.array(out, dtype=np.uint32)
+
+
 def graph_from_labelled_edges(n: int, triples: Sequence[Tuple[int, int, int]], labels: Sequence[int],
                               n_el: int, name: str = "") -> Graph:
     """CSR of labelled edges (u, v, e); a pair may carry several labels.
