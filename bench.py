@@ -64,40 +64,87 @@ def percentile(xs, p):
     return float(np.percentile(np.array(xs, dtype=float), p)) if xs else 0.0
 
 
+def _planted_ord(g, q, b):
+    """ord of the planted match's minimum-ord batch edge (its seed), from the
+    oracle's own canonical batch, or None."""
+    from oracle import plain as O2
+    if q.planted is None:
+        return None
+    r = O2.run(g, q, b, sample_mod=1 << 30, sample_rem=(1 << 30) - 1, want_tuples=False)
+    pv = [int(x) for x in q.planted]
+    pairs = {(min(pv[x], pv[y]), max(pv[x], pv[y])) for (x, y) in q.edges.tolist()}
+    ords = [i for i, (lo, hi) in enumerate(zip(r.canon_lo.tolist(), r.canon_hi.tolist())) if (lo, hi) in pairs]
+    return min(ords) if ords else None
+
+
 def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     """Time the oracle on a deterministic 1-in-M sample of the first batch's
     seeds (by canonical ord), shrinking M until the run takes a few seconds
-    and has found matches (or the time budget is spent)."""
+    and has found matches (or the time budget is spent).  When the matches
+    sit on so few updates that the sample (residue 0) holds none, the
+    residue class of a timed query's planted match is used instead.  The
+    same oracle on one thread is timed on a sub-sample (the same residue
+    class modulo a multiple of M that keeps the sample's busiest update)."""
     from oracle import plain as O2
     threads = min(os.cpu_count() or 1, 16)
     g, b = w.graph, (w.batches[0] if batch is None else batch)
+
+    per_ord = {}  # matches per sampled canonical ord (the oracle's own attribution)
+
+    def run(M, rem, nthreads):
+        tot_matches, tot_s, n_seeds = 0, 0.0, 0
+        per_ord.clear()
+        for qi, q in enumerate(queries):
+            r = O2.run(g, q, b, qid=qi, threads=nthreads, sample_mod=M, sample_rem=rem, want_tuples=False)
+            tot_matches += r.count[0] + r.count[1]
+            tot_s += r.seconds
+            n_seeds = len(range(rem, r.n_canonical, M))
+            for o in range(rem, r.n_canonical, M):
+                per_ord[o] = per_ord.get(o, 0) + int(r.seed_count[o])
+        return tot_matches, tot_s, n_seeds
+
     M = 2048
     best = None
     spent = 0.0
     while M >= 1:
-        tot_matches, tot_s, n_seeds = 0, 0.0, 0
-        for qi, q in enumerate(queries):
-            r = O2.run(g, q, b, qid=qi, threads=threads, sample_mod=M, sample_rem=0, want_tuples=False)
-            tot_matches += r.count[0] + r.count[1]
-            tot_s += r.seconds
-            n_seeds = len(range(0, r.n_canonical, M))
+        tot_matches, tot_s, n_seeds = run(M, 0, threads)
         spent += tot_s
-        best = (tot_matches, tot_s, M, n_seeds)
+        best = (tot_matches, tot_s, M, n_seeds, 0)
         if M == 1 or spent + 4 * tot_s > budget_s * 2:
             break
         if tot_matches > 0 and tot_s >= budget_s / 4:
             break
         M //= 4
-    matches, secs, M, n_seeds = best
+    matches, secs, M, n_seeds, rem = best
+    how = "seeds with canonical ord %% %d == 0" % M
+    anchor = 0  # an ord of the sample; the one-thread sub-sample keeps it
+    if matches == 0:
+        for q in queries:
+            o = _planted_ord(g, q, b) if batch is None else None
+            if o is not None:
+                tm, ts, ns = run(M, o % M, threads)
+                matches, secs, n_seeds, rem, anchor = tm, ts, ns, o % M, o
+                how = ("seeds with canonical ord %% %d == %d (the residue class of the planted match's seed: "
+                       "residue 0 held no matches)" % (M, o % M))
+                break
+    if per_ord and max(per_ord.values()) > 0:
+        anchor = max(per_ord, key=lambda o: (per_ord[o], -o))  # keep the sample's busiest update
+    M1 = M
+    while secs * threads * M / M1 > budget_s and M1 < (1 << 30):
+        M1 *= 4  # a sub-sample of the same residue class, about budget_s on one thread
+    one = run(M1, anchor % M1, 1)
     return {
         # no matches in the sample (they sit on a few updates): no rate to report
         "value": (matches / secs) if secs > 0 and matches > 0 else None,
         "unit": "matches/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "first batch, seeds with canonical ord %% %d == 0 (%d of %d updates), the timed queries; "
-                  "%d matches in %.2f s including the oracle's own graph update" % (
-                      M, n_seeds, len(b), matches, secs),
+        "sample": "first batch, %s (%d of %d updates), the timed queries; "
+                  "%d matches in %.2f s including the oracle's own graph update" % (how, n_seeds, len(b), matches, secs),
+        **({"one_thread": {"value": (one[0] / one[1]) if one[1] > 0 and one[0] > 0 else None,
+                           "unit": "matches/s",
+                           "sample": "ord %% %d == %d (%d updates): %d matches in %.2f s" % (
+                               M1, anchor % M1, one[2], one[0], one[1])}}),
     }
 
 
@@ -135,6 +182,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-steal", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--group-seeds", action="store_true", help="sort seeds by their first data vertex (tunable)")
+    ap.add_argument("--tuples", action="store_true",
+                    help="materialise every match (TUPLES) and copy the tuples to the host inside the timed step")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -199,7 +249,10 @@ def main():
     left_out = [args.workload == "large" and q.kind == "sparse" for q in w.queries]
     timed_queries = [q for q, lo in zip(w.queries, left_out) if not lo]
     unsolved_queries = [q for q, lo in zip(w.queries, left_out) if lo]
-    ctx = Context(device=0, steal=not args.no_steal, waves_per_cu=args.waves_per_cu)
+    ctx = Context(device=0, steal=not args.no_steal, waves_per_cu=args.waves_per_cu,
+                  tuple_capacity=(1 << 25) if args.tuples else 0)
+    if args.group_seeds:
+        ctx.set_tuning(group_seeds=2)
     t0 = time.time()
     ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels, elabels=w.graph.elab, n_elabels=w.graph.n_elabels)
     load_s = time.time() - t0
@@ -223,8 +276,11 @@ def main():
     for i in range(args.steps):
         b = batches[args.warmup + i]
         t1 = time.perf_counter()
-        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(args.warmup + i))
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(args.warmup + i),
+                            tuples=args.tuples)
         t2 = time.perf_counter()
+        if args.tuples and r.truncated:
+            raise SystemExit("tuple capacity reached: this workload has too many matches to materialise")
         lat.append((t2 - t1) * 1e3)
         upd += r.stats["n_canonical"]
         mat += int(r.counts.sum())
@@ -266,7 +322,8 @@ def main():
             "edges": w.graph.m,
             "queries": [{"k": q.k, "edges": q.m, "kind": q.kind} for q in timed_queries],
             "batch_updates": len(batches[args.warmup]),
-            "mode": "counts + hash (every match enumerated)",
+            "mode": ("tuples written to HBM and copied to host memory, plus counts + hash" if args.tuples
+                     else "counts + hash (every match enumerated)"),
             **({"edge_labels": w.graph.n_elabels,
                 "query_edge_labels": [q.elabels.tolist() for q in timed_queries]} if w.graph.elab is not None else {}),
             **({"vertex_deletions_per_batch": args.vertex_deletions,
@@ -406,19 +463,28 @@ def run_symmetric(args):
     ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
     for q in w.queries:
         ctx.register_query(q.k, q.labels, q.edges)
-    t_on, t_off, upd, mat = [], [], 0, 0
+    t_on, t_off, t_grp, t_both, upd, mat = [], [], [], [], 0, 0
     for i, b in enumerate(w.batches):
-        ctx.set_tuning(coalesced_search=1)
+        # dry runs: plain, update-edge grouping alone, both; then coalesced search applied
+        ctx.set_tuning(coalesced_search=1, group_seeds=1)
         r_off = ctx.apply_batch(b.src, b.dst, b.op, hash=True, dry_run=True)
-        ctx.set_tuning(coalesced_search=2)
+        ctx.set_tuning(coalesced_search=1, group_seeds=2)
+        r_grp = ctx.apply_batch(b.src, b.dst, b.op, hash=True, dry_run=True)
+        ctx.set_tuning(coalesced_search=2, group_seeds=2)
+        r_both = ctx.apply_batch(b.src, b.dst, b.op, hash=True, dry_run=True)
+        ctx.set_tuning(coalesced_search=2, group_seeds=1)
         r_on = ctx.apply_batch(b.src, b.dst, b.op, hash=True)
-        if not (np.array_equal(r_on.counts, r_off.counts) and np.array_equal(r_on.hash_sum, r_off.hash_sum)):
-            raise SystemExit("coalesced and plain search differ")
-        print("[bench] batch %d: coalesced %.1f ms, plain %.1f ms, %d matches" % (
-            i, r_on.stats["ms_total"], r_off.stats["ms_total"], int(r_on.counts.sum())), file=sys.stderr, flush=True)
+        for r in (r_off, r_grp, r_both):
+            if not (np.array_equal(r_on.counts, r.counts) and np.array_equal(r_on.hash_sum, r.hash_sum)):
+                raise SystemExit("coalesced, grouped and plain search differ")
+        print("[bench] batch %d: coalesced %.1f ms, plain %.1f ms, grouped %.1f ms, both %.1f ms, %d matches" % (
+            i, r_on.stats["ms_total"], r_off.stats["ms_total"], r_grp.stats["ms_total"], r_both.stats["ms_total"],
+            int(r_on.counts.sum())), file=sys.stderr, flush=True)
         if i >= args.warmup:
             t_on.append(r_on.stats["ms_total"])
             t_off.append(r_off.stats["ms_total"])
+            t_grp.append(r_grp.stats["ms_total"])
+            t_both.append(r_both.stats["ms_total"])
             upd += r_on.stats["n_canonical"]
             mat += int(r_on.counts.sum())
     ctx.close()
@@ -436,6 +502,11 @@ def run_symmetric(args):
         "plain_search": {"updates_per_s": upd / s_off, "matches_per_s": mat / s_off,
                          "p50_ms": percentile(t_off, 50), "p99_ms": percentile(t_off, 99),
                          "speedup_of_coalesced": s_off / s_on},
+        "update_edge_grouping": {"updates_per_s": upd / (sum(t_grp) / 1e3),
+                                 "p50_ms": percentile(t_grp, 50),
+                                 "speedup_over_plain": s_off / (sum(t_grp) / 1e3),
+                                 "with_coalesced": {"updates_per_s": upd / (sum(t_both) / 1e3),
+                                                    "p50_ms": percentile(t_both, 50)}},
     }
     print(json.dumps(out))
 

@@ -106,6 +106,10 @@ typedef struct gamma_tuning {
                                 automorphism of the query maps onto each other are searched
                                 once and the other matches are produced by permuting the
                                 found ones (Sec. V-B); 1 = off */
+  uint32_t group_seeds;   /* 2 = seeds sorted (stably) by their first data vertex before the
+                             search, so that waves starting together share rows (update-edge
+                             grouping); 1 = generation order (default).  With query_launch = 2
+                             seeds stay in generation order. */
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),

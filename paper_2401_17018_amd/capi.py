@@ -56,10 +56,11 @@ class Tuning(ctypes.Structure):
         ("query_launch", ctypes.c_uint32),
         ("handover_gate", ctypes.c_uint32),
         ("coalesced_search", ctypes.c_uint32),
+        ("group_seeds", ctypes.c_uint32),
     ]
 
     FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch", "handover_gate",
-              "coalesced_search")
+              "coalesced_search", "group_seeds")
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in self.FIELDS}

@@ -135,6 +135,19 @@ __global__ void k_label_index(GmGraphDev G, const uint32_t* __restrict__ verts, 
   }
 }
 
+// Update-edge grouping: sort keys (position << ib | a) of the seeds, then
+// the seeds gathered in key order (a stable sort by a, the first data vertex).
+__global__ void k_seed_keys(const GmSeed* __restrict__ seeds, uint64_t n, int ib, uint64_t* __restrict__ keys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    keys[i] = (i << ib) | seeds[i].a;
+}
+
+__global__ void k_seed_gather(const GmSeed* __restrict__ in, const uint64_t* __restrict__ keys, uint64_t n, int ib,
+                              GmSeed* __restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = in[keys[i] >> ib];
+}
+
 // The search starts with one unfinished work item per seed of its window.
 __global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds - ctr->seed_begin; }
 
@@ -164,6 +177,16 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, uint32_t ro
 }
 
 void launch_pending_init(GmCounters* ctr, hipStream_t s) { k_pending_init<<<1, 1, 0, s>>>(ctr); }
+
+void launch_seed_keys(const GmSeed* seeds, uint64_t n, int ib, uint64_t* keys, hipStream_t s) {
+  if (!n) return;
+  k_seed_keys<<<grid_for(n, 256), 256, 0, s>>>(seeds, n, ib, keys);
+}
+
+void launch_seed_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int ib, GmSeed* out, hipStream_t s) {
+  if (!n) return;
+  k_seed_gather<<<grid_for(n, 256), 256, 0, s>>>(in, keys, n, ib, out);
+}
 void launch_seed_window(GmCounters* ctr, hipStream_t s) { k_seed_window<<<1, 1, 0, s>>>(ctr); }
 
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,

@@ -177,6 +177,10 @@ void launch_filter(GmGraphDev G, const uint32_t* verts, uint32_t nv, uint32_t ro
                    const GmFilterEntry* fe, const GmReq* reqs, uint16_t* cand, uint32_t only_q,
                    hipStream_t s);
 void launch_pending_init(GmCounters* ctr, hipStream_t s);
+// update-edge grouping: keys (position << ib | seed.a), sorted by the caller over the low ib bits,
+// then the seeds gathered in key order
+void launch_seed_keys(const GmSeed* seeds, uint64_t n, int ib, uint64_t* keys, hipStream_t s);
+void launch_seed_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int ib, GmSeed* out, hipStream_t s);
 // opens the seed window of the next search launch: seed_begin = seed_head =
 // n_seeds; sets the deadline origin on the first call of a batch
 void launch_seed_window(GmCounters* ctr, hipStream_t s);

@@ -84,7 +84,7 @@ struct gamma_ctx {
   DevBuf b_src, b_dst, b_op, b_el, keys, keys_tmp, hist, hist_scan, scan_tmp, keep, ords;
   DevBuf canon_lo, canon_hi, canon_sign, canon_a, canon_b, canon_e, hkeys, hvals, dkeys, dkeys_tmp;
   DevBuf runvals, runscan, touched, run_start, run_end, sizes, r1off, r2_off, r2_len;
-  DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr;
+  DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr, seeds_tmp, gkeys, gkeys_tmp;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep;
   DevBuf lix, lix_lab, r0_off, r0_len, permtab, qeltab;
@@ -116,7 +116,7 @@ struct gamma_ctx {
                       &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp, &keep, &ords, &canon_lo, &canon_e,
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
                       &runvals, &runscan, &touched, &run_start, &run_end, &sizes, &r1off, &r2_off,
-                      &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &tmp64a,
+                      &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &seeds_tmp, &gkeys, &gkeys_tmp, &tmp64a,
                       &tmp64b, &tmp32a};
     for (DevBuf* b : list) all.push_back(b);
   }
@@ -430,6 +430,7 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
   c->tun.query_launch = 1;
   c->tun.handover_gate = 2;
   c->tun.coalesced_search = 2;
+  c->tun.group_seeds = 1;
   *out = c;
   return GAMMA_OK;
 }
@@ -801,10 +802,31 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
     const bool per_query = C.tun.query_launch == 2 && nq > 1;
     gm::launch_seed_window(ctr, s);
-    if (nq && !per_query)
+    if (nq && !per_query) {
       gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                        (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu,
                        C.tun.coalesced_search == 2 ? 1u : 0u, s);
+      if (C.tun.group_seeds == 2) {
+        // update-edge grouping: a stable sort of the seeds by their first
+        // data vertex (keys: position << ibr | a, ibr = ib rounded up to the
+        // sort's 8-bit digits so that no digit mixes in position bits),
+        // then a gather
+        unsigned long long hn = 0;
+        chk(hipMemcpyAsync(&hn, &ctr->n_seeds, 8, hipMemcpyDeviceToHost, s), "d2h");
+        chk(hipStreamSynchronize(s), "sync");
+        const uint64_t ns = std::min<uint64_t>(hn, seed_cap);
+        const int ibr = (ib + 7) & ~7;
+        if (ns > 1 && ns < (1ull << (64 - ibr))) {
+          uint64_t* gk = C.ensure<uint64_t>(C.gkeys, ns);
+          uint64_t* gt = C.ensure<uint64_t>(C.gkeys_tmp, ns);
+          GmSeed* so = C.ensure<GmSeed>(C.seeds_tmp, ns);
+          gm::launch_seed_keys(sd, ns, ibr, gk, s);
+          C.sort_keys(gk, gt, ns, ibr);
+          gm::launch_seed_gather(sd, gk, ns, ibr, so, s);
+          chk(hipMemcpyAsync(sd, so, ns * sizeof(GmSeed), hipMemcpyDeviceToDevice, s), "copy");
+        }
+      }
+    }
     chk(hipEventRecord(C.ev[4], s), "event");
 
     // ---------------------------------------------------------- search
@@ -1136,7 +1158,7 @@ bool tuning_ok(const gamma_tuning& t) {
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
          (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
-         (t.coalesced_search == 1 || t.coalesced_search == 2);
+         (t.coalesced_search == 1 || t.coalesced_search == 2) && (t.group_seeds == 1 || t.group_seeds == 2);
 }
 }  // namespace
 
@@ -1151,6 +1173,7 @@ gamma_status gamma_set_tuning(gamma_ctx* c, const gamma_tuning* in) {
   if (in->query_launch) t.query_launch = in->query_launch;
   if (in->handover_gate) t.handover_gate = in->handover_gate;
   if (in->coalesced_search) t.coalesced_search = in->coalesced_search;
+  if (in->group_seeds) t.group_seeds = in->group_seeds;
   if (!tuning_ok(t)) return fail(c, GAMMA_EINVAL, "set_tuning: value out of range");
   c->tun = t;
   return GAMMA_OK;
@@ -1167,7 +1190,8 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
   auto same = [](const gamma_tuning& a, const gamma_tuning& b) {
     return a.waves_per_cu == b.waves_per_cu && a.steal == b.steal && a.poll_cycles == b.poll_cycles &&
            a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch &&
-           a.handover_gate == b.handover_gate && a.coalesced_search == b.coalesced_search;
+           a.handover_gate == b.handover_gate && a.coalesced_search == b.coalesced_search &&
+           a.group_seeds == b.group_seeds;
   };
   gamma_status err = GAMMA_OK;
   // median device time of `reps` dry runs at tuning t (< 0: failed)
@@ -1221,9 +1245,10 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
         }
       }
     };
-    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1};
+    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1}, gs_v[] = {1, 2};
     if (many_q) sweep(&gamma_tuning::query_launch, ql_v, 2);
     sweep(&gamma_tuning::coalesced_search, cs_v, 2);
+    if (cur.query_launch == 1) sweep(&gamma_tuning::group_seeds, gs_v, 2);
     sweep(&gamma_tuning::steal, steal_v, 2);
     sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);
     if (cur.steal == 1) {

@@ -77,6 +77,7 @@ def test_per_query_launches_identical():
 
 TUNINGS = [
     dict(waves_per_cu=4, steal=1, poll_cycles=500, split_inner=2, split_leaf=2, handover_gate=1024),  # hand over almost anything
+    dict(waves_per_cu=8, steal=1, group_seeds=2),  # seeds grouped by their first data vertex
     dict(waves_per_cu=32, steal=1, poll_cycles=1000000, split_inner=1 << 20, split_leaf=1 << 20),
     dict(waves_per_cu=12, steal=2),
     dict(waves_per_cu=1, steal=1, poll_cycles=3000, handover_gate=1),
@@ -98,7 +99,7 @@ def test_tunables_do_not_change_results(seed):
             outs.append(ctx.apply_batch(b.src, b.dst, b.op, per_update=True, tuples=True, dry_run=True))
     for o in outs[1:]:
         _same(outs[0], o)
-    assert outs[0].stats["steals"] > 0 and outs[2].stats["steals"] == 0
+    assert outs[0].stats["steals"] > 0 and outs[3].stats["steals"] == 0
     check_against_o2(outs[0], g, q, b, check_tuples=not outs[0].truncated)
 
 
@@ -106,7 +107,7 @@ def test_set_tuning_rejects_out_of_range():
     with make_ctx(cap=0) as ctx:
         before = ctx.get_tuning()
         for bad in (dict(split_inner=1), dict(waves_per_cu=33), dict(steal=3), dict(query_launch=7),
-                    dict(poll_cycles=10), dict(handover_gate=2000)):
+                    dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=3)):
             with pytest.raises(GammaError) as ei:
                 ctx.set_tuning(**bad)
             assert ei.value.status == capi.GAMMA_EINVAL
