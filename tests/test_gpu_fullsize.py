@@ -65,3 +65,45 @@ def test_star_and_edge_closed_forms_on_large_graph():
     print("[fullsize] large: n=%d m=%d" % (w.graph.n, w.graph.m), flush=True)
     res = star_and_edge_check(w.graph, w.batches[0])
     assert res.count(0, 1) > 0
+
+
+@pytest.mark.parametrize("name,M", [("elabel", 16), ("vertices", 512)])
+def test_full_size_sampled_attribution_next4(name, M):
+    """The edge-labelled mid workload (7 skewed edge labels) and the mid
+    workload with 64 vertex deletions in its batch, at full size with the
+    default tuning: per-update attribution of a 1-in-M sample of the
+    canonical batch equals the oracle's; batch identities hold."""
+    from oracle import vertices as OV
+    if name == "elabel":
+        w = W.edge_labelled()
+        b, vd, ref_batch = w.batches[0], None, w.batches[0]
+    else:
+        w = W.mid()
+        b0 = w.batches[0]
+        vd = W.vertex_deletions(w.graph, 64, 1000)
+        keep = ~((b0.op == 1) & (np.isin(b0.src, vd) | np.isin(b0.dst, vd)))
+        b = W.Batch(b0.src[keep], b0.dst[keep], b0.op[keep])
+        status, ref_batch = OV.deletion_batch(w.graph, b, vd)
+        assert status == "ok"
+    q = w.queries[0]
+    print("[fullsize] %s: n=%d m=%d, batch %d updates" % (name, w.graph.n, w.graph.m, len(ref_batch)), flush=True)
+    with Context(device=0) as ctx:
+        ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels, elabels=w.graph.elab, n_elabels=w.graph.n_elabels)
+        ctx.register_query(q.k, q.labels, q.edges, elabels=q.elabels)
+        res = ctx.apply_batch(b.src, b.dst, b.op, elab=b.elab, delete_vertices=vd, hash=True, per_update=True,
+                              canonical=True)
+    nc = int(res.stats["n_canonical"])
+    sign = res.canon_sign.astype(bool)
+    assert int(res.upd_count.sum()) == int(res.counts.sum())
+    assert int(res.upd_count[sign].sum()) == res.count(0, 1)
+    assert int(res.upd_count[~sign].sum()) == res.count(0, 0)
+    ref = O2.run(w.graph, q, ref_batch, qid=0, threads=16, sample_mod=M, sample_rem=0, want_tuples=False)
+    assert ref.status == 0 and ref.n_canonical == nc
+    assert np.array_equal(res.canon_lo, ref.canon_lo) and np.array_equal(res.canon_hi, ref.canon_hi)
+    idx = np.arange(0, nc, M)
+    print("[fullsize] %s: %d sampled updates, %d oracle matches in %.1f s" % (
+        name, len(idx), int(ref.seed_count[idx].sum()), ref.seconds), flush=True)
+    assert int(ref.seed_count[idx].sum()) > 0
+    assert np.array_equal(res.upd_count[idx], ref.seed_count[idx])
+    assert np.array_equal(res.upd_hash_sum[idx], ref.seed_hsum[idx])
+    assert np.array_equal(res.upd_hash_xor[idx], ref.seed_hxor[idx])
