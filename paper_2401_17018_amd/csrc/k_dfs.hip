@@ -117,6 +117,10 @@ __device__ inline uint64_t uni64(uint64_t x) {
 __device__ inline uint32_t lane_val(uint32_t x, uint32_t i) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)i);
 }
+// value of lane i (i per lane, 0..63)
+__device__ inline uint32_t lane_at(uint32_t x, uint32_t i) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(i << 2), (int)x);
+}
 __device__ inline uint64_t lane_val64(uint64_t x, uint32_t i) {
   return ((uint64_t)lane_val((uint32_t)(x >> 32), i) << 32) | lane_val((uint32_t)x, i);
 }
@@ -970,13 +974,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       TALLY_ALWAYS(7, (uint32_t)__popcll(pm));
       const uint32_t lenv = ((pm >> lane) & 1ull) ? my_len : 0u;
       const uint32_t incl = wave_incl_scan(lenv, lane);  // end of each survivor's range
+      const uint32_t excl = incl - lenv;                  // its start
       const uint32_t T = lane_val(incl, GM_WAVE - 1);
       const uint32_t b0 = (uint32_t)__ffsll((unsigned long long)pm) - 1;
       const uint32_t nb1 = uni(S.st_n);
       const uint64_t st_h = uni64(S.st_h);
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
       const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
-      uint64_t wnd = pm;  // survivors whose range is not finished
       for (uint32_t t0 = 0; t0 < T; t0 += LEAF_UNROLL * GM_WAVE) {
         // the cycle-counter read behind a poll is a scalar memory access:
         // every 4th step is often enough
@@ -984,33 +988,24 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           abort_now = true;
           return;
         }
-        while (wnd && lane_val(incl, (uint32_t)__ffsll((unsigned long long)wnd) - 1) <= t0) wnd &= wnd - 1;
-        // survivor of each candidate: scan the few survivors overlapping
-        // [t0, t0 + 256) (lanes past T read survivor b0's first entry)
+        // survivor of each candidate t: the first lane whose range ends
+        // after t.  incl is non-decreasing over the 64 lanes (lanes that
+        // are not packed survivors add 0), so a 6-step binary search over
+        // it finds that lane, whatever the number of survivors in the
+        // window.  Lanes past T read survivor b0's first entry.
         uint32_t sl[LEAF_UNROLL], off[LEAF_UNROLL];
-        bool ok[LEAF_UNROLL], found[LEAF_UNROLL];
+        bool ok[LEAF_UNROLL];
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) {
           const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
           ok[j] = t < T;
-          sl[j] = b0;
-          off[j] = t;
-          found[j] = false;
-        }
-        const uint32_t tend = t0 + LEAF_UNROLL * GM_WAVE;
-        for (uint64_t w = wnd; w; w &= w - 1) {
-          const uint32_t b = (uint32_t)__ffsll((unsigned long long)w) - 1;
-          const uint32_t hb = lane_val(incl, b), lb = hb - lane_val(lenv, b);
-          if (lb >= tend) break;
+          uint32_t pos = 0;
 #pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
-            const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
-            if (ok[j] && !found[j] && t < hb) {
-              sl[j] = b;
-              off[j] = lb;
-              found[j] = true;
-            }
-          }
+          for (uint32_t step = GM_WAVE / 2; step; step >>= 1)
+            if (lane_at(incl, pos + step - 1) <= t) pos += step;
+          const uint32_t lb = lane_at(excl, pos);
+          sl[j] = ok[j] ? pos : b0;
+          off[j] = ok[j] ? lb : t;
         }
         uint32_t e[LEAF_UNROLL], x[LEAF_UNROLL], cs[LEAF_UNROLL];
 #pragma unroll
