@@ -380,6 +380,14 @@ gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, 
 gamma_status gamma_serve_submit(gamma_server* srv, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
                                 const uint8_t* op, uint64_t* ticket);
 
+/* As gamma_serve_submit on an edge-labelled graph: update i names the
+ * triple (src[i], dst[i], elab[i]) (elab NULL: all 0), labels < the
+ * graph's n_elabels (else EINVAL); one pair twice in a request must be the
+ * same triple with the same op (else ECONFLICT).  A request naming a pair
+ * of the forming batch under another label or op starts the next batch. */
+gamma_status gamma_serve_submit_el(gamma_server* srv, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                   const uint8_t* op, const uint32_t* elab, uint64_t* ticket);
+
 /* Move up to `max` committed requests (ticket order) into out[]; *n_out
  * receives how many.  Each is returned once. */
 gamma_status gamma_serve_poll(gamma_server* srv, gamma_request_result* out, uint32_t max, uint32_t* n_out);

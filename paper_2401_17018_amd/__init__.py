@@ -399,14 +399,17 @@ class Server:
                "serve_create")
         self.n_queries = len(ctx.query_k)
 
-    def submit(self, src, dst, op) -> int:
+    def submit(self, src, dst, op, elab=None) -> int:
+        """Queue one request; elab: its edge labels (edge-labelled graphs)."""
         s = np.ascontiguousarray(src, dtype=np.uint32)
         d = np.ascontiguousarray(dst, dtype=np.uint32)
         o = np.ascontiguousarray(op, dtype=np.uint8)
+        e = None if elab is None else np.ascontiguousarray(elab, dtype=np.uint32)
         t = ctypes.c_uint64()
-        st = self._lib.gamma_serve_submit(self._ptr, int(s.shape[0]), s.ctypes.data_as(ctypes.c_void_p),
-                                          d.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p),
-                                          ctypes.byref(t))
+        st = self._lib.gamma_serve_submit_el(self._ptr, int(s.shape[0]), s.ctypes.data_as(ctypes.c_void_p),
+                                             d.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p),
+                                             e.ctypes.data_as(ctypes.c_void_p) if e is not None else None,
+                                             ctypes.byref(t))
         if st < 0:
             raise GammaError(st, "serve_submit: %s" % self._lib.gamma_status_string(st).decode())
         return int(t.value)

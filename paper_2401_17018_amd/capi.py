@@ -25,7 +25,7 @@ EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
     "gamma_load_graph_el", "gamma_register_query_el", "gamma_apply_batch_el", "gamma_export_graph_el",
     "gamma_apply_batch_vertices", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
-    "gamma_serve_create", "gamma_serve_submit", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
+    "gamma_serve_create", "gamma_serve_submit", "gamma_serve_submit_el", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
     "gamma_serve_get_batch", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
     "gamma_validate_query", "gamma_validate_batch", "gamma_status_string", "gamma_last_error",
@@ -217,6 +217,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_serve_create.argtypes = [P, ctypes.POINTER(ServeOptions), ctypes.POINTER(P)]
     lib.gamma_serve_submit.restype = st
     lib.gamma_serve_submit.argtypes = [P, u32, P, P, P, ctypes.POINTER(u64)]
+    lib.gamma_serve_submit_el.restype = st
+    lib.gamma_serve_submit_el.argtypes = [P, u32, P, P, P, P, ctypes.POINTER(u64)]
     lib.gamma_serve_poll.restype = st
     lib.gamma_serve_poll.argtypes = [P, ctypes.POINTER(RequestResult), u32, ctypes.POINTER(u32)]
     lib.gamma_serve_drain.restype = st

@@ -5,6 +5,7 @@
 struct gamma_ctx;
 
 namespace gm {
-// true if a graph is loaded; *n receives its vertex count
-bool ctx_has_graph(const gamma_ctx* c, uint32_t* n);
+// true if a graph is loaded; *n receives its vertex count and *n_el (may
+// be null) its number of edge labels
+bool ctx_has_graph(const gamma_ctx* c, uint32_t* n, uint32_t* n_el = nullptr);
 }  // namespace gm

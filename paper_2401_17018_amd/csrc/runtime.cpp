@@ -1034,9 +1034,10 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
 }  // extern "C"
 
 namespace gm {
-bool ctx_has_graph(const gamma_ctx* c, uint32_t* n) {
+bool ctx_has_graph(const gamma_ctx* c, uint32_t* n, uint32_t* n_el) {
   if (!c || !c->has_graph) return false;
   if (n) *n = c->n;
+  if (n_el) *n_el = c->n_el;
   return true;
 }
 }  // namespace gm

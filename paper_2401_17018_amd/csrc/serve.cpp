@@ -12,7 +12,9 @@
 // the graph that applying its requests one by one would give, and the
 // batch's net result (|+| - |-| per query) equals the sum of theirs.
 // Batches are applied and committed in order; a request completes when its
-// batch is committed.
+// batch is committed.  On an edge-labelled graph requests name triples
+// (u, v, label): a request that names a pair of the batch under another
+// label, or with the other op, also closes the batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +37,7 @@ struct Request {
   double t_submit;
   std::vector<uint32_t> src, dst;
   std::vector<uint8_t> op;
+  std::vector<uint32_t> el;  // edge labels (empty: all 0)
 };
 
 struct BatchRecord {
@@ -47,7 +50,7 @@ struct BatchRecord {
 struct gamma_server {
   gamma_ctx* ctx = nullptr;
   gamma_serve_options opt{};
-  uint32_t n = 0;
+  uint32_t n = 0, n_el = 1;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request> queue;
@@ -62,10 +65,14 @@ struct gamma_server {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
 
+  static uint32_t tag(const Request& r, size_t i) {
+    return ((r.el.empty() ? 0u : r.el[i]) << 1) | (r.op[i] ? 1u : 0u);
+  }
+
   void run() {
-    std::vector<uint32_t> src, dst;
+    std::vector<uint32_t> src, dst, el;
     std::vector<uint8_t> op;
-    std::unordered_map<uint64_t, uint8_t> seen;
+    std::unordered_map<uint64_t, uint32_t> seen;  // pair -> label << 1 | op
     for (;;) {
       std::vector<Request> take;
       {
@@ -83,13 +90,13 @@ struct gamma_server {
             for (size_t i = 0; i < r.op.size() && !conflict; ++i) {
               const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
               auto it = seen.find((a << 32) | b);
-              conflict = it != seen.end() && it->second != (r.op[i] ? 1 : 0);
+              conflict = it != seen.end() && it->second != tag(r, i);
             }
             if (conflict) break;
           }
           for (size_t i = 0; i < r.op.size(); ++i) {
             const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
-            seen[(a << 32) | b] = r.op[i] ? 1 : 0;
+            seen[(a << 32) | b] = tag(r, i);
           }
           nupd += r.op.size();
           take.push_back(std::move(r));
@@ -100,16 +107,21 @@ struct gamma_server {
       src.clear();
       dst.clear();
       op.clear();
+      el.clear();
       for (auto& r : take) {
         src.insert(src.end(), r.src.begin(), r.src.end());
         dst.insert(dst.end(), r.dst.begin(), r.dst.end());
         op.insert(op.end(), r.op.begin(), r.op.end());
+        if (r.el.empty())
+          el.insert(el.end(), r.op.size(), 0u);
+        else
+          el.insert(el.end(), r.el.begin(), r.el.end());
       }
       const double t_start = now_ms();
       gamma_batch_result res;
       std::memset(&res, 0, sizeof(res));
-      const gamma_status st = gamma_apply_batch(ctx, (uint32_t)op.size(), src.data(), dst.data(), op.data(),
-                                                GAMMA_MEM_HOST, opt.flags, &res);
+      const gamma_status st = gamma_apply_batch_el(ctx, (uint32_t)op.size(), src.data(), dst.data(), op.data(),
+                                                   n_el > 1 ? el.data() : nullptr, GAMMA_MEM_HOST, opt.flags, &res);
       const double t_done = now_ms();
       BatchRecord rec;
       std::memset(&rec.info, 0, sizeof(rec.info));
@@ -156,13 +168,14 @@ gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, 
   if (o.max_batch_updates > (1u << 20) || (o.coalesce != 1 && o.coalesce != 2) ||
       (o.flags & (GAMMA_F_TUPLES | GAMMA_F_DRY_RUN | GAMMA_F_CANONICAL)))
     return GAMMA_EINVAL;
-  uint32_t n = 0;
-  if (!gm::ctx_has_graph(ctx, &n)) return GAMMA_ESTATE;
+  uint32_t n = 0, n_el = 1;
+  if (!gm::ctx_has_graph(ctx, &n, &n_el)) return GAMMA_ESTATE;
   gamma_server* s = new (std::nothrow) gamma_server();
   if (!s) return GAMMA_ENOMEM;
   s->ctx = ctx;
   s->opt = o;
   s->n = n;
+  s->n_el = n_el;
   s->t0 = std::chrono::steady_clock::now();
   try {
     s->worker = std::thread([s] { s->run(); });
@@ -174,8 +187,8 @@ gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, 
   return GAMMA_OK;
 }
 
-gamma_status gamma_serve_submit(gamma_server* s, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
-                                const uint8_t* op, uint64_t* ticket) {
+gamma_status gamma_serve_submit_el(gamma_server* s, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                   const uint8_t* op, const uint32_t* elab, uint64_t* ticket) {
   if (!s) return GAMMA_EINVAL;
   if (n_upd == 0 || n_upd > s->opt.max_batch_updates) return GAMMA_EINVAL;
   const gamma_status v = gamma_validate_batch(s->n, n_upd, src, dst, op);
@@ -184,6 +197,17 @@ gamma_status gamma_serve_submit(gamma_server* s, uint32_t n_upd, const uint32_t*
   r.src.assign(src, src + n_upd);
   r.dst.assign(dst, dst + n_upd);
   r.op.assign(op, op + n_upd);
+  if (elab) {
+    r.el.assign(elab, elab + n_upd);
+    // labels in range; one pair twice must be the same triple (with the same op)
+    std::unordered_map<uint64_t, uint32_t> pairs;
+    for (uint32_t i = 0; i < n_upd; ++i) {
+      if (r.el[i] >= s->n_el) return GAMMA_EINVAL;
+      const uint64_t a = std::min(src[i], dst[i]), b = std::max(src[i], dst[i]);
+      auto ins = pairs.emplace((a << 32) | b, gamma_server::tag(r, i));
+      if (!ins.second && ins.first->second != gamma_server::tag(r, i)) return GAMMA_ECONFLICT;
+    }
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return GAMMA_ESTATE;
   r.ticket = s->next_ticket++;
@@ -192,6 +216,11 @@ gamma_status gamma_serve_submit(gamma_server* s, uint32_t n_upd, const uint32_t*
   s->queue.push_back(std::move(r));
   s->cv_work.notify_one();
   return GAMMA_OK;
+}
+
+gamma_status gamma_serve_submit(gamma_server* s, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                const uint8_t* op, uint64_t* ticket) {
+  return gamma_serve_submit_el(s, n_upd, src, dst, op, nullptr, ticket);
 }
 
 gamma_status gamma_serve_poll(gamma_server* s, gamma_request_result* out, uint32_t max, uint32_t* n_out) {

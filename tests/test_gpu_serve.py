@@ -196,3 +196,94 @@ def test_concurrent_submitters():
                 single.apply_batch(r[0], r[1], r[2])
         ref = _graph(single, g.labels)
     assert np.array_equal(final.row_ptr, ref.row_ptr) and np.array_equal(final.col, ref.col)
+
+
+def _labelled_request_stream(g, seed, n_req, max_size):
+    """Requests on labelled triples, valid in sequence: insert an absent pair
+    with some label, delete a present pair under its label; revisits make
+    later requests delete or re-insert (under a new label) pairs earlier
+    requests touched."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    src = np.repeat(np.arange(g.n, dtype=np.uint64), np.diff(g.row_ptr).astype(np.int64))
+    keep = src < g.col.astype(np.uint64)
+    keys = (src[keep] << np.uint64(32)) | g.col.astype(np.uint64)[keep]
+    present = dict(zip(keys.tolist(), g.elab[keep].tolist()))
+    touched, reqs = [], []
+    for _ in range(n_req):
+        size = int(rng.integers(1, max_size + 1))
+        ups, seen = [], set()
+        while len(ups) < size:
+            if touched and rng.random() < 0.3:
+                key = touched[int(rng.integers(0, len(touched)))]
+            else:
+                u, v = (int(x) for x in rng.integers(0, g.n, 2))
+                if u == v:
+                    continue
+                key = (min(u, v) << 32) | max(u, v)
+            if key in seen:
+                continue
+            seen.add(key)
+            if key in present:
+                ups.append((key >> 32, key & 0xFFFFFFFF, present[key], 0))
+            else:
+                ups.append((key & 0xFFFFFFFF, key >> 32, int(rng.integers(0, g.n_elabels)), 1))
+        for (a, b, e, o) in ups:
+            key = (min(a, b) << 32) | max(a, b)
+            if o:
+                present[key] = e
+            else:
+                present.pop(key, None)
+            touched.append(key)
+        reqs.append(tuple(np.array(x, dt) for x, dt in zip(zip(*ups), (np.uint32, np.uint32, np.uint32, np.uint8))))
+    return [(s, d, o, e) for (s, d, e, o) in reqs]
+
+
+def test_served_labelled_stream_isolation():
+    g = W.with_edge_labels(_er(900, 5000, 47, 2), 3, 48)
+    qs = [W.query_from_edges(3, [(0, 1), (1, 2)], (0, 1, 0), elabels=[0, 1]),
+          W.query_from_edges(3, [(0, 1), (1, 2), (2, 0)], (0, 0, 1), elabels=[0, 0, 2])]
+    reqs = _labelled_request_stream(g, 5, 40, 60)
+
+    def setup(ctx):
+        ctx.load_graph(g.row_ptr, g.col, g.labels, elabels=g.elab, n_elabels=g.n_elabels)
+        for q in qs:
+            ctx.register_query(q.k, q.labels, q.edges, elabels=q.elabels)
+
+    def graph_of(ctx):
+        rp, col, lab, el, nel = ctx.export_graph_el()
+        return W.Graph(len(lab), rp, col, lab, elab=el, n_elabels=nel)
+
+    with make_ctx(cap=0) as ctx:
+        setup(ctx)
+        with Server(ctx, max_batch_updates=150) as srv:
+            with pytest.raises(GammaError) as ei:  # one pair under two labels in a request
+                srv.submit(np.array([1, 2], np.uint32), np.array([2, 1], np.uint32), np.array([1, 1], np.uint8),
+                           elab=np.array([0, 1], np.uint32))
+            assert ei.value.status == capi.GAMMA_ECONFLICT
+            with pytest.raises(GammaError) as ei:  # a label the graph does not have
+                srv.submit(np.array([1], np.uint32), np.array([2], np.uint32), np.array([1], np.uint8),
+                           elab=np.array([3], np.uint32))
+            assert ei.value.status == capi.GAMMA_EINVAL
+            for r in reqs:
+                srv.submit(r[0], r[1], r[2], elab=r[3])
+            srv.drain()
+            n_sub, n_com, n_bat = srv.counts()
+            batches = [srv.batch(i) for i in range(n_bat)]
+        served_final = graph_of(ctx)
+    assert n_sub == n_com == len(reqs) and 1 < len(batches) < len(reqs)
+    with make_ctx(cap=0) as plain:
+        setup(plain)
+        for b in batches:
+            assert b["status"] == 0
+            rs = reqs[b["first_ticket"]:b["first_ticket"] + b["n_requests"]]
+            merged = W.Batch(*(np.concatenate([r[i] for r in rs]) for i in range(4)))
+            before = graph_of(plain)
+            res = plain.apply_batch(merged.src, merged.dst, merged.op, elab=merged.elab, hash=True)
+            assert np.array_equal(res.counts, b["counts"]) and np.array_equal(res.hash_sum, b["hash_sum"])
+            for qid, q in enumerate(qs):
+                ref = O2.run(before, q, merged, qid=qid, threads=4, want_tuples=False)
+                assert [int(res.counts[qid, 0]), int(res.counts[qid, 1])] == [ref.count[0], ref.count[1]]
+                assert int(res.hash_xor[qid, 1]) == ref.hxor[1]
+        plain_final = graph_of(plain)
+    assert np.array_equal(served_final.row_ptr, plain_final.row_ptr)
+    assert np.array_equal(served_final.col, plain_final.col) and np.array_equal(served_final.elab, plain_final.elab)
