@@ -434,6 +434,15 @@ gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t 
                                   const uint32_t* qedges);
 gamma_status gamma_validate_batch(uint32_t n, uint32_t n_upd, const uint32_t* src,
                                   const uint32_t* dst, const uint8_t* op);
+/* Edge-labelled forms, the rules of gamma_load_graph_el and
+ * gamma_apply_batch_el: labels < n_elabels, a mirror entry carries its
+ * entry's label (validate_graph_el); one pair twice in a batch must be
+ * the same triple with the same op, else ECONFLICT (validate_batch_el).
+ * NULL labels: the unlabelled rules. */
+gamma_status gamma_validate_graph_el(uint32_t n, uint64_t nnz, const uint64_t* row_ptr, const uint32_t* col,
+                                     const uint32_t* labels, const uint32_t* elabels, uint32_t n_elabels);
+gamma_status gamma_validate_batch_el(uint32_t n, uint32_t n_elabels, uint32_t n_upd, const uint32_t* src,
+                                     const uint32_t* dst, const uint8_t* op, const uint32_t* elab);
 
 /* Text of a status code, and of the last error on a context. */
 const char* gamma_status_string(gamma_status s);

@@ -28,7 +28,7 @@ EXPORTS = [
     "gamma_serve_create", "gamma_serve_submit", "gamma_serve_submit_el", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
     "gamma_serve_get_batch", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
-    "gamma_validate_query", "gamma_validate_batch", "gamma_status_string", "gamma_last_error",
+    "gamma_validate_query", "gamma_validate_batch", "gamma_validate_graph_el", "gamma_validate_batch_el", "gamma_status_string", "gamma_last_error",
     "gamma_version",
 ]
 
@@ -241,6 +241,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_validate_query.argtypes = [u32, P, u32, P]
     lib.gamma_validate_batch.restype = st
     lib.gamma_validate_batch.argtypes = [u32, u32, P, P, P]
+    lib.gamma_validate_graph_el.restype = st
+    lib.gamma_validate_graph_el.argtypes = [u32, u64, P, P, P, P, u32]
+    lib.gamma_validate_batch_el.restype = st
+    lib.gamma_validate_batch_el.argtypes = [u32, u32, u32, P, P, P, P]
     lib.gamma_status_string.restype = ctypes.c_char_p
     lib.gamma_status_string.argtypes = [st]
     lib.gamma_last_error.restype = ctypes.c_char_p

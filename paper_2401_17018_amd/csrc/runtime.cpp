@@ -1392,6 +1392,40 @@ gamma_status gamma_validate_graph(uint32_t n, uint64_t nnz, const uint64_t* rp, 
   return GAMMA_OK;
 }
 
+gamma_status gamma_validate_graph_el(uint32_t n, uint64_t nnz, const uint64_t* rp, const uint32_t* col,
+                                     const uint32_t* labels, const uint32_t* elabels, uint32_t n_elabels) {
+  if (n_elabels == 0 || n_elabels > GAMMA_MAX_EDGE_LABELS || (!elabels && n_elabels != 1)) return GAMMA_EINVAL;
+  const gamma_status st = gamma_validate_graph(n, nnz, rp, col, labels);
+  if (st != GAMMA_OK || !elabels) return st;
+  // every label in range and equal on the mirror entry (the graph is simple)
+  for (uint32_t v = 0; v < n; ++v)
+    for (uint64_t j = rp[v]; j < rp[v + 1]; ++j) {
+      if (elabels[j] >= n_elabels) return GAMMA_EINVAL;
+      const uint32_t x = col[j];
+      const uint32_t* p = std::lower_bound(col + rp[x], col + rp[x + 1], v);
+      if (elabels[p - col] != elabels[j]) return GAMMA_EINVAL;
+    }
+  return GAMMA_OK;
+}
+
+gamma_status gamma_validate_batch_el(uint32_t n, uint32_t n_elabels, uint32_t n_upd, const uint32_t* src,
+                                     const uint32_t* dst, const uint8_t* op, const uint32_t* elab) {
+  if (n_elabels == 0 || n_elabels > GAMMA_MAX_EDGE_LABELS) return GAMMA_EINVAL;
+  const gamma_status st = gamma_validate_batch(n, n_upd, src, dst, op);
+  if (st != GAMMA_OK || !elab) return st;
+  std::vector<std::pair<uint64_t, uint32_t>> keys;  // pair, label << 1 | op
+  keys.reserve(n_upd);
+  for (uint32_t i = 0; i < n_upd; ++i) {
+    if (elab[i] >= n_elabels) return GAMMA_EINVAL;
+    const uint64_t lo = std::min(src[i], dst[i]), hi = std::max(src[i], dst[i]);
+    keys.push_back({(lo << 32) | hi, (elab[i] << 1) | (op[i] ? 1u : 0u)});
+  }
+  std::sort(keys.begin(), keys.end());
+  for (size_t i = 1; i < keys.size(); ++i)
+    if (keys[i].first == keys[i - 1].first && keys[i].second != keys[i - 1].second) return GAMMA_ECONFLICT;
+  return GAMMA_OK;
+}
+
 gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges) {
   return (gamma_status)gm::validate_query(k, qlabels, m, qedges, nullptr);
 }

@@ -102,3 +102,27 @@ def test_validate_batch(lib):
     assert validate_batch(5, [0, 1], [1, 0], [1, 0]) == capi.GAMMA_ECONFLICT
     assert validate_batch(5, [0, 1], [1, 0], [1, 1]) == 0  # duplicate, not a conflict
     assert validate_batch(5, [], [], []) == 0
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None and a.size else None
+
+
+def test_validate_labelled_graph_and_batch(lib):
+    g = W.graph_from_labelled_edges(4, [(0, 1, 0), (1, 2, 2), (2, 3, 1)], [0, 1, 0, 1], 3)
+    rp, col, lab, el = g.row_ptr, g.col, g.labels, g.elab
+    v = lambda e, L: lib.gamma_validate_graph_el(4, len(col), _p(rp), _p(col), _p(lab), _p(e), L)
+    assert v(el, 3) == 0
+    assert v(el, 2) == capi.GAMMA_EINVAL          # a label >= n_elabels
+    bad = el.copy()
+    bad[0] = (bad[0] + 1) % 3                     # mirror entry disagrees
+    assert v(bad, 3) == capi.GAMMA_EINVAL
+    assert v(None, 1) == 0 and v(None, 3) == capi.GAMMA_EINVAL
+    u32 = lambda *x: np.array(x, np.uint32)
+    vb = lambda s, d, o, e, L=3: lib.gamma_validate_batch_el(4, L, len(s), _p(s), _p(d), _p(np.array(o, np.uint8)),
+                                                            _p(e))
+    assert vb(u32(0, 1), u32(1, 2), [1, 0], u32(0, 2)) == 0
+    assert vb(u32(0, 1), u32(1, 0), [1, 1], u32(0, 1)) == capi.GAMMA_ECONFLICT  # one pair, two labels
+    assert vb(u32(0, 1), u32(1, 0), [1, 1], u32(2, 2)) == 0                     # duplicate triple
+    assert vb(u32(0), u32(1), [1], u32(3)) == capi.GAMMA_EINVAL                 # label out of range
+    assert vb(u32(0), u32(1), [1], None) == 0
