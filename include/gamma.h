@@ -340,10 +340,12 @@ typedef struct gamma_server gamma_server;
 typedef struct gamma_serve_options {
   uint32_t max_batch_updates; /* admission limit per device batch, 1..2^20 (0 = 2^17); a single
                                  request may not exceed it */
-  uint32_t flags;             /* GAMMA_F_HASH / GAMMA_F_PER_UPDATE for every batch (no TUPLES,
-                                 DRY_RUN or CANONICAL) */
+  uint32_t flags;             /* GAMMA_F_HASH / GAMMA_F_PER_UPDATE / GAMMA_F_TUPLES (+ SEED_ATTR)
+                                 for every batch (no DRY_RUN or CANONICAL) */
   uint32_t coalesce;          /* 1 = continuous batching (default), 2 = one request per batch */
-  uint32_t reserved[5];
+  uint32_t tuple_fill_pct;    /* with TUPLES: admission keeps a batch's estimated tuples within
+                                 this share of the context's tuple_capacity, 1..100 (0 = 50) */
+  uint32_t reserved[4];
 } gamma_serve_options;
 
 /* A committed request. */
@@ -367,6 +369,8 @@ typedef struct gamma_serve_batch {
   int32_t status;
   float ms_device;       /* stats.ms_total of the batch */
   double t_start_ms, t_done_ms;
+  uint64_t n_tuples;       /* with TUPLES: tuple records kept for the batch */
+  uint64_t n_tuples_found; /* matches found (> n_tuples when the buffer overflowed: TRUNCATED) */
 } gamma_serve_batch;
 
 /* Start a server on a context with a loaded graph.  Errors: EINVAL (bad
@@ -402,6 +406,20 @@ gamma_status gamma_serve_counts(gamma_server* srv, uint64_t* submitted, uint64_t
  * NULL) of device batch `batch`.  Errors: EINVAL (no such batch). */
 gamma_status gamma_serve_get_batch(gamma_server* srv, uint64_t batch, gamma_serve_batch* info,
                                    gamma_query_result* queries, uint32_t max_queries);
+
+/* Match buffer of a served batch (servers created with GAMMA_F_TUPLES).
+ * Admission by estimated match-buffer memory: the server keeps a moving
+ * estimate of tuple records per update from the batches it has committed
+ * and admits requests into a batch while the estimate for the batch stays
+ * within tuple_fill_pct of the context's tuple_capacity (one request per
+ * batch until a batch has been seen).  After each commit the batch's
+ * records (layout as in gamma_batch_result) are copied to host memory and
+ * kept with the batch until the server is destroyed.  This copies up to
+ * max_records of them into caller host buffers (any may be NULL; ord only
+ * with SEED_ATTR); *n_records and *width receive the batch's totals.
+ * Errors: EINVAL (no such batch), ESTATE (the server keeps no tuples). */
+gamma_status gamma_serve_get_tuples(gamma_server* srv, uint64_t batch, uint32_t* tuples, uint32_t* meta,
+                                    uint32_t* ord, uint64_t max_records, uint64_t* n_records, uint32_t* width);
 
 /* Apply what is queued, stop the worker and free the server.  NULL is accepted. */
 gamma_status gamma_serve_destroy(gamma_server* srv);

@@ -387,13 +387,18 @@ class Server:
     through it."""
 
     def __init__(self, ctx: Context, max_batch_updates: int = 0, hash: bool = True, per_update: bool = False,
-                 coalesce: bool = True):
+                 coalesce: bool = True, tuples: bool = False, seed_attr: bool = False, tuple_fill_pct: int = 0):
+        """tuples: keep every batch's match records (the context needs a
+        tuple_capacity); admission then also bounds a batch's estimated
+        records by tuple_fill_pct of that capacity."""
         self._lib = ctx._lib
         self.ctx = ctx
         o = capi.ServeOptions()
         o.max_batch_updates = int(max_batch_updates)
-        o.flags = F_COUNT | (F_HASH if hash else 0) | (F_PER_UPDATE if per_update else 0)
+        o.flags = (F_COUNT | (F_HASH if hash else 0) | (F_PER_UPDATE if per_update else 0) |
+                   (F_TUPLES if tuples else 0) | (F_SEED_ATTR if tuples and seed_attr else 0))
         o.coalesce = 1 if coalesce else 2
+        o.tuple_fill_pct = int(tuple_fill_pct)
         self._ptr = ctypes.c_void_p()
         _check(self._lib, ctx._ptr, self._lib.gamma_serve_create(ctx._ptr, ctypes.byref(o), ctypes.byref(self._ptr)),
                "serve_create")
@@ -413,6 +418,19 @@ class Server:
         if st < 0:
             raise GammaError(st, "serve_submit: %s" % self._lib.gamma_status_string(st).decode())
         return int(t.value)
+
+    def tuples(self, batch: int):
+        """(tuples [n, width] uint32, meta [n], ord [n] or None) of a served batch."""
+        n, w = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(self._lib, None, self._lib.gamma_serve_get_tuples(self._ptr, int(batch), None, None, None, 0,
+                                                                 ctypes.byref(n), ctypes.byref(w)), "serve_get_tuples")
+        t = np.zeros((n.value, w.value), np.uint32)
+        m = np.zeros(n.value, np.uint32)
+        o = np.zeros(n.value, np.uint32)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        _check(self._lib, None, self._lib.gamma_serve_get_tuples(self._ptr, int(batch), ptr(t), ptr(m), ptr(o), n.value,
+                                                                 ctypes.byref(n), ctypes.byref(w)), "serve_get_tuples")
+        return t, m, o
 
     def poll(self, max_results: int = 1024) -> List[dict]:
         buf = (capi.RequestResult * max_results)()

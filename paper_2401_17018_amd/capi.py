@@ -26,7 +26,7 @@ EXPORTS = [
     "gamma_load_graph_el", "gamma_register_query_el", "gamma_apply_batch_el", "gamma_export_graph_el",
     "gamma_apply_batch_vertices", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
     "gamma_serve_create", "gamma_serve_submit", "gamma_serve_submit_el", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
-    "gamma_serve_get_batch", "gamma_serve_destroy",
+    "gamma_serve_get_batch", "gamma_serve_get_tuples", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
     "gamma_validate_query", "gamma_validate_batch", "gamma_validate_graph_el", "gamma_validate_batch_el", "gamma_status_string", "gamma_last_error",
     "gamma_version",
@@ -71,7 +71,8 @@ class ServeOptions(ctypes.Structure):
         ("max_batch_updates", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
         ("coalesce", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("tuple_fill_pct", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 4),
     ]
 
 
@@ -98,6 +99,8 @@ class ServeBatch(ctypes.Structure):
         ("ms_device", ctypes.c_float),
         ("t_start_ms", ctypes.c_double),
         ("t_done_ms", ctypes.c_double),
+        ("n_tuples", ctypes.c_uint64),
+        ("n_tuples_found", ctypes.c_uint64),
     ]
 
 
@@ -229,6 +232,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_serve_get_batch.argtypes = [P, u64, ctypes.POINTER(ServeBatch), ctypes.POINTER(QueryResult), u32]
     lib.gamma_serve_destroy.restype = st
     lib.gamma_serve_destroy.argtypes = [P]
+    lib.gamma_serve_get_tuples.restype = st
+    lib.gamma_serve_get_tuples.argtypes = [P, u64, P, P, P, u64, ctypes.POINTER(u64), ctypes.POINTER(u32)]
     lib.gamma_copy_tuples.restype = st
     lib.gamma_copy_tuples.argtypes = [P, P, P, P, u64, ctypes.c_int]
     lib.gamma_result_release.restype = st

@@ -1034,6 +1034,8 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
 }  // extern "C"
 
 namespace gm {
+uint64_t ctx_tuple_capacity(const gamma_ctx* c) { return c ? c->opt.tuple_capacity : 0; }
+
 bool ctx_has_graph(const gamma_ctx* c, uint32_t* n, uint32_t* n_el) {
   if (!c || !c->has_graph) return false;
   if (n) *n = c->n;

@@ -12,7 +12,9 @@
 // the graph that applying its requests one by one would give, and the
 // batch's net result (|+| - |-| per query) equals the sum of theirs.
 // Batches are applied and committed in order; a request completes when its
-// batch is committed.  On an edge-labelled graph requests name triples
+// batch is committed.  With TUPLES, admission also bounds a batch by its
+// estimated match-buffer use (a moving estimate of tuple records per
+// update), and each batch's records are copied out after its commit.  On an edge-labelled graph requests name triples
 // (u, v, label): a request that names a pair of the batch under another
 // label, or with the other op, also closes the batch.
 #include <hip/hip_runtime.h>
@@ -43,6 +45,8 @@ struct Request {
 struct BatchRecord {
   gamma_serve_batch info;
   std::vector<gamma_query_result> q;
+  std::vector<uint32_t> tup, meta, ord;  // tuple records (TUPLES)
+  uint32_t width = 0;
 };
 
 }  // namespace
@@ -58,6 +62,9 @@ struct gamma_server {
   std::vector<BatchRecord> batches;
   uint64_t next_ticket = 0, n_committed = 0;
   bool stop = false;
+  bool tuples = false;
+  double budget = 0;          // tuple records a batch may be estimated to fill
+  double per_update = -1.0;   // estimated tuple records per update (< 0: no batch seen yet)
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
 
@@ -86,6 +93,8 @@ struct gamma_server {
           Request& r = queue.front();
           if (!take.empty()) {
             if (opt.coalesce == 2 || nupd + r.op.size() > opt.max_batch_updates) break;
+            // admission by estimated match-buffer memory
+            if (tuples && (per_update < 0 || (double)(nupd + r.op.size()) * per_update > budget)) break;
             bool conflict = false;
             for (size_t i = 0; i < r.op.size() && !conflict; ++i) {
               const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
@@ -135,6 +144,20 @@ struct gamma_server {
         rec.info.n_canonical = res.n_canonical;
         rec.info.ms_device = res.stats.ms_total;
         rec.q.assign(res.queries, res.queries + res.n_queries);
+        if (tuples) {
+          const uint64_t nt = res.n_tuples;
+          rec.width = res.tuple_width;
+          rec.info.n_tuples = nt;
+          rec.info.n_tuples_found = res.n_tuples_found;
+          rec.tup.resize(std::max<uint64_t>(nt * rec.width, 1));
+          rec.meta.resize(std::max<uint64_t>(nt, 1));
+          if (opt.flags & GAMMA_F_SEED_ATTR) rec.ord.resize(std::max<uint64_t>(nt, 1));
+          if (nt)
+            gamma_copy_tuples(ctx, rec.tup.data(), rec.meta.data(), rec.ord.empty() ? nullptr : rec.ord.data(), nt,
+                              GAMMA_MEM_HOST);
+          const double rate = (double)res.n_tuples_found / std::max<double>(op.size(), 1.0);
+          per_update = per_update < 0 ? rate : 0.5 * per_update + 0.5 * rate;
+        }
       }
       std::lock_guard<std::mutex> lk(mu);
       rec.info.batch = batches.size();
@@ -165,9 +188,12 @@ gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, 
   if (opt) o = *opt;
   if (o.max_batch_updates == 0) o.max_batch_updates = 1u << 17;
   if (o.coalesce == 0) o.coalesce = 1;
-  if (o.max_batch_updates > (1u << 20) || (o.coalesce != 1 && o.coalesce != 2) ||
-      (o.flags & (GAMMA_F_TUPLES | GAMMA_F_DRY_RUN | GAMMA_F_CANONICAL)))
+  if (o.tuple_fill_pct == 0) o.tuple_fill_pct = 50;
+  if (o.max_batch_updates > (1u << 20) || (o.coalesce != 1 && o.coalesce != 2) || o.tuple_fill_pct > 100 ||
+      (o.flags & (GAMMA_F_DRY_RUN | GAMMA_F_CANONICAL)))
     return GAMMA_EINVAL;
+  const uint64_t tcap = gm::ctx_tuple_capacity(ctx);
+  if ((o.flags & GAMMA_F_TUPLES) && tcap == 0) return GAMMA_EINVAL;
   uint32_t n = 0, n_el = 1;
   if (!gm::ctx_has_graph(ctx, &n, &n_el)) return GAMMA_ESTATE;
   gamma_server* s = new (std::nothrow) gamma_server();
@@ -176,6 +202,8 @@ gamma_status gamma_serve_create(gamma_ctx* ctx, const gamma_serve_options* opt, 
   s->opt = o;
   s->n = n;
   s->n_el = n_el;
+  s->tuples = (o.flags & GAMMA_F_TUPLES) != 0;
+  s->budget = (double)tcap * o.tuple_fill_pct / 100.0;
   s->t0 = std::chrono::steady_clock::now();
   try {
     s->worker = std::thread([s] { s->run(); });
@@ -261,6 +289,22 @@ gamma_status gamma_serve_get_batch(gamma_server* s, uint64_t batch, gamma_serve_
   info->n_queries = (uint32_t)r.q.size();
   if (queries)
     for (uint32_t i = 0; i < std::min<uint32_t>(max_queries, (uint32_t)r.q.size()); ++i) queries[i] = r.q[i];
+  return GAMMA_OK;
+}
+
+gamma_status gamma_serve_get_tuples(gamma_server* s, uint64_t batch, uint32_t* tuples, uint32_t* meta, uint32_t* ord,
+                                    uint64_t max_records, uint64_t* n_records, uint32_t* width) {
+  if (!s) return GAMMA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (batch >= s->batches.size()) return GAMMA_EINVAL;
+  if (!s->tuples) return GAMMA_ESTATE;
+  const BatchRecord& r = s->batches[batch];
+  const uint64_t nt = r.info.n_tuples, k = std::min(nt, max_records);
+  if (n_records) *n_records = nt;
+  if (width) *width = r.width;
+  if (tuples && k) std::memcpy(tuples, r.tup.data(), k * r.width * 4);
+  if (meta && k) std::memcpy(meta, r.meta.data(), k * 4);
+  if (ord && k && !r.ord.empty()) std::memcpy(ord, r.ord.data(), k * 4);
   return GAMMA_OK;
 }
 

@@ -287,3 +287,51 @@ def test_served_labelled_stream_isolation():
         plain_final = graph_of(plain)
     assert np.array_equal(served_final.row_ptr, plain_final.row_ptr)
     assert np.array_equal(served_final.col, plain_final.col) and np.array_equal(served_final.elab, plain_final.elab)
+
+
+def test_served_tuples_with_match_buffer_admission():
+    """Serving with TUPLES: admission bounds each batch by its estimated
+    tuple records (half of a small tuple buffer).  Every batch's records
+    equal the plain path's for the same merged batch (or, if the estimate
+    was short and the buffer overflowed, the counts still do)."""
+    g = _er(800, 5000, 53, 2)
+    qs = _queries(21, [3, 4])
+    reqs = _request_stream(g, 23, 40, 50)
+    cap = 6000
+    with make_ctx(cap=cap) as ctx:
+        _setup(ctx, g, qs)
+        with pytest.raises(GammaError):  # TUPLES needs a tuple buffer
+            with make_ctx(cap=0) as c0:
+                _setup(c0, g, qs)
+                Server(c0, tuples=True)
+        with Server(ctx, tuples=True, seed_attr=True, tuple_fill_pct=50) as srv:
+            for r in reqs:
+                srv.submit(*r)
+            srv.drain()
+            n_sub, n_com, n_bat = srv.counts()
+            batches = [srv.batch(i) for i in range(n_bat)]
+            recs = [srv.tuples(i) for i in range(n_bat)]
+    assert n_sub == n_com == len(reqs)
+    assert batches[0]["n_requests"] == 1  # no estimate before the first batch
+    assert max(b["n_requests"] for b in batches) > 1
+    n_trunc = 0
+    with make_ctx(cap=1 << 20) as plain:
+        _setup(plain, g, qs)
+        for b, (t, m, o) in zip(batches, recs):
+            rs = reqs[b["first_ticket"]:b["first_ticket"] + b["n_requests"]]
+            merged = W.Batch(np.concatenate([r[0] for r in rs]), np.concatenate([r[1] for r in rs]),
+                             np.concatenate([r[2] for r in rs]))
+            res = plain.apply_batch(merged.src, merged.dst, merged.op, hash=True, tuples=True)
+            assert np.array_equal(res.counts, b["counts"]) and np.array_equal(res.hash_sum, b["hash_sum"])
+            assert b["n_tuples_found"] == int(res.counts.sum())
+            if b["status"] == capi.GAMMA_TRUNCATED:
+                n_trunc += 1
+                assert b["n_tuples"] == cap
+                continue
+            assert b["status"] == 0 and b["n_tuples"] == int(res.counts.sum()) == len(t)
+            for qid, q in enumerate(qs):
+                for sign in (0, 1):
+                    sel = m == ((qid << 1) | sign)
+                    got = {tuple(int(v) for v in row[:q.k]) for row in t[sel]}
+                    assert got == res.tuple_set(qid, sign, q.k)
+    assert n_trunc <= len(batches) // 4
