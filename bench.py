@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--unsolved-deadline-s", type=int, default=30,
                     help="deadline of the one attempt at a query left out of the timed steps (0: skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="after the stream: dry runs of the next batch from the same graph state (0: none)")
     ap.add_argument("--no-steal", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--group-seeds", action="store_true", help="sort seeds by their first data vertex (tunable)")
@@ -212,6 +214,8 @@ def main():
 
     n_batches = args.warmup + args.steps
     t0 = time.time()
+    if args.workload in ("mid", "elabel", "vertices", "large", "tiny") and args.reps > 0:
+        n_batches += 1  # the batch the repeated dry runs use
     if args.workload == "batched":
         return run_batched(args)
     if args.workload == "served":
@@ -291,6 +295,25 @@ def main():
             i, lat[-1], r.stats["ms_dfs"], r.stats["n_canonical"], int(r.counts.sum()), r.stats["steals"]),
             file=sys.stderr, flush=True)
     t_total = time.perf_counter() - t_start
+    same_batch = None
+    if args.reps > 0:
+        # the timing protocol's repeated runs: the next batch of the stream as
+        # dry runs (each restores the graph), one untimed, then `reps` timed
+        b = batches[args.warmup + args.steps]
+        vd = vd_of(args.warmup + args.steps)
+        runs = []
+        for i in range(args.reps + 1):
+            r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd, dry_run=True)
+            if i:
+                runs.append(r.stats)
+        tot = sorted(st["ms_total"] for st in runs)
+        same_batch = {"reps": args.reps, "min_ms": tot[0], "median_ms": tot[len(tot) // 2], "max_ms": tot[-1],
+                      "phases_ms_median": {k: sorted(st[k] for st in runs)[len(runs) // 2]
+                                           for k in ("ms_canon", "ms_merge", "ms_filter", "ms_seed", "ms_dfs",
+                                                     "ms_commit")},
+                      "timing": "device time (HIP events) of dry runs of the same batch from the same graph"}
+        print("[bench] same batch x%d: min %.1f median %.1f max %.1f ms" % (
+            args.reps, tot[0], tot[len(tot) // 2], tot[-1]), file=sys.stderr, flush=True)
     ctx.close()
     unsolved = ([attempt_unsolved(w, q, batches[0], args.unsolved_deadline_s) for q in unsolved_queries]
                 if args.unsolved_deadline_s > 0 else [])
@@ -330,6 +353,7 @@ def main():
                 "updates": "canonical edge updates incl. the deleted vertices' edges"} if vdels is not None else {}),
         },
         "phases_ms": phases,
+        **({"same_batch": same_batch} if same_batch else {}),
         **({"unsolved": unsolved} if unsolved else {}),
         "roofline": {
             "bound": "hbm",
