@@ -105,7 +105,13 @@ typedef struct gamma_tuning {
   uint32_t coalesced_search; /* 2 = on (default): directed query edges that a label-preserving
                                 automorphism of the query maps onto each other are searched
                                 once and the other matches are produced by permuting the
-                                found ones (Sec. V-B); 1 = off */
+                                found ones (Sec. V-B); 3 = also over the k-degenerated
+                                automorphic subgraph left by removing the degree-1 query
+                                vertices, for queries with no automorphism of their own: the
+                                core edges of one orbit are searched once, each core match is
+                                permuted by the core's automorphisms and the removed vertices
+                                are matched anew for each permutation; 1 = off.  Results are
+                                identical in every mode */
   uint32_t group_seeds;   /* 2 = seeds sorted (stably) by their first data vertex before the
                              search, so that waves starting together share rows (update-edge
                              grouping); 1 = generation order (default).  With query_launch = 2

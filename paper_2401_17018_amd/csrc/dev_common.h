@@ -46,6 +46,20 @@ struct alignas(16) GmPlan {
   uint32_t n_perm;
   uint32_t perm_base;
   uint32_t el;  // edge label of the query edge (x, y) (0 without edge labels)
+  // Coalesced search over a k-degenerated automorphic subgraph (Sec. V-B,
+  // the degree-1 query vertices removed): a plan of a core edge matches the
+  // n_core core vertices first; a representative (n_cperm >= 2) then
+  // re-enters level n_core once per permutation of its core prefix by the
+  // perms [cperm_base, cperm_base + n_cperm) (the first is the identity);
+  // n_cperm = 0: a core plan a representative stands for; 1: ordinary.
+  uint32_t n_core;
+  uint32_t n_cperm;
+  uint32_t cperm_base;
+  // Candidate test of query vertex u in a representative's core search:
+  // the data vertex must pass the filter of some query vertex in omask[u]
+  // (the positions pi^-1(u) over its permutations: any of them is where a
+  // permuted prefix may put it).  1 << u otherwise.
+  uint32_t omask[GM_MAX_K];
 };
 
 #define GM_MAX_PERM 16

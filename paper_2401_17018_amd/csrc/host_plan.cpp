@@ -67,7 +67,13 @@ int validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32
   return GAMMA_OK;
 }
 
-void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& label_count) {
+namespace {
+
+// Matching plan of the directed query edge (x, y).  With core_mask != 0
+// (the seed edge inside it) the vertices of core_mask are placed before any
+// other vertex.
+GmPlan make_plan(const HostQuery& q, uint32_t qindex, uint32_t x, uint32_t y, uint32_t el,
+                 const std::vector<uint64_t>& label_count, uint32_t core_mask) {
   const uint32_t k = q.k;
   std::vector<uint32_t> adjm(k, 0), deg(k, 0);
   for (auto& e : q.edges) {
@@ -80,70 +86,76 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
     uint32_t l = q.labels[u];
     return l < label_count.size() ? label_count[l] : 0;
   };
+  GmPlan p;
+  std::memset(&p, 0, sizeof(p));
+  p.k = k;
+  p.x = x;
+  p.y = y;
+  p.q = qindex;
+  p.el = el;
+  uint32_t matched = (1u << x) | (1u << y);
+  p.order[0] = x;
+  p.order[1] = y;
+  for (uint32_t l = 2; l < k; ++l) {
+    // while core vertices remain unplaced, only they are eligible
+    const bool core_first = core_mask && (core_mask & ~matched) != 0;
+    int best = -1;
+    for (uint32_t u = 0; u < k; ++u) {
+      if (matched & (1u << u)) continue;
+      if (core_first && !((core_mask >> u) & 1u)) continue;
+      uint32_t mn = __builtin_popcount(adjm[u] & matched);
+      if (mn == 0) continue;
+      if (best < 0) {
+        best = (int)u;
+        continue;
+      }
+      uint32_t bm = __builtin_popcount(adjm[best] & matched);
+      if (mn != bm) {
+        if (mn > bm) best = (int)u;
+        continue;
+      }
+      if (deg[u] != deg[best]) {
+        if (deg[u] > deg[best]) best = (int)u;
+        continue;
+      }
+      if (lcount(u) != lcount(best)) {
+        if (lcount(u) < lcount(best)) best = (int)u;
+        continue;
+      }
+    }
+    p.order[l] = (uint32_t)best;
+    matched |= 1u << best;
+  }
+  uint32_t bofs = 0;
+  uint32_t placed = 0;
+  for (uint32_t l = 0; l < k; ++l) {
+    uint32_t u = p.order[l];
+    p.pos[u] = l;
+    p.lab[l] = q.labels[u];
+    p.back[l] = l >= 2 ? (adjm[u] & placed) : 0;
+    p.bofs[l] = bofs;
+    if (l >= 2) bofs += __builtin_popcount(p.back[l]);
+    placed |= 1u << u;
+  }
+  p.n_core = k;
+  p.n_cperm = 1;
+  p.cperm_base = 0;
+  for (uint32_t u = 0; u < GM_MAX_K; ++u) p.omask[u] = 1u << u;
+  return p;
+}
+
+}  // namespace
+
+void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& label_count) {
   q.plans.clear();
-  std::vector<std::pair<uint32_t, uint32_t>> dirs;
-  std::vector<uint32_t> dir_el;
   for (size_t i = 0; i < q.edges.size(); ++i) {
     const auto& e = q.edges[i];
     const uint32_t el = i < q.elabels.size() ? q.elabels[i] : 0u;
-    dirs.push_back({e.first, e.second});
-    dirs.push_back({e.second, e.first});
-    dir_el.push_back(el);
-    dir_el.push_back(el);
-  }
-  for (size_t di = 0; di < dirs.size(); ++di) {
-    const auto& d = dirs[di];
-    GmPlan p;
-    std::memset(&p, 0, sizeof(p));
-    p.k = k;
-    p.x = d.first;
-    p.y = d.second;
-    p.q = qindex;
-    p.el = dir_el[di];
-    uint32_t matched = (1u << d.first) | (1u << d.second);
-    p.order[0] = d.first;
-    p.order[1] = d.second;
-    for (uint32_t l = 2; l < k; ++l) {
-      int best = -1;
-      for (uint32_t u = 0; u < k; ++u) {
-        if (matched & (1u << u)) continue;
-        uint32_t mn = __builtin_popcount(adjm[u] & matched);
-        if (mn == 0) continue;
-        if (best < 0) {
-          best = (int)u;
-          continue;
-        }
-        uint32_t bm = __builtin_popcount(adjm[best] & matched);
-        if (mn != bm) {
-          if (mn > bm) best = (int)u;
-          continue;
-        }
-        if (deg[u] != deg[best]) {
-          if (deg[u] > deg[best]) best = (int)u;
-          continue;
-        }
-        if (lcount(u) != lcount(best)) {
-          if (lcount(u) < lcount(best)) best = (int)u;
-          continue;
-        }
-      }
-      p.order[l] = (uint32_t)best;
-      matched |= 1u << best;
-    }
-    uint32_t bofs = 0;
-    uint32_t placed = 0;
-    for (uint32_t l = 0; l < k; ++l) {
-      uint32_t u = p.order[l];
-      p.pos[u] = l;
-      p.lab[l] = q.labels[u];
-      p.back[l] = l >= 2 ? (adjm[u] & placed) : 0;
-      p.bofs[l] = bofs;
-      if (l >= 2) bofs += __builtin_popcount(p.back[l]);
-      placed |= 1u << u;
-    }
-    q.plans.push_back(p);
+    q.plans.push_back(make_plan(q, qindex, e.first, e.second, el, label_count, 0));
+    q.plans.push_back(make_plan(q, qindex, e.second, e.first, el, label_count, 0));
   }
   coalesce_query(q);
+  coalesce_core(q, label_count);
 }
 
 namespace {
@@ -243,6 +255,107 @@ void coalesce_query(HostQuery& q) {
         for (uint32_t i = 0; i < k; ++i) pi.inv[pi.fwd[i]] = i;
         q.perms.push_back(pi);
         if (j != g0) q.plans[mb].n_perm = 0;
+      }
+    }
+  }
+}
+
+void coalesce_core(HostQuery& q, const std::vector<uint64_t>& label_count) {
+  const uint32_t k = q.k;
+  q.cperms.clear();
+  for (auto& p : q.plans) {
+    p.n_core = k;
+    p.n_cperm = 1;
+    p.cperm_base = 0;
+    for (uint32_t u = 0; u < GM_MAX_K; ++u) p.omask[u] = 1u << u;
+  }
+  if (k < 3) return;
+  for (auto& p : q.plans)
+    if (p.n_perm != 1) return;  // the whole query is symmetric: the k = 0 case applies
+  // the core: the query without its degree-1 vertices
+  std::vector<uint32_t> deg(k, 0);
+  for (auto& e : q.edges) {
+    deg[e.first]++;
+    deg[e.second]++;
+  }
+  std::vector<uint32_t> cid(k, 0xFFFFFFFFu), cv;
+  for (uint32_t u = 0; u < k; ++u)
+    if (deg[u] >= 2) {
+      cid[u] = (uint32_t)cv.size();
+      cv.push_back(u);
+    }
+  // (a core of two vertices would be the seed edge itself, whose level is
+  // entered by the seed rather than by a core match: not coalesced)
+  if (cv.size() < 3 || cv.size() == k) return;
+  HostQuery core;
+  core.k = (uint32_t)cv.size();
+  for (uint32_t v : cv) core.labels.push_back(q.labels[v]);
+  for (size_t i = 0; i < q.edges.size(); ++i) {
+    const auto& e = q.edges[i];
+    if (cid[e.first] == 0xFFFFFFFFu || cid[e.second] == 0xFFFFFFFFu) continue;
+    core.edges.push_back({cid[e.first], cid[e.second]});
+    core.elabels.push_back(i < q.elabels.size() ? q.elabels[i] : 0u);
+  }
+  if (core.edges.empty()) return;
+  std::vector<std::vector<uint32_t>> aut;
+  automorphisms(core, 4096, aut);
+  if (aut.size() <= 1) return;
+  uint32_t core_mask = 0;
+  for (uint32_t v : cv) core_mask |= 1u << v;
+  // core-edge plans match the core first; their groups follow the orbits of
+  // the core's directed edges (as for the whole query)
+  std::map<std::pair<uint32_t, uint32_t>, uint32_t> dir;  // core ids -> plan index
+  for (uint32_t i = 0; i < q.plans.size(); ++i) {
+    GmPlan& p = q.plans[i];
+    if (!((core_mask >> p.x) & 1u) || !((core_mask >> p.y) & 1u)) continue;
+    const uint32_t el = p.el, qi = p.q;
+    p = make_plan(q, qi, p.x, p.y, el, label_count, core_mask);
+    p.n_perm = 1;
+    p.perm_base = 0;
+    p.n_core = (uint32_t)cv.size();
+    dir[{cid[p.x], cid[p.y]}] = i;
+  }
+  const uint32_t kc = core.k;
+  GmPerm id;
+  std::memset(&id, 0, sizeof(id));
+  for (uint32_t i = 0; i < GM_MAX_K; ++i) id.fwd[i] = id.inv[i] = i;
+  std::map<uint32_t, char> seen;
+  for (auto& kv : dir) {
+    const uint32_t d0 = kv.second;
+    if (seen.count(d0)) continue;
+    std::vector<uint32_t> cls{d0};
+    std::map<uint32_t, std::vector<uint32_t>> tau;  // plan -> core automorphism taking d0 to it
+    seen[d0] = 1;
+    tau[d0].resize(kc);
+    for (uint32_t i = 0; i < kc; ++i) tau[d0][i] = i;
+    for (size_t h = 0; h < cls.size(); ++h) {
+      const uint32_t a = cls[h];
+      for (auto& sg : aut) {
+        const uint32_t b = dir.at({sg[cid[q.plans[a].x]], sg[cid[q.plans[a].y]]});
+        if (seen.count(b)) continue;
+        seen[b] = 1;
+        tau[b].resize(kc);
+        for (uint32_t i = 0; i < kc; ++i) tau[b][i] = sg[tau[a][i]];
+        cls.push_back(b);
+      }
+    }
+    for (size_t g0 = 0; g0 < cls.size(); g0 += GM_MAX_PERM) {
+      const size_t g1 = std::min(cls.size(), g0 + GM_MAX_PERM);
+      const uint32_t r = cls[g0];
+      q.plans[r].n_cperm = (uint32_t)(g1 - g0);
+      q.plans[r].cperm_base = (uint32_t)q.cperms.size();
+      for (size_t j = g0; j < g1; ++j) {
+        const uint32_t mb = cls[j];
+        std::vector<uint32_t> tinv(kc);
+        for (uint32_t i = 0; i < kc; ++i) tinv[tau[mb][i]] = i;
+        // pi = tau[r] o tau[mb]^-1 on core ids, the identity on the removed vertices
+        GmPerm pi = id;
+        for (uint32_t i = 0; i < kc; ++i) pi.fwd[cv[i]] = cv[tau[r][tinv[i]]];
+        for (uint32_t v = 0; v < k; ++v) pi.inv[pi.fwd[v]] = v;
+        q.cperms.push_back(pi);
+        if (j != g0) q.plans[mb].n_cperm = 0;
+        // the representative's vertex u lands on pi^-1(u)
+        for (uint32_t u = 0; u < k; ++u) q.plans[r].omask[u] |= 1u << pi.inv[u];
       }
     }
   }

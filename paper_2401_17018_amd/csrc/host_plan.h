@@ -18,6 +18,7 @@ struct HostQuery {
   std::vector<uint32_t> elabels;                      // [m] edge label per edge (0 without labels)
   std::vector<GmPlan> plans;                          // one per directed edge
   std::vector<GmPerm> perms;                          // coalesced search, referenced by plans
+  std::vector<GmPerm> cperms;                         // core-prefix permutations (k > 0 coalescing)
 };
 
 // Validates a query; on failure returns the status code (EINVAL or
@@ -36,6 +37,15 @@ void plan_query(HostQuery& q, uint32_t qindex, const std::vector<uint64_t>& labe
 // edges they map onto each other (groups of at most GM_MAX_PERM), and sets
 // each plan's n_perm / perm_base (perm_base indexes q.perms).
 void coalesce_query(HostQuery& q);
+
+// Coalesced search over the k-degenerated automorphic subgraph obtained by
+// removing the degree-1 query vertices (Sec. V-B), for queries whose own
+// automorphism group is trivial: if the remaining core has label- and
+// edge-label-preserving automorphisms, core-edge plans are re-planned core
+// first and grouped by the orbits of the core's directed edges (n_core,
+// n_cperm, cperm_base; cperm_base indexes q.cperms) and each
+// representative's omask is set.
+void coalesce_core(HostQuery& q, const std::vector<uint64_t>& label_count);
 
 // Candidate-filter tables for all queries over data labels < label_slots:
 // entries per data label (sorted by query), each with its neighbour-label

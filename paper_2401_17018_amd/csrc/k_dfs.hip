@@ -101,6 +101,13 @@ struct WaveState {
   uint32_t pf_len[GM_WAVE];
   uint64_t pf_base[GM_WAVE];
   uint64_t pf_h[GM_WAVE];  // its element term
+  // coalescing over a core (k-degenerated automorphic subgraph): the core
+  // prefix as the search found it, and the permutation now applied to it
+  uint32_t fcore[GM_MAX_K];
+  uint32_t fxcore[GM_MAX_K];
+  uint32_t ccw[GM_MAX_K];  // candidate-filter word of each core vertex's data vertex
+  uint32_t pidx;
+  uint32_t pvalid;  // bit p: permutation p puts every core data vertex where the filter admits it
 };
 
 // Plans and query records are never written during a search: reading them
@@ -306,11 +313,13 @@ __device__ inline void broadcast_stop(const GmDfsParams& P, int lane) {
     __hip_atomic_store(&P.mflag[s], MSG_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-#ifdef GM_DFS_WAVES_PER_EU
-#define GM_DFS_ATTR __attribute__((amdgpu_waves_per_eu(GM_DFS_WAVES_PER_EU)))
-#else
-#define GM_DFS_ATTR
+// Three waves per SIMD (12 per CU, the default launch) stay resident: the
+// register budget is held to 512 / 3 VGPRs, which this kernel meets without
+// spilling (left to itself the allocator lands just above it).
+#ifndef GM_DFS_WAVES_PER_EU
+#define GM_DFS_WAVES_PER_EU 3
 #endif
+#define GM_DFS_ATTR __attribute__((amdgpu_waves_per_eu(GM_DFS_WAVES_PER_EU)))
 
 __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) {
   __shared__ WaveState WS[DFS_WAVES];
@@ -366,6 +375,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     uint32_t q, dq, ord, sign, base_l;
     uint32_t tword = 0;  // handed-over work: lane w holds word w of the task record
     bool handed = false;
+    bool ptask = false;  // the handed work is a share of another wave's core permutations
     if (seeds_left) {
       if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) {
         if (lane == 0) atomicExch(&P.ctr->aborted, 1u);
@@ -428,7 +438,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint32_t os = lane_val(w, 1);
       ord = os >> 1;
       sign = os & 1u;
-      base_l = lane_val(w, 2);
+      const uint32_t w2 = lane_val(w, 2);
+      ptask = (w2 >> 31) != 0u;
+      base_l = w2 & 0x7FFFFFFFu;
       if (lane >= 8 && lane < 8 + GM_MAX_K) S.f[lane - 8] = w;
       handed = true;
     }
@@ -438,6 +450,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // coalesced search: this plan's matches stand for nperm permutations
     const uint32_t nperm = P.coalesce ? uni(pl->n_perm) : 1u;
     CPerm perm0 = (CPerm)P.perms + (P.coalesce ? uni(pl->perm_base) : 0u);
+    // coalescing over the core: after the n_core core levels, level L0 is
+    // entered once per permutation of the core prefix
+    const uint32_t ncp = P.coalesce >= 2 ? uni(pl->n_cperm) : 1u;
+    const uint32_t L0 = ncp > 1 ? uni(pl->n_core) : 0xFFFFFFFFu;
+    CPerm cperm0 = (CPerm)P.perms + (ncp > 1 ? uni(pl->cperm_base) : 0u);
     const uint32_t key = (q << 1) | sign;
     if (key != A.key) {
       flush_acc(P, A, lane);
@@ -478,7 +495,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // list drives the level, the others are probed.  Lane i < nb holds list
     // i as (w = query vertex, base = arena index of the subrange, sub = its
     // length).
-    const uint32_t pf_lvl = k >= 4 ? k - 2 : 0xFFFFFFFFu;
+    // (a plan that permutes its core prefix keeps it when level k-2 lies
+    // past the core, whose levels are all set up again under each
+    // permutation; with k-2 inside the core the prefetched state would
+    // belong to the identity only)
+    const uint32_t pf_lvl = (k >= 4 && (ncp <= 1 || L0 + 2 <= k)) ? k - 2 : 0xFFFFFFFFu;
     // checksum terms of every position but the last vertex's, for each
     // permutation pi of a coalesced plan: position i's vertex f(i) takes
     // position pi^-1(i) in the permuted tuple
@@ -676,7 +697,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
       for (uint32_t j = 0; j < l; ++j) ok = ok && (c != lane_val(fo_all, j));
       if (ok && l + 1 < k) {
-        ok = (P.cand[(uint64_t)q * n + c] >> u) & 1u;
+        // (a representative's core vertex passes for any of its positions)
+        const uint32_t om = ncp > 1 ? uni(pl->omask[u]) : 1u << u;
+        ok = (P.cand[(uint64_t)q * n + c] & om) != 0u;
         st_bytes += 2;
       }
       if (ok && (e & GM_FLAG)) ok = visible(P.H, S.drvv[l], c, ord, sign, st_bytes);
@@ -711,6 +734,24 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       uint32_t lv = 0xFFFFFFFFu, kind = 0, mid = 0, old_len = 0;
       uint64_t give = 0;
       for (uint32_t x = base_l; x <= lcur; ++x) {
+        if (x == L0 && base_l < L0) {
+          // the permutations of the core prefix not yet entered (each a
+          // whole subtree), when at least two are left: the upper half of
+          // them.  The donor keeps at least one, so a single permutation is
+          // never passed on (a wave that has just received one polls before
+          // entering it, and would hand it on again, and so on, for as long
+          // as some wave is idle).
+          const uint32_t pi = uni(S.pidx);
+          const uint32_t rem = uni(S.pvalid) & (pi == 0xFFFFFFFFu ? 0xFFFFFFFFu : ~((2u << pi) - 1u));
+          if (__popc(rem) >= 2) {
+            uint32_t g = rem;
+            for (int i = 0, h = (__popc(rem) + 1) / 2; i < h; ++i) g &= g - 1;  // drop the lower half
+            lv = x;
+            kind = 3;
+            give = g;
+            break;
+          }
+        }
         const uint32_t cur = uni(S.cur[x]), len = uni(S.len[x]);
         const uint32_t min_split = (x == k - 1) ? P.split_leaf : P.split_inner;
         if (len > cur && len - cur >= min_split) {
@@ -764,18 +805,20 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if ((uint32_t)lane < IDLE_REPS) atomicSub(&P.idle_rep[lane * IDLE_STRIDE], 1u);
       if (kind == 1)
         S.len[lv] = mid;
-      else
+      else if (kind == 2)
         S.mask[lv] = uni64(S.mask[lv]) & ~give;
+      else
+        S.pvalid = uni(S.pvalid) & ~(uint32_t)give;
       uint32_t w = 0;
       if (lane == 0) w = (q << 8) | dq;
       else if (lane == 1) w = (ord << 1) | sign;
-      else if (lane == 2) w = lv;
+      else if (lane == 2) w = kind == 3 ? (lv | 0x80000000u) : lv;
       else if (lane == 3) w = kind == 2 ? uni(S.chunk[lv]) : 0u;
       else if (lane == 4) w = (uint32_t)give;
       else if (lane == 5) w = (uint32_t)(give >> 32);
       else if (lane == 6) w = kind == 1 ? mid : 0u;
       else if (lane == 7) w = kind == 1 ? old_len : 0u;
-      else if (lane < 8 + GM_MAX_K) w = S.f[lane - 8];
+      else if (lane < 8 + GM_MAX_K) w = (kind == 3 || (lv < L0 && lcur >= L0)) ? S.fcore[lane - 8] : S.f[lane - 8];
       if (lane == 0) atomicAdd(&P.ctr->pending, 1ull);
       if (lane < TASK_WORDS) P.mbox[(uint64_t)target * TASK_WORDS + lane] = w;
       if (lane == 0) {
@@ -1052,12 +1095,88 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
     };
 
+    // core permutation p (0: the identity) of the prefix saved in fcore:
+    // query vertex v takes fcore[pi(v)]; positions < L0 are the core
+    auto apply_cperm = [&](uint32_t p) {
+      CPerm pp = cperm0 + p;
+      uint32_t v = 0, nf = 0, nx = 0;
+      if ((uint32_t)lane < L0) {
+        v = pl->order[lane];
+        const uint32_t src = pp->fwd[v];
+        nf = S.fcore[src];
+        nx = S.fxcore[src];
+      }
+      if ((uint32_t)lane < L0) {
+        S.f[v] = nf;
+        S.fx[v] = nx;
+        S.fo[lane] = nf;
+      }
+    };
+    // bit p set: permutation p puts every core vertex's data vertex where
+    // the filter admits it.  All permutations at once: lane t checks levels
+    // 4 (t & 3) .. 4 (t & 3) + 3 under permutation t / 4 (n_core <= 16 and
+    // at most 16 permutations fill the 64 lanes).
+    auto cperm_valid = [&]() -> uint32_t {
+      const uint32_t p = (uint32_t)lane >> 2;
+      bool bad = false;
+      if (p < ncp) {
+        CPerm pp = cperm0 + p;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+          const uint32_t i = ((uint32_t)lane & 3u) * 4u + j;
+          if (i < L0) {
+            const uint32_t v = pl->order[i];
+            bad = bad || !((S.ccw[pp->fwd[v]] >> v) & 1u);
+          }
+        }
+      }
+      const uint64_t b = __ballot(bad);
+      uint32_t ok = 0;
+      for (uint32_t q4 = 0; q4 < ncp; ++q4)
+        if (((b >> (4 * q4)) & 0xFull) == 0) ok |= 1u << q4;
+      return ok;
+    };
+    // back to the core prefix as found (the identity permutation)
+    auto restore_core = [&]() {
+      if ((uint32_t)lane < L0) {
+        const uint32_t v = pl->order[lane];
+        const uint32_t c = S.fcore[v];
+        S.f[v] = c;
+        S.fx[v] = S.fxcore[v];
+        S.fo[lane] = c;
+      }
+    };
+
     uint32_t l = base_l;
     bool pf_ok = false;  // level k-2's prefetch records belong to its current chunk
-    if (!init_level(l, !handed)) {
+    bool go;
+    if (ptask) {
+      // a share of another wave's core permutations: its core prefix (the
+      // identity) and the permutations to enter.  Level L0-1 stands used up
+      // below it, so that stepping back from L0 ends the task.
+      if ((uint32_t)lane < L0) {
+        const uint32_t v = pl->order[lane];
+        S.fcore[v] = S.f[v];
+        S.fxcore[v] = S.fx[v];
+      }
+      S.pvalid = lane_val(tword, 4);
+      S.pidx = 0xFFFFFFFFu;
+      base_l = L0 - 1;
+      S.cur[L0 - 1] = 0;
+      S.len[L0 - 1] = 0;
+      S.mask[L0 - 1] = 0;
+      l = L0;
+      S.cur[L0] = 0;
+      S.len[L0] = 0;
+      S.mask[L0] = 0;
+      go = true;
+    } else {
+      go = init_level(l, !handed);
+    }
+    if (!go) {
       // an empty first level (a seed with no extension)
     } else {
-      if (handed) {
+      if (handed && !ptask) {
         S.cur[l] = lane_val(tword, 6);
         S.len[l] = lane_val(tword, 7);
         S.chunk[l] = lane_val(tword, 3);
@@ -1067,6 +1186,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       for (;;) {
         uint64_t m = uni64(S.mask[l]);
+        uint32_t nl = 0xFFFFFFFFu;  // the level to set up next (none yet)
         if (m == 0) {
           if (poll(l)) {
             abort_now = true;
@@ -1075,53 +1195,101 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           const uint32_t cur = uni(S.cur[l]);
           if (cur >= uni(S.len[l])) {
             if (l == base_l) break;
-            --l;
-            continue;
-          }
-          const uint64_t t_ev = CYCLES();
-          if (l == k - 1) {
-            S.cur[l] = cur + LEAF_UNROLL * GM_WAVE;
-            leaf_step(cur);
-            TALLY(3, CYCLES() - t_ev);
-            continue;
-          }
-          S.cur[l] = cur + GM_WAVE;
-          S.chunk[l] = cur;
-          uint32_t c, eidx;
-          bool ok;
-          m = eval_chunk(l, cur, c, eidx, ok);
-          S.mask[l] = m;
-          TALLY(2, CYCLES() - t_ev);
-          if (l == pf_lvl) {
-            pf_ok = true;
-            if (m) {
-              const uint32_t my_len = prefetch_leaf(l, eidx, c, ok);
-              const uint64_t t_pk = CYCLES();
-              leaf_packed(l, m, my_len);
-              TALLY(3, CYCLES() - t_pk);
-              if (abort_now) break;
-              m = uni64(S.mask[l]);
+            // the core prefix's next permutation that puts every data
+            // vertex where the filter admits it (a received task starting
+            // at L0 searches its own permuted prefix only).  pidx + 1 <= 16.
+            if (l == L0 && (uni(S.pvalid) >> (uni(S.pidx) + 1)) != 0u) {
+              const uint32_t p0 = uni(S.pidx) + 1;
+              const uint32_t p = p0 + (uint32_t)__builtin_ctz(uni(S.pvalid) >> p0);
+              S.pidx = p;
+              apply_cperm(p);
+              l = L0 - 1;
+              nl = L0;
+            } else {
+              if (l == L0) restore_core();
+              --l;
+              continue;
             }
+          } else {
+            const uint64_t t_ev = CYCLES();
+            if (l == k - 1) {
+              S.cur[l] = cur + LEAF_UNROLL * GM_WAVE;
+              leaf_step(cur);
+              TALLY(3, CYCLES() - t_ev);
+              continue;
+            }
+            S.cur[l] = cur + GM_WAVE;
+            S.chunk[l] = cur;
+            uint32_t c, eidx;
+            bool ok;
+            m = eval_chunk(l, cur, c, eidx, ok);
+            S.mask[l] = m;
+            TALLY(2, CYCLES() - t_ev);
+            if (l == pf_lvl) {
+              pf_ok = true;
+              if (m) {
+                const uint32_t my_len = prefetch_leaf(l, eidx, c, ok);
+                const uint64_t t_pk = CYCLES();
+                leaf_packed(l, m, my_len);
+                TALLY(3, CYCLES() - t_pk);
+                if (abort_now) break;
+                m = uni64(S.mask[l]);
+              }
+            }
+            if (m == 0) continue;
           }
-          if (m == 0) continue;
         }
-        const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;
-        S.mask[l] = m & (m - 1);
-        if (l == pf_lvl && pf_ok) {
-          const uint64_t t0 = CYCLES();
-          const bool r = init_leaf_fast(bit);
-          TALLY(1, CYCLES() - t0);
-          if (r) ++l;
-          continue;
+        if (nl == 0xFFFFFFFFu) {
+          const uint32_t bit = (uint32_t)__ffsll((unsigned long long)m) - 1;
+          S.mask[l] = m & (m - 1);
+          if (l == pf_lvl && pf_ok) {
+            const uint64_t t0 = CYCLES();
+            const bool r = init_leaf_fast(bit);
+            TALLY(1, CYCLES() - t0);
+            if (r) ++l;
+            continue;
+          }
+          const uint64_t at = uni64(S.drv[l]) + uni(S.chunk[l]) + bit;
+          const uint32_t c = uni(col[at] & GM_IDMASK);
+          const uint32_t u = uni(pl->order[l]);
+          S.f[u] = c;
+          S.fo[l] = c;
+          S.fx[u] = uni(ext[at]);
+          st_bytes += 8;
+          if (l + 1 == L0) {
+            // a core match: keep it with its vertices' filter words and
+            // stand at level L0 used up under a permutation -1, so that the
+            // step back above enters the permutations from the identity on
+            if ((uint32_t)lane < L0) {
+              const uint32_t v = pl->order[lane];
+              const uint32_t fv = S.f[v];
+              S.fcore[v] = fv;
+              S.fxcore[v] = S.fx[v];
+              S.ccw[v] = P.cand[(uint64_t)q * n + fv];
+              st_bytes += 2;
+            }
+            S.pvalid = cperm_valid();
+            S.pidx = 0xFFFFFFFFu;
+            l = L0;
+            S.cur[L0] = 0;
+            S.len[L0] = 0;
+            S.mask[L0] = 0;
+            continue;
+          }
+          nl = l + 1;
         }
-        const uint64_t at = uni64(S.drv[l]) + uni(S.chunk[l]) + bit;
-        const uint32_t c = uni(col[at] & GM_IDMASK);
-        const uint32_t u = uni(pl->order[l]);
-        S.f[u] = c;
-        S.fo[l] = c;
-        S.fx[u] = uni(ext[at]);
-        st_bytes += 8;
-        if (init_level(l + 1, true)) ++l;
+        // one set-up site for every descent (the set-up is inlined where it
+        // is called, and each copy costs registers)
+        if (init_level(nl, true)) {
+          l = nl;
+        } else if (nl == L0) {
+          // no candidate under this permutation: stand at level L0 used up,
+          // so that the next pass tries the next permutation
+          l = L0;
+          S.cur[L0] = 0;
+          S.len[L0] = 0;
+          S.mask[L0] = 0;
+        }
       }
     }
     if (abort_now) break;

@@ -96,7 +96,12 @@ __global__ void k_seeds(const uint32_t* __restrict__ canon_a, const uint32_t* __
     for (uint32_t d = 0; d < Q.n_plans; ++d) {
       const GmPlan& P = plans[Q.plan_base + d];
       if (coalesce && P.n_perm == 0) continue;  // another plan's matches stand for this one's
-      if (((ca >> P.x) & 1u) && ((cb >> P.y) & 1u) && P.el == el) {
+      if (coalesce >= 2 && P.n_cperm == 0) continue;  // likewise over the core's permutations
+      // a representative's seed stands for the seeds of the plans it
+      // permutes into: a and b pass the filter of any of their positions
+      const bool core = coalesce >= 2 && P.n_cperm >= 2;
+      const uint32_t mx = core ? P.omask[P.x] : 1u << P.x, my = core ? P.omask[P.y] : 1u << P.y;
+      if ((ca & mx) && (cb & my) && P.el == el) {
         unsigned long long pos = atomicAdd(&ctr->n_seeds, 1ull);
         if (pos < cap) {
           GmSeed sd;

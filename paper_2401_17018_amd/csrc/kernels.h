@@ -84,7 +84,8 @@ struct GmDfsParams {
   uint32_t split_leaf;            // smallest last-level range worth handing over
   uint32_t gate;                  // hand-over attempt probability per idle wave, in 1/1024
   const GmPerm* perms;            // coalesced search: permutation table referenced by plans
-  uint32_t coalesce;              // 1: search representative plans only and permute their matches
+  uint32_t coalesce;              // 1: search representative plans only and permute their matches;
+                                  // 2: also permute core prefixes (plans with n_cperm >= 2)
   uint32_t pad3;
   const uint8_t* qel;             // [nq][16][16] edge label of query edge {u, w} (used when G.elb > 0)
 };

@@ -262,12 +262,15 @@ struct gamma_ctx {
         qel[t0 + a * GM_MAX_K + b] = qel[t0 + b * GM_MAX_K + a] = (uint8_t)q.elabels[e];
       }
       const uint32_t pofs = (uint32_t)all_perms.size();
+      const uint32_t cofs = pofs + (uint32_t)q.perms.size();
       for (auto& p : q.plans) {
         GmPlan pp = p;
         pp.perm_base += pofs;
+        pp.cperm_base += cofs;
         all_plans.push_back(pp);
       }
       all_perms.insert(all_perms.end(), q.perms.begin(), q.perms.end());
+      all_perms.insert(all_perms.end(), q.cperms.begin(), q.cperms.end());
     }
     if (!all_perms.empty()) {
       GmPerm* dperm = ensure<GmPerm>(permtab, all_perms.size());
@@ -805,7 +808,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     if (nq && !per_query) {
       gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                        (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu,
-                       C.tun.coalesced_search == 2 ? 1u : 0u, s);
+                       C.tun.coalesced_search - 1, s);
       if (C.tun.group_seeds == 2) {
         // update-edge grouping: a stable sort of the seeds by their first
         // data vertex (keys: position << ibr | a, ibr = ib rounded up to the
@@ -880,14 +883,14 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.split_leaf = C.tun.split_leaf;
       P.gate = C.tun.handover_gate;
       P.perms = (const GmPerm*)C.permtab.p;
-      P.coalesce = C.tun.coalesced_search == 2 ? 1u : 0u;
+      P.coalesce = C.tun.coalesced_search - 1;
       P.qel = (const uint8_t*)C.qeltab.p;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
           gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                            (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi,
-                           C.tun.coalesced_search == 2 ? 1u : 0u, s);
+                           C.tun.coalesced_search - 1, s);
         }
         gm::fill_u32(P.mflag, 0, slots, s);
         gm::fill_u64((uint64_t*)P.idle_bits, 0, (slots + 63) / 64, s);
@@ -1161,7 +1164,7 @@ bool tuning_ok(const gamma_tuning& t) {
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
          (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
-         (t.coalesced_search == 1 || t.coalesced_search == 2) && (t.group_seeds == 1 || t.group_seeds == 2);
+         t.coalesced_search >= 1 && t.coalesced_search <= 3 && (t.group_seeds == 1 || t.group_seeds == 2);
 }
 }  // namespace
 
@@ -1248,9 +1251,9 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
         }
       }
     };
-    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1}, gs_v[] = {1, 2};
+    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1, 3}, gs_v[] = {1, 2};
     if (many_q) sweep(&gamma_tuning::query_launch, ql_v, 2);
-    sweep(&gamma_tuning::coalesced_search, cs_v, 2);
+    sweep(&gamma_tuning::coalesced_search, cs_v, 3);
     if (cur.query_launch == 1) sweep(&gamma_tuning::group_seeds, gs_v, 2);
     sweep(&gamma_tuning::steal, steal_v, 2);
     sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);

@@ -597,6 +597,26 @@ def symmetric_queries(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Wo
     return w
 
 
+def core_symmetric_queries(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
+    """The mid graph and its batch stream with four queries that have no
+    automorphism of their own but whose cores (the query without its
+    degree-1 vertices) have: a triangle with labels 0, 1, 1 and a label-2
+    leaf on one label-1 vertex; a label-1 triangle with leaves of labels 4
+    and 5 on two of its vertices; a label-2 4-cycle with leaves of labels 4
+    and 5 on two adjacent vertices; two label-1 triangles on a shared edge
+    with leaves of labels 4 and 5 on a shared and an unshared vertex.
+    (About 10^10 matches change per batch, most of them the last two's.)"""
+    w = mid(seed, n_batches=n_batches, threads=threads)
+    w.queries = [
+        query_from_edges(4, [(0, 1), (1, 2), (2, 0), (1, 3)], (0, 1, 1, 2), "dense"),
+        query_from_edges(5, [(0, 1), (1, 2), (2, 0), (0, 3), (1, 4)], (1, 1, 1, 4, 5), "dense"),
+        query_from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (1, 5)], (2, 2, 2, 2, 4, 5), "sparse"),
+        query_from_edges(6, [(0, 1), (1, 2), (2, 0), (1, 3), (3, 0), (0, 4), (2, 5)], (1, 1, 1, 1, 4, 5), "dense"),
+    ]
+    w.name = "core-symmetric-rmat20"
+    return w
+
+
 def _batched_spec(seed: int, n_queries: int):
     d = Draws(sub_seed(seed, TAG_QUERY + 1000), TAG_QUERY)
     spec = []
