@@ -68,6 +68,11 @@ constexpr int LEAF_UNROLL = GM_LEAF_UNROLL;          // last-level chunks examin
 #define GM_PACK_MAX 512
 #endif
 constexpr uint32_t PACK_MAX = GM_PACK_MAX;
+// the last level polls (deadline, hand-over) once per this many steps
+#ifndef GM_POLL_STEPS
+#define GM_POLL_STEPS 4
+#endif
+constexpr uint32_t POLL_STEPS = GM_POLL_STEPS;
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
@@ -1188,11 +1193,14 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         uint64_t m = uni64(S.mask[l]);
         uint32_t nl = 0xFFFFFFFFu;  // the level to set up next (none yet)
         if (m == 0) {
-          if (poll(l)) {
+          const uint32_t cur = uni(S.cur[l]);
+          // the cycle-counter read behind a poll is a scalar memory access
+          // that the step waits for: at the last level, every 4th step is
+          // often enough (about 10 % of the mid search time)
+          if ((l + 1 < k || (cur & (POLL_STEPS * LEAF_UNROLL * GM_WAVE - 1)) == 0) && poll(l)) {
             abort_now = true;
             break;
           }
-          const uint32_t cur = uni(S.cur[l]);
           if (cur >= uni(S.len[l])) {
             if (l == base_l) break;
             // the core prefix's next permutation that puts every data
