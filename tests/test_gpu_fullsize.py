@@ -107,3 +107,40 @@ def test_full_size_sampled_attribution_next4(name, M):
     assert np.array_equal(res.upd_count[idx], ref.seed_count[idx])
     assert np.array_equal(res.upd_hash_sum[idx], ref.seed_hsum[idx])
     assert np.array_equal(res.upd_hash_xor[idx], ref.seed_hxor[idx])
+
+
+@pytest.mark.parametrize("qi", range(4))
+def test_full_size_core_coalescing(qi):
+    """The mid graph's first batch with a query whose core is symmetric
+    (the core workload's queries), in bench.py's launch configuration:
+    coalescing over the core gives the same counts, checksums and
+    per-update attribution as coalescing off, and the sampled attribution
+    equals the oracle's."""
+    w = W.core_symmetric_queries(n_batches=1)
+    q = w.queries[qi]
+    b = w.batches[0]
+    print("[fullsize] core query %d: k=%d m=%d labels=%s" % (qi, q.k, q.m, q.labels.tolist()), flush=True)
+    with Context(device=0, deadline_ms=60000) as ctx:
+        ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
+        ctx.register_query(q.k, q.labels, q.edges)
+        ctx.set_tuning(coalesced_search=1)
+        off = ctx.apply_batch(b.src, b.dst, b.op, hash=True, per_update=True, canonical=True, dry_run=True)
+        ctx.set_tuning(coalesced_search=3)
+        on = ctx.apply_batch(b.src, b.dst, b.op, hash=True, per_update=True, canonical=True)
+    assert on.stats["n_seeds"] < off.stats["n_seeds"]
+    assert np.array_equal(on.counts, off.counts)
+    assert np.array_equal(on.hash_sum, off.hash_sum) and np.array_equal(on.hash_xor, off.hash_xor)
+    assert np.array_equal(on.upd_count, off.upd_count)
+    assert np.array_equal(on.upd_hash_sum, off.upd_hash_sum) and np.array_equal(on.upd_hash_xor, off.upd_hash_xor)
+    assert int(on.upd_count.sum()) == int(on.counts.sum()) > 0
+    nc = int(on.stats["n_canonical"])
+    M = (512, 512, 256, 2048)[qi]  # a sample that holds matches of every query, a few seconds of oracle time
+    ref = O2.run(w.graph, q, b, qid=0, threads=16, sample_mod=M, sample_rem=0, want_tuples=False)
+    assert ref.status == 0 and ref.n_canonical == nc
+    idx = np.arange(0, nc, M)
+    print("[fullsize] core query %d: %d sampled updates, %d oracle matches in %.1f s" % (
+        qi, len(idx), int(ref.seed_count[idx].sum()), ref.seconds), flush=True)
+    assert int(ref.seed_count[idx].sum()) > 0
+    assert np.array_equal(on.upd_count[idx], ref.seed_count[idx])
+    assert np.array_equal(on.upd_hash_sum[idx], ref.seed_hsum[idx])
+    assert np.array_equal(on.upd_hash_xor[idx], ref.seed_hxor[idx])
