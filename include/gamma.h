@@ -456,6 +456,44 @@ gamma_status gamma_validate_graph(uint32_t n, uint64_t nnz, const uint64_t* row_
                                   const uint32_t* col, const uint32_t* labels);
 gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t m,
                                   const uint32_t* qedges);
+
+/* The matching plans of a query as registration builds them (Algorithm 1
+ * runs one per directed query edge; Sec. V-B groups them), for inspection
+ * and tests.  Host only: no context, no GPU.  Without a graph the label
+ * frequencies are unknown, so ties in the matching order are broken by
+ * query degree and vertex id only (registration after load_graph also
+ * prefers rarer labels); the groups do not depend on the order.
+ *
+ * plans[i], i < 2m, describes directed query edge (x, y):
+ *   order[0 .. k-1]  the order query vertices are matched in (x, y first)
+ *   n_perm           whole-query coalescing (coalesced_search >= 2): >= 1 on a
+ *                    group's representative, whose matches f stand for f o pi
+ *                    for each of its n_perm permutations
+ *                    perms[perm_first .. perm_first + n_perm); 0 on a plan a
+ *                    representative stands for
+ *   n_core, n_cperm  core coalescing (coalesced_search = 3): a representative
+ *                    (n_cperm >= 2) matches its n_core core vertices first, and
+ *                    each core match f is continued as f o pi for each
+ *                    pi in perms[cperm_first .. cperm_first + n_cperm);
+ *                    n_cperm = 0: stood for; 1: ordinary (n_core = k)
+ *   omask[u]         bit w set: a representative's core search admits at query
+ *                    vertex u a data vertex that passes the filter of w
+ * perms[16 * j + v] = pi_j(v): the forward map of permutation j (a match g
+ * derived from f is g(v) = f(pi_j(v))).
+ * Errors: the query rules of gamma_validate_query (and edge labels < 256);
+ * EINVAL for null outputs or when 2m > max_plans or the permutations exceed
+ * max_perms (n_plans and n_perms are still set to the sizes needed). */
+typedef struct gamma_plan_info {
+  uint32_t x, y;
+  uint32_t n_perm, perm_first;
+  uint32_t n_core, n_cperm, cperm_first;
+  uint32_t reserved;
+  uint32_t order[16];
+  uint32_t omask[16];
+} gamma_plan_info;
+gamma_status gamma_describe_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges,
+                                  const uint32_t* qelabels, uint32_t max_plans, gamma_plan_info* plans,
+                                  uint32_t* n_plans, uint32_t max_perms, uint32_t* perms, uint32_t* n_perms);
 gamma_status gamma_validate_batch(uint32_t n, uint32_t n_upd, const uint32_t* src,
                                   const uint32_t* dst, const uint8_t* op);
 /* Edge-labelled forms, the rules of gamma_load_graph_el and

@@ -31,7 +31,8 @@ from . import capi
 from .capi import (F_CANONICAL, F_COUNT, F_DRY_RUN, F_HASH, F_PER_UPDATE, F_SEED_ATTR, F_TUPLES,
                    GAMMA_MEM_DEVICE, GAMMA_MEM_HOST)
 
-__all__ = ["Context", "Server", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch"]
+__all__ = ["Context", "Server", "GammaError", "BatchOutput", "validate_graph", "validate_query", "validate_batch",
+           "describe_query"]
 
 
 class GammaError(RuntimeError):
@@ -483,6 +484,42 @@ def validate_graph(row_ptr, col, labels) -> int:
     lb = np.ascontiguousarray(labels, dtype=np.uint32)
     return int(lib.gamma_validate_graph(int(lb.shape[0]), int(cl.shape[0]), rp.ctypes.data_as(ctypes.c_void_p),
                                         cl.ctypes.data_as(ctypes.c_void_p), lb.ctypes.data_as(ctypes.c_void_p)))
+
+
+def describe_query(k, labels, edges, elabels=None):
+    """The matching plans registration builds for a query (host only; see
+    gamma_describe_query): a list of per-directed-edge dicts (x, y, order,
+    n_perm, perm_first, n_core, n_cperm, cperm_first, omask) and the
+    permutations as a [n, 16] array of forward maps.  Raises GammaError on an
+    invalid query."""
+    lib = capi.load_library()
+    ql = np.ascontiguousarray(labels, dtype=np.uint32)
+    qe = np.ascontiguousarray(edges, dtype=np.uint32).reshape(-1)
+    m = qe.shape[0] // 2
+    el = None if elabels is None else np.ascontiguousarray(elabels, dtype=np.uint32)
+    cap_p, cap_g = 2 * m, 64
+    while True:
+        pi = (capi.PlanInfo * max(cap_p, 1))()
+        perms = np.zeros((max(cap_g, 1), 16), np.uint32)
+        n_p, n_g = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        st = lib.gamma_describe_query(int(k), ql.ctypes.data_as(ctypes.c_void_p), int(m),
+                                      qe.ctypes.data_as(ctypes.c_void_p),
+                                      None if el is None else el.ctypes.data_as(ctypes.c_void_p),
+                                      cap_p, pi, ctypes.byref(n_p), cap_g, perms.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(n_g))
+        if st == capi.GAMMA_EINVAL and (n_p.value > cap_p or n_g.value > cap_g):
+            cap_p, cap_g = max(cap_p, n_p.value), max(cap_g, n_g.value)
+            continue
+        if st != 0:
+            raise GammaError(st, "describe_query: invalid query")
+        break
+    plans = []
+    for i in range(n_p.value):
+        r = pi[i]
+        plans.append(dict(x=r.x, y=r.y, n_perm=r.n_perm, perm_first=r.perm_first, n_core=r.n_core,
+                          n_cperm=r.n_cperm, cperm_first=r.cperm_first, order=list(r.order)[:int(k)],
+                          omask=list(r.omask)[:int(k)]))
+    return plans, perms[:n_g.value].copy()
 
 
 def validate_query(k, labels, edges) -> int:

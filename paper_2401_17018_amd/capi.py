@@ -29,8 +29,15 @@ EXPORTS = [
     "gamma_serve_get_batch", "gamma_serve_get_tuples", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
     "gamma_validate_query", "gamma_validate_batch", "gamma_validate_graph_el", "gamma_validate_batch_el", "gamma_status_string", "gamma_last_error",
+    "gamma_describe_query",
     "gamma_version",
 ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("x", "y", "n_perm", "perm_first", "n_core", "n_cperm",
+                                                 "cperm_first", "reserved")] + [
+        ("order", ctypes.c_uint32 * 16), ("omask", ctypes.c_uint32 * 16)]
 
 
 class Options(ctypes.Structure):
@@ -244,6 +251,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_validate_graph.argtypes = [u32, u64, P, P, P]
     lib.gamma_validate_query.restype = st
     lib.gamma_validate_query.argtypes = [u32, P, u32, P]
+    lib.gamma_describe_query.restype = st
+    lib.gamma_describe_query.argtypes = [u32, P, u32, P, P, u32, ctypes.POINTER(PlanInfo), ctypes.POINTER(u32),
+                                         u32, P, ctypes.POINTER(u32)]
     lib.gamma_validate_batch.restype = st
     lib.gamma_validate_batch.argtypes = [u32, u32, P, P, P]
     lib.gamma_validate_graph_el.restype = st

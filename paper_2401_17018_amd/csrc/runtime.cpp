@@ -1435,6 +1435,49 @@ gamma_status gamma_validate_query(uint32_t k, const uint32_t* qlabels, uint32_t 
   return (gamma_status)gm::validate_query(k, qlabels, m, qedges, nullptr);
 }
 
+gamma_status gamma_describe_query(uint32_t k, const uint32_t* qlabels, uint32_t m, const uint32_t* qedges,
+                                  const uint32_t* qelabels, uint32_t max_plans, gamma_plan_info* plans,
+                                  uint32_t* n_plans, uint32_t max_perms, uint32_t* perms, uint32_t* n_perms) {
+  const int st = gm::validate_query(k, qlabels, m, qedges, nullptr);
+  if (st != GAMMA_OK) return (gamma_status)st;
+  for (uint32_t e = 0; qelabels && e < m; ++e)
+    if (qelabels[e] >= GAMMA_MAX_EDGE_LABELS) return GAMMA_EINVAL;
+  if (!n_plans || !n_perms) return GAMMA_EINVAL;
+  gm::HostQuery q;
+  q.k = k;
+  q.labels.assign(qlabels, qlabels + k);
+  for (uint32_t e = 0; e < m; ++e) q.edges.push_back({qedges[2 * e], qedges[2 * e + 1]});
+  q.elabels.assign(m, 0);
+  if (qelabels) q.elabels.assign(qelabels, qelabels + m);
+  gm::plan_query(q, 0, std::vector<uint64_t>());
+  const uint32_t np = (uint32_t)q.plans.size();
+  const uint32_t n0 = (uint32_t)q.perms.size(), nt = n0 + (uint32_t)q.cperms.size();
+  *n_plans = np;
+  *n_perms = nt;
+  if (np > max_plans || nt > max_perms || (np && !plans) || (nt && !perms)) return GAMMA_EINVAL;
+  for (uint32_t i = 0; i < np; ++i) {
+    const GmPlan& p = q.plans[i];
+    gamma_plan_info& o = plans[i];
+    std::memset(&o, 0, sizeof(o));
+    o.x = p.x;
+    o.y = p.y;
+    o.n_perm = p.n_perm;
+    o.perm_first = p.perm_base;
+    o.n_core = p.n_core;
+    o.n_cperm = p.n_cperm;
+    o.cperm_first = n0 + p.cperm_base;
+    for (uint32_t l = 0; l < GM_MAX_K; ++l) {
+      o.order[l] = l < k ? p.order[l] : 0u;
+      o.omask[l] = p.omask[l];
+    }
+  }
+  for (uint32_t j = 0; j < nt; ++j) {
+    const GmPerm& g = j < n0 ? q.perms[j] : q.cperms[j - n0];
+    for (uint32_t v = 0; v < GM_MAX_K; ++v) perms[GM_MAX_K * j + v] = g.fwd[v];
+  }
+  return GAMMA_OK;
+}
+
 gamma_status gamma_validate_batch(uint32_t n, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
                                   const uint8_t* op) {
   if (n_upd > (1u << 20)) return GAMMA_EINVAL;
