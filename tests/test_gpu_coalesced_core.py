@@ -194,3 +194,26 @@ def test_mode_switches_on_one_context():
         b2 = _mixed_batch(g1, 65, 150, 60)
         r2 = ctx.apply_batch(b2.src, b2.dst, b2.op, tuples=True, per_update=True)
     check_against_o2(r2, g1, q, b2)
+
+
+def test_core_orbit_split_into_groups():
+    """K5 with differently labelled leaves on four of its vertices: the
+    core's 20 directed edges form one orbit, searched as two groups (16 and
+    4 permutations)."""
+    k = 9
+    edges = [(a, b) for a in range(5) for b in range(a + 1, 5)] + [(0, 5), (1, 6), (2, 7), (3, 8)]
+    q = W.query_from_edges(k, edges, (0, 0, 0, 0, 0, 1, 2, 3, 4))
+    n = 150
+    lo, hi = W.er_edges(n, 3200, 77)
+    rp, col = W.csr_from_edges(n, lo, hi)
+    rng = np.random.Generator(np.random.PCG64(78))
+    g = W.Graph(n, rp, col, np.where(rng.random(n) < 0.4, 0, rng.integers(1, 5, n)).astype(np.uint32))
+    b = _mixed_batch(g, 79, 200, 80)
+    on = _run(g, [q], b, 3)
+    off = _run(g, [q], b, 1)
+    _same(on, off)
+    for sign in (0, 1):
+        assert on.tuple_set(0, sign, k) == off.tuple_set(0, sign, k)
+    check_against_o2(on, g, q, b, check_tuples=not on.truncated)
+    assert on.count(0, 1) + on.count(0, 0) > 0
+    assert on.stats["n_seeds"] < off.stats["n_seeds"]

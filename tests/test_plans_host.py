@@ -188,6 +188,20 @@ def test_random_queries():
     assert n_core_groups > 0 and n_k0_groups > 0 and total > 0
 
 
+def test_core_orbit_larger_than_a_group():
+    """K5 with differently labelled leaves on four of its vertices: no
+    automorphism of the query, the core's 20 directed edges form one orbit,
+    split into groups of at most 16 permutations."""
+    k = 9
+    edges = [(a, b) for a in range(5) for b in range(a + 1, 5)] + [(0, 5), (1, 6), (2, 7), (3, 8)]
+    labels = (0, 0, 0, 0, 0, 1, 2, 3, 4)
+    plans, perms = _check_structure(k, edges, labels, None)
+    reps = [p for p in plans if p["n_cperm"] >= 2]
+    assert sorted(p["n_cperm"] for p in reps) == [4, 16]
+    assert sum(p["n_cperm"] == 0 for p in plans) == 20 - len(reps)
+    assert all(p["n_cperm"] == 1 for p in plans if p["x"] >= 5 or p["y"] >= 5)
+
+
 def test_edge_labels_break_core_symmetry():
     k, edges, labels = 4, [(0, 1), (1, 2), (2, 0), (1, 3)], (0, 1, 1, 2)
     sym, _ = _check_structure(k, edges, labels, [1, 0, 1, 1])
