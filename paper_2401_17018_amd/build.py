@@ -7,6 +7,7 @@ disabled for all device code.
 from __future__ import annotations
 
 import concurrent.futures
+import json
 import os
 import subprocess
 import sys
@@ -26,15 +27,49 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+# kernels whose register use is recorded at build time (resources.json):
+# the search kernel must keep three waves per SIMD without spilling
+WATCH = {"k_dfs.hip"}
+
+
+def _resources(stderr: str) -> dict:
+    """Per-kernel figures from hipcc's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    keys = {"VGPRs": "vgprs", "AGPRs": "agprs", "ScratchSize [bytes/lane]": "scratch_bytes",
+            "Occupancy [waves/SIMD]": "occupancy", "VGPRs Spill": "vgpr_spill", "SGPRs Spill": "sgpr_spill",
+            "LDS Size [bytes/block]": "lds_bytes"}
+    for line in stderr.splitlines():
+        if "remark:" not in line:
+            continue
+        body = line.split("remark:", 1)[1].split("[-Rpass")[0].strip()
+        if body.startswith("Function Name:"):
+            cur = body.split(":", 1)[1].strip()
+            out[cur] = {}
+        elif cur and ":" in body:
+            name, val = body.rsplit(":", 1)
+            if name.strip() in keys:
+                try:
+                    out[cur][keys[name.strip()]] = int(val.strip())
+                except ValueError:
+                    pass
+    return out
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     cmd = ["hipcc"] + COMMON + DEVICE
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
+    watch = os.path.basename(src) in WATCH
+    if watch:
+        cmd += ["-Rpass-analysis=kernel-resource-usage"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))
+    if watch:
+        with open(os.path.join(BUILD_DIR, os.path.basename(src) + ".resources.json"), "w") as f:
+            json.dump(_resources(r.stderr), f, indent=1)
     return obj
 
 
