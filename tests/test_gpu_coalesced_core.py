@@ -217,3 +217,53 @@ def test_core_orbit_split_into_groups():
     check_against_o2(on, g, q, b, check_tuples=not on.truncated)
     assert on.count(0, 1) + on.count(0, 0) > 0
     assert on.stats["n_seeds"] < off.stats["n_seeds"]
+
+
+def test_served_stream_with_core_coalescing():
+    """A served stream whose queries are core-coalesced: every device batch
+    the server forms reports what coalescing off reports for the same
+    batch on the same graph state, and the oracle agrees."""
+    from paper_2401_17018_amd import Server
+    from test_gpu_serve import _request_stream
+    g = _er(400, 3600, 61, 4)
+    qs = [_query("triangle_leaf"), _query("cycle4_leaves")]
+    reqs = _request_stream(g, 5, 24, 60)
+    with make_ctx(cap=0, deadline_ms=30000) as ctx:
+        ctx.load_graph(g.row_ptr, g.col, g.labels)
+        for q in qs:
+            ctx.register_query(q.k, q.labels, q.edges)
+        ctx.set_tuning(coalesced_search=3)
+        with Server(ctx, max_batch_updates=150) as srv:
+            for r in reqs:
+                srv.submit(*r)
+            srv.drain()
+            n_bat = srv.counts()[2]
+            batches = [srv.batch(i) for i in range(n_bat)]
+    assert sum(b["n_requests"] for b in batches) == len(reqs)
+    total = 0
+    with make_ctx(cap=0, deadline_ms=30000) as plain:
+        plain.load_graph(g.row_ptr, g.col, g.labels)
+        for q in qs:
+            plain.register_query(q.k, q.labels, q.edges)
+        plain.set_tuning(coalesced_search=1)
+        for b in batches:
+            rs = reqs[b["first_ticket"]:b["first_ticket"] + b["n_requests"]]
+            merged = W.Batch(np.concatenate([r[0] for r in rs]), np.concatenate([r[1] for r in rs]),
+                             np.concatenate([r[2] for r in rs]))
+            rp, col, lab = plain.export_graph()
+            before = W.Graph(len(lab), rp, col, lab)
+            res = plain.apply_batch(merged.src, merged.dst, merged.op, hash=True)
+            assert np.array_equal(res.counts, b["counts"])
+            assert np.array_equal(res.hash_sum, b["hash_sum"]) and np.array_equal(res.hash_xor, b["hash_xor"])
+            for qid, q in enumerate(qs):
+                ref = _o2(before, q, merged, qid)
+                assert [int(res.counts[qid, 0]), int(res.counts[qid, 1])] == [ref.count[0], ref.count[1]]
+            total += int(res.counts.sum())
+    assert total > 0
+
+
+def _o2(g, q, b, qid):
+    from oracle import plain as O2
+    r = O2.run(g, q, b, qid=qid, threads=4, want_tuples=False)
+    assert r.status == 0
+    return r
