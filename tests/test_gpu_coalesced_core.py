@@ -267,3 +267,27 @@ def _o2(g, q, b, qid):
     r = O2.run(g, q, b, qid=qid, threads=4, want_tuples=False)
     assert r.status == 0
     return r
+
+
+def test_vertex_deletions_with_core_coalescing():
+    """Vertex deletions expanded on the device, under coalescing over the
+    core: equal to coalescing off and to the oracle on the merged batch."""
+    from test_gpu_vertices import _vertex_case
+    g = _er(400, 3600, 71, 4)
+    qs = [_query("triangle_leaf"), _query("cycle4_leaves")]
+    b, vdel, merged = _vertex_case(g, 73, 150, 50, 6)
+    outs = []
+    for mode in (3, 1):
+        with make_ctx(cap=1 << 22, deadline_ms=30000) as ctx:
+            ctx.load_graph(g.row_ptr, g.col, g.labels)
+            for q in qs:
+                ctx.register_query(q.k, q.labels, q.edges)
+            ctx.set_tuning(coalesced_search=mode)
+            outs.append(ctx.apply_batch(b.src, b.dst, b.op, delete_vertices=vdel, tuples=True, per_update=True))
+    _same(outs[0], outs[1])
+    for qid, q in enumerate(qs):
+        for sign in (0, 1):
+            assert outs[0].tuple_set(qid, sign, q.k) == outs[1].tuple_set(qid, sign, q.k)
+        ref = _o2(g, q, merged, qid)
+        assert [outs[0].count(qid, 0), outs[0].count(qid, 1)] == [ref.count[0], ref.count[1]]
+    assert int(outs[0].counts.sum()) > 0
