@@ -62,6 +62,13 @@
  *
  * A `mutant` argument plants a known mistake (tests use it to show that the
  * pins catch each one); 0 is the correct oracle.
+ *
+ * Seed cap (a sampling control for very large result sets, not part of the
+ * method): with seed_cap > 0 a seed whose matches exceed seed_cap is given
+ * up as soon as its (seed_cap + 1)-th match is found.  It is flagged in
+ * seed_incomplete, its tuples are dropped, and it contributes nothing to
+ * the per-pass totals; its seed_count holds seed_cap + 1, a lower bound of
+ * its true count.  Every seed that is not flagged is exact.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -98,6 +105,9 @@ typedef struct {
   double seconds;
   int32_t threads_used;
   uint32_t* canon_e; /* n_canonical: edge label of each canonical update */
+  uint8_t* seed_incomplete; /* n_canonical: 1 = given up at the seed cap */
+  uint64_t n_incomplete;
+  double seconds_prep; /* keys, canonical batch and G' (the oracle's own graph update) */
 } o2_result;
 
 /* ---------------------------------------------------------------- hashing */
@@ -341,28 +351,33 @@ typedef struct {
   uint32_t qid;
   int mutant, want_tuples;
   uint32_t sample_mod, sample_rem;
+  uint64_t seed_cap; /* 0: none */
   /* work distribution */
   uint32_t next; /* atomic counter over canonical updates */
   /* per seed totals */
   uint64_t *seed_count, *seed_hsum, *seed_hxor;
+  uint8_t* seed_incomplete;
 } shared_t;
 
 typedef struct {
   shared_t* sh;
   tbuf_t out;
   uint64_t count[2], hsum[2], hxor[2];
+  int give_up; /* the current seed passed the seed cap */
 } worker_t;
 
 static void emit(worker_t* w, int sign, uint32_t ord, const uint32_t* f) {
   const shared_t* sh = w->sh;
   uint32_t k = sh->q->k;
   uint64_t h = tuple_hash(sh->qid, sign, f, k);
-  w->count[sign]++;
-  w->hsum[sign] += h;
-  w->hxor[sign] ^= h;
+  (void)sign;
   sh->seed_count[ord]++;
   sh->seed_hsum[ord] += h;
   sh->seed_hxor[ord] ^= h;
+  if (sh->seed_cap && sh->seed_count[ord] > sh->seed_cap) {
+    w->give_up = 1;
+    return;
+  }
   if (!sh->want_tuples) return;
   if (w->out.n == w->out.cap) {
     w->out.cap = w->out.cap ? w->out.cap * 2 : 1024;
@@ -404,7 +419,7 @@ static void extend(worker_t* w, int sign, uint32_t ord, const uint32_t* pi, uint
   /* nb >= 1: the BFS order keeps every prefix connected */
   uint32_t a0 = f[back[0]];
   const int any_el = sh->mutant == MUT_NO_EDGE_LABEL_CHECK;
-  for (uint64_t t = H->rp[a0]; t < H->rp[a0 + 1]; ++t) {
+  for (uint64_t t = H->rp[a0]; t < H->rp[a0 + 1] && !w->give_up; ++t) {
     uint32_t c = H->col[t] / sh->L, ce = H->col[t] % sh->L;
     if (!any_el && ce != q->qel[u][back[0]]) continue;
     if (sh->mutant != MUT_NO_LABEL_CHECK && sh->labels[c] != q->qlab[u]) continue;
@@ -438,7 +453,9 @@ static void* worker_main(void* arg) {
     if (sh->sample_mod > 1 && i % sh->sample_mod != sh->sample_rem) continue;
     int sign = sh->c->sign[i];
     uint32_t lo = sh->c->lo[i], hi = sh->c->hi[i], el = sh->c->e[i];
-    for (uint32_t d = 0; d < q->n_dqe; ++d) {
+    const uint64_t n_out0 = w->out.n;
+    w->give_up = 0;
+    for (uint32_t d = 0; d < q->n_dqe && !w->give_up; ++d) {
       uint32_t x = q->dx[d], y = q->dy[d];
       if (sh->labels[lo] != q->qlab[x] || sh->labels[hi] != q->qlab[y]) continue;
       if (sh->mutant != MUT_NO_EDGE_LABEL_CHECK && q->qel[x][y] != el) continue;
@@ -446,6 +463,15 @@ static void* worker_main(void* arg) {
       f[y] = hi;
       extend(w, sign, i, q->order[d], 2, f);
     }
+    if (w->give_up) {
+      /* given up at the seed cap: drop what it found */
+      sh->seed_incomplete[i] = 1;
+      w->out.n = n_out0;
+      continue;
+    }
+    w->count[sign] += sh->seed_count[i];
+    w->hsum[sign] += sh->seed_hsum[i];
+    w->hxor[sign] ^= sh->seed_hxor[i];
   }
   return NULL;
 }
@@ -501,8 +527,8 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
               uint32_t L, const uint32_t* elab, uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m,
               const uint32_t* qedges, const uint32_t* qelab, uint32_t n_upd, const uint32_t* src,
               const uint32_t* dst, const uint8_t* op, const uint32_t* uelab, int threads, uint32_t sample_mod,
-              uint32_t sample_rem, int want_tuples, int mutant, o2_result* res) {
-  struct timespec t0, t1;
+              uint32_t sample_rem, uint64_t seed_cap, int want_tuples, int mutant, o2_result* res) {
+  struct timespec t0, t1, tp;
   clock_gettime(CLOCK_MONOTONIC, &t0);
   memset(res, 0, sizeof(*res));
   if (k < 2 || k > 16 || m == 0 || m > 120 || L == 0) return -3;
@@ -559,6 +585,8 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   uint32_t* col2;
   build_updated(&G, L, &c, &rp2, &col2);
   csr_t G2 = {n, rp2, col2};
+  clock_gettime(CLOCK_MONOTONIC, &tp);
+  res->seconds_prep = (double)(tp.tv_sec - t0.tv_sec) + 1e-9 * (double)(tp.tv_nsec - t0.tv_nsec);
 
   shared_t sh;
   memset(&sh, 0, sizeof(sh));
@@ -573,10 +601,12 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   sh.want_tuples = want_tuples;
   sh.sample_mod = sample_mod;
   sh.sample_rem = sample_rem;
+  sh.seed_cap = seed_cap;
   uint32_t nc = c.n ? c.n : 1;
   sh.seed_count = (uint64_t*)calloc(nc, 8);
   sh.seed_hsum = (uint64_t*)calloc(nc, 8);
   sh.seed_hxor = (uint64_t*)calloc(nc, 8);
+  sh.seed_incomplete = (uint8_t*)calloc(nc, 1);
 
   if (threads < 1) threads = 1;
   worker_t* ws = (worker_t*)calloc((size_t)threads, sizeof(worker_t));
@@ -623,6 +653,8 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   res->seed_count = sh.seed_count;
   res->seed_hsum = sh.seed_hsum;
   res->seed_hxor = sh.seed_hxor;
+  res->seed_incomplete = sh.seed_incomplete;
+  for (uint32_t i = 0; i < c.n; ++i) res->n_incomplete += sh.seed_incomplete[i];
   res->threads_used = threads;
   free(ws);
   free(th);
@@ -642,7 +674,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
            int threads, uint32_t sample_mod, uint32_t sample_rem, int want_tuples, int mutant,
            o2_result* res) {
   return o2_run_el(n, row_ptr, col, labels, 1, NULL, qid, k, qlabels, m, qedges, NULL, n_upd, src, dst, op, NULL,
-                   threads, sample_mod, sample_rem, want_tuples, mutant, res);
+                   threads, sample_mod, sample_rem, 0, want_tuples, mutant, res);
 }
 
 /* G' as a CSR for callers that chain batches (row_ptr n+1; col and, when
@@ -702,6 +734,7 @@ void o2_free(o2_result* r) {
   free(r->seed_count);
   free(r->seed_hsum);
   free(r->seed_hxor);
+  free(r->seed_incomplete);
   memset(r, 0, sizeof(*r));
 }
 

@@ -50,6 +50,9 @@ class _Res(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("threads_used", ctypes.c_int32),
         ("canon_e", ctypes.POINTER(ctypes.c_uint32)),
+        ("seed_incomplete", ctypes.POINTER(ctypes.c_uint8)),
+        ("n_incomplete", ctypes.c_uint64),
+        ("seconds_prep", ctypes.c_double),
     ]
 
 
@@ -72,7 +75,7 @@ def _L():
         u32 = ctypes.c_uint32
         lib.o2_run_el.restype = ctypes.c_int
         lib.o2_run_el.argtypes = [u32, P, P, P, u32, P, u32, u32, P, u32, P, P, u32, P, P, P, P, ctypes.c_int,
-                                  u32, u32, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Res)]
+                                  u32, u32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Res)]
         lib.o2_free.restype = None
         lib.o2_free.argtypes = [ctypes.POINTER(_Res)]
         lib.o2_updated_graph_el.restype = ctypes.c_int
@@ -121,6 +124,13 @@ class O2Result:
     seed_hxor: np.ndarray
     seconds: float
     threads: int
+    seed_incomplete: Optional[np.ndarray] = None  # [n_canonical] uint8: 1 = given up at the seed cap
+    n_incomplete: int = 0
+    seconds_prep: float = 0.0  # the oracle's own graph update (keys, canonical batch, G')
+
+    @property
+    def seconds_search(self) -> float:
+        return self.seconds - self.seconds_prep
 
     def tuple_set(self, sign: int) -> set:
         if self.tuples is None:
@@ -145,9 +155,11 @@ def _p(a):
 
 
 def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1, sample_rem: int = 0,
-        want_tuples: bool = True, mutant: int = MUT_NONE) -> O2Result:
+        want_tuples: bool = True, mutant: int = MUT_NONE, seed_cap: int = 0) -> O2Result:
     """Run O2 on (graph, query, batch); graph/query/batch are workloads types
-    (edge labels when they carry them)."""
+    (edge labels when they carry them).  seed_cap > 0 gives up every seed
+    with more than seed_cap matches (flagged in seed_incomplete, left out of
+    the totals and tuples); every other seed's figures are exact."""
     L = _L()
     n_el, gel, qel, bel = _labels_of(graph, query, batch)
     rp = np.ascontiguousarray(graph.row_ptr, dtype=np.uint64)
@@ -168,8 +180,8 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
     r = _Res()
     rc = L.o2_run_el(graph.n, _ptr(rp), _ptr(col), _ptr(lab), n_el, _p(gel), qid, query.k, _ptr(ql), query.m,
                      _ptr(qe), _p(qel), n_upd, _ptr(src), _ptr(dst), _ptr(op), _p(bel) if n_upd else None,
-                     int(threads), int(sample_mod), int(sample_rem), 1 if want_tuples else 0, int(mutant),
-                     ctypes.byref(r))
+                     int(threads), int(sample_mod), int(sample_rem), int(seed_cap), 1 if want_tuples else 0,
+                     int(mutant), ctypes.byref(r))
     if rc == -3:
         raise ValueError("query rejected by the oracle (k, edges or connectivity)")
     k = query.k
@@ -188,7 +200,9 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
         seed_count=_arr(r.seed_count, r.n_canonical, np.uint64),
         seed_hsum=_arr(r.seed_hsum, r.n_canonical, np.uint64),
         seed_hxor=_arr(r.seed_hxor, r.n_canonical, np.uint64),
-        seconds=float(r.seconds), threads=int(r.threads_used))
+        seconds=float(r.seconds), threads=int(r.threads_used),
+        seed_incomplete=_arr(r.seed_incomplete, r.n_canonical, np.uint8), n_incomplete=int(r.n_incomplete),
+        seconds_prep=float(r.seconds_prep))
     if rc == 0:
         L.o2_free(ctypes.byref(r))
     return out

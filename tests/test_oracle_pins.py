@@ -103,6 +103,36 @@ def test_o2_threads_agree():
     assert r1.hsum == r8.hsum and r1.hxor == r8.hxor
 
 
+@pytest.mark.parametrize("cap", [2, 8, 30, 100])
+def test_seed_cap_keeps_completed_seeds_exact(cap):
+    """The seed cap (a sampling control for huge results) gives up exactly the
+    seeds whose true count exceeds it; every other seed keeps its exact
+    count, checksums and tuples, and the totals are those seeds' sums."""
+    g, q, b = W.random_small(11, n=40, p=0.3, n_labels=2, k=4, extra_q_edges=1, n_ins=30, n_del=20)
+    full = _check_o2_equals_o1(g, q, b)
+    for threads in (1, 4):
+        r = O2.run(g, q, b, threads=threads, seed_cap=cap)
+        assert r.status == 0 and r.n_canonical == full.n_canonical
+        over = full.seed_count > cap
+        assert over.any() and (~over & (full.seed_count > 0)).any()  # both kinds occur
+        assert np.array_equal(r.seed_incomplete.astype(bool), over)
+        assert r.n_incomplete == int(over.sum())
+        done = ~over
+        assert np.array_equal(r.seed_count[done], full.seed_count[done])
+        assert np.array_equal(r.seed_hsum[done], full.seed_hsum[done])
+        assert np.array_equal(r.seed_hxor[done], full.seed_hxor[done])
+        assert np.all(r.seed_count[over] == cap + 1)  # a lower bound of the true count
+        for sign in (0, 1):
+            sel = done & (full.canon_sign == sign)
+            assert r.count[sign] == int(full.seed_count[sel].sum())
+            keep = np.isin(full.ord, np.nonzero(sel)[0]) & (full.sign == sign)
+            assert r.tuple_set(sign) == {tuple(int(x) for x in t) for t in full.tuples[keep]}
+    # no cap (0) and a cap above every seed change nothing
+    r = O2.run(g, q, b, seed_cap=int(full.seed_count.max()))
+    assert r.n_incomplete == 0 and r.count == full.count and r.hsum == full.hsum and r.hxor == full.hxor
+    assert 0 < r.seconds_prep <= r.seconds
+
+
 # ---------------------------------------------------------------- closed forms
 
 
