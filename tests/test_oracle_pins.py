@@ -203,6 +203,38 @@ def test_triangle_count_textbook():
     assert CF.triangles(O1.adjacency(4, c4)) == 0
 
 
+@pytest.mark.parametrize("name,k,edges,labels,order", [
+    # group orders known in closed form: S_3, S_4, S_3 on the leaves, the
+    # dihedral groups D_4 and D_5, S_2 x S_3 on the two sides of K_{2,3},
+    # the reflection of a path
+    ("triangle", 3, [(0, 1), (1, 2), (0, 2)], (0, 0, 0), 6),
+    ("K4", 4, [(a, b) for a in range(4) for b in range(a + 1, 4)], (0, 0, 0, 0), 24),
+    ("star3", 4, [(0, 1), (0, 2), (0, 3)], (0, 1, 1, 1), 6),
+    ("C4", 4, [(0, 1), (1, 2), (2, 3), (0, 3)], (0, 0, 0, 0), 8),
+    ("C5", 5, [(0, 1), (1, 2), (2, 3), (3, 4), (0, 4)], (0,) * 5, 10),
+    ("K23", 5, [(a, b) for a in (0, 1) for b in (2, 3, 4)], (0,) * 5, 12),
+    ("P3", 3, [(0, 1), (1, 2)], (0, 0, 0), 2),
+    # labels cut the group down: a 4-cycle labelled 0,0,1,1 keeps only the
+    # reflection through the midpoints of its two one-label edges; a path
+    # with different end labels keeps only the identity; a K4 with labels
+    # 0,0,0,1 keeps S_3 on the three equal vertices
+    ("C4_labelled", 4, [(0, 1), (1, 2), (2, 3), (0, 3)], (0, 0, 1, 1), 2),
+    ("P3_ends", 3, [(0, 1), (1, 2)], (0, 1, 2), 1),
+    ("K4_one_odd", 4, [(a, b) for a in range(4) for b in range(a + 1, 4)], (0, 0, 0, 1), 6),
+])
+def test_automorphism_counts_exact(name, k, edges, labels, order):
+    """|Aut_L(Q)| against group orders known in closed form (the closure
+    invariant and coalesced search rely on this enumeration)."""
+    aut = CF.automorphisms(k, labels, edges)
+    assert len(aut) == order, name
+    assert len(set(aut)) == order and tuple(range(k)) in aut
+    # a group: closed under composition
+    s = set(aut)
+    for p in aut:
+        for r in aut:
+            assert tuple(p[r[i]] for i in range(k)) in s
+
+
 # ---------------------------------------------------------------- invariants
 
 
