@@ -8,7 +8,15 @@ Prints one JSON line:
   metric    incremental matches/s and updates/s on 1 MI355X; p50/p99 batch latency
   value     incremental matches per second over the timed steps (+ and - results)
   roofline  the search kernel (the dominant kernel): algorithmic bytes per
-            launch / its average duration (HIP events on the library stream)
+            launch / its average duration (HIP events on the library stream).
+            Algorithmic bytes follow a fixed model of what the method reads:
+            per candidate examined a 4-byte id, a 1-byte label and one bit of
+            the candidate table; per lower-bound search in a list of length n,
+            ceil(log2 n) + 1 reads of 4 bytes; 16 bytes per batch-hash probe
+            of a flagged entry; 4 bytes per tuple element written.  Where a
+            rocprofv3 counter summary of the same kernel source exists,
+            `traffic` is its HBM bytes per launch and `hbm_frac` that traffic
+            over the launch time, against the same peak.
   cpu_baseline  the CPU oracle (O2) on a bounded sample of the same batch
 
 With --workload batched (64 standing queries on the mid graph) the search
@@ -16,7 +24,8 @@ is first tuned on a calibration batch (dry runs), then every timed batch is
 searched twice: with one search launch per query (a dry run) and with all
 queries in one launch (applied); both rates are reported.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload mid|large|tiny|batched]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|mid|tiny|batched|...]
+(default: the large workload, R-MAT scale 24 with both of its queries)
 """
 from __future__ import annotations
 
@@ -57,6 +66,27 @@ def counter_traffic(workload: str):
     if rec.get("source_sha16") != kernel_source_hash():
         return None
     return float(rec["traffic_bytes"])
+
+
+def roofline(achieved, avg_bytes, avg_dfs_s, traffic):
+    """The search kernel's roofline record: algorithmic bytes (the model in
+    the module docstring) per launch over the average launch time, and the
+    counter traffic beside it when a summary for this kernel source exists."""
+    rec = {
+        "bound": "hbm",
+        "kernel": "k_dfs",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "bytes_alg_per_launch": avg_bytes,
+        "avg_launch_ms": avg_dfs_s * 1e3,
+    }
+    if traffic is not None and avg_dfs_s > 0:
+        rec["traffic_GBps"] = traffic / avg_dfs_s / 1e9
+        rec["hbm_frac"] = rec["traffic_GBps"] / HBM_PEAK_GBS
+    return rec
 
 
 def percentile(xs, p):
@@ -148,38 +178,19 @@ def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     }
 
 
-def attempt_unsolved(w, q, b, deadline_s):
-    """One batch of a query alone under a deadline: what it found before the
-    deadline (the batch is rolled back)."""
-    from paper_2401_17018_amd import Context, GammaError
-    with Context(device=0, deadline_ms=deadline_s * 1000) as ctx:
-        ctx.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
-        ctx.register_query(q.k, q.labels, q.edges)
-        t1 = time.perf_counter()
-        try:
-            r = ctx.apply_batch(b.src, b.dst, b.op, hash=True)
-            return {"query": {"k": q.k, "edges": q.m, "kind": q.kind}, "solved": True,
-                    "seconds": time.perf_counter() - t1, "matches": int(r.counts.sum())}
-        except GammaError as e:
-            st = getattr(e, "stats", {})
-            return {"query": {"k": q.k, "edges": q.m, "kind": q.kind}, "solved": False, "deadline_s": deadline_s,
-                    "matches_before_deadline": int(sum(sum(c) for c in getattr(e, "counts", []))),
-                    "seeds_started": int(st.get("seeds_started", 0)), "seeds": int(st.get("n_seeds", 0))}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid",
+    ap.add_argument("--workload", default="large",
                     choices=["tiny", "mid", "large", "batched", "served", "symmetric", "core", "elabel",
                              "vertices"])
     ap.add_argument("--vertex-deletions", type=int, default=64, help="vertices deleted per batch (vertices workload)")
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="offered loads (x capacity) for the served workload")
     ap.add_argument("--tune-points", type=int, default=24, help="autotuner evaluations (batched workload)")
-    ap.add_argument("--unsolved-deadline-s", type=int, default=30,
-                    help="deadline of the one attempt at a query left out of the timed steps (0: skip it)")
+    ap.add_argument("--deadline-s", type=int, default=120,
+                    help="per-batch search deadline; a batch past it ends the run with an error")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reps", type=int, default=5,
                     help="after the stream: dry runs of the next batch from the same graph state (0: none)")
@@ -250,14 +261,9 @@ def main():
     print("[bench] workload %s generated in %.1fs: n=%d m=%d queries=%s batches=%d" % (
         w.name, gen_s, w.graph.n, w.graph.m, [q.k for q in w.queries], len(w.batches)), file=sys.stderr, flush=True)
 
-    # the large workload's sparse query does not finish a batch in minutes
-    # (unsolved in the paper's sense): it gets one deadline-bounded attempt
-    # after the timed steps instead of a place in them
-    left_out = [args.workload == "large" and q.kind == "sparse" for q in w.queries]
-    timed_queries = [q for q, lo in zip(w.queries, left_out) if not lo]
-    unsolved_queries = [q for q, lo in zip(w.queries, left_out) if lo]
+    timed_queries = list(w.queries)
     ctx = Context(device=0, steal=not args.no_steal, waves_per_cu=args.waves_per_cu,
-                  tuple_capacity=(1 << 25) if args.tuples else 0)
+                  tuple_capacity=(1 << 25) if args.tuples else 0, deadline_ms=args.deadline_s * 1000)
     if args.group_seeds:
         ctx.set_tuning(group_seeds=2)
     t0 = time.time()
@@ -318,12 +324,11 @@ def main():
         print("[bench] same batch x%d: min %.1f median %.1f max %.1f ms" % (
             args.reps, tot[0], tot[len(tot) // 2], tot[-1]), file=sys.stderr, flush=True)
     ctx.close()
-    unsolved = ([attempt_unsolved(w, q, batches[0], args.unsolved_deadline_s) for q in unsolved_queries]
-                if args.unsolved_deadline_s > 0 else [])
 
     avg_dfs_s = sum(dfs_ms) / len(dfs_ms) / 1e3
     avg_bytes = sum(dfs_bytes) / len(dfs_bytes)
     achieved = avg_bytes / avg_dfs_s / 1e9 if avg_dfs_s > 0 else 0.0
+    traffic = counter_traffic(w.name)
     phases = {k: round(sum(s[k] for s in stats) / len(stats), 3)
               for k in ("ms_canon", "ms_merge", "ms_filter", "ms_seed", "ms_dfs", "ms_commit", "ms_total")}
     out = {
@@ -346,7 +351,11 @@ def main():
             "workload": w.name,
             "vertices": w.graph.n,
             "edges": w.graph.m,
-            "queries": [{"k": q.k, "edges": q.m, "kind": q.kind} for q in timed_queries],
+            "queries": [{"k": q.k, "edges": q.m, "kind": q.kind, "labels": q.labels.tolist()}
+                        for q in timed_queries],
+            **({"query_walks": "random walks on G u I over vertices of label rank >= 20 (sparse query) and "
+                               ">= 12 (dense query), starting at an inserted edge"} if args.workload == "large"
+               else {}),
             "batch_updates": len(batches[args.warmup]),
             "mode": ("tuples written to HBM and copied to host memory, plus counts + hash" if args.tuples
                      else "counts + hash (every match enumerated)"),
@@ -357,18 +366,7 @@ def main():
         },
         "phases_ms": phases,
         **({"same_batch": same_batch} if same_batch else {}),
-        **({"unsolved": unsolved} if unsolved else {}),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_dfs",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic(w.name),
-            "bytes_alg_per_launch": avg_bytes,
-            "avg_launch_ms": avg_dfs_s * 1e3,
-        },
+        "roofline": roofline(achieved, avg_bytes, avg_dfs_s, traffic),
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
@@ -468,11 +466,7 @@ def run_batched(args):
             "speedup_of_one_launch": sp / s1,
         },
         "autotune": {k: tune[k] for k in ("best_ms", "base_ms", "max_points", "reps")},
-        "roofline": {
-            "bound": "hbm", "kernel": "k_dfs", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(w.name), "bytes_alg_per_launch": avg_bytes,
-            "avg_launch_ms": avg_dfs_s * 1e3,
-        },
+        "roofline": roofline(achieved, avg_bytes, avg_dfs_s, counter_traffic(w.name)),
     }
     print(json.dumps(out))
 

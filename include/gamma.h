@@ -141,7 +141,11 @@ typedef struct gamma_batch_stats {
   uint64_t dfs_nodes;      /* partial matches extended (levels >= 2) */
   uint64_t steals;         /* successful work steals */
   uint64_t cand_scanned;   /* candidate-list entries examined */
-  uint64_t bytes_alg_dfs;  /* algorithmic bytes read by the search kernel */
+  uint64_t bytes_alg_dfs;  /* algorithmic bytes of the search by a fixed model (Sec. IV-C's
+                              GenCandidates): per candidate examined 4 B id + 1 B label +
+                              1 bit of the candidate table; per lower-bound search in a list
+                              of length n, (ceil(log2 n) + 1) x 4 B; 16 B per batch-hash
+                              probe; 4 B per tuple element written */
   uint64_t bytes_alg_update; /* algorithmic bytes of the graph update (merge + commit) */
   float ms_canon, ms_merge, ms_filter, ms_seed, ms_dfs, ms_commit, ms_total;
   float reserved1;
@@ -182,6 +186,11 @@ typedef struct gamma_batch_result {
   uint64_t* upd_hash_sum;
   uint64_t* upd_hash_xor;
   gamma_batch_stats stats;
+  /* with GAMMA_F_PER_UPDATE, per ord: 1 = some search work seeded from this
+   * update did not finish, so its figures above are partial.  All 0 after a
+   * completed search; after a deadline (GAMMA_ETIMEDOUT) the updates marked
+   * 0 still carry exact figures. */
+  uint8_t* upd_open;
 } gamma_batch_result;
 
 typedef struct gamma_ctx gamma_ctx;

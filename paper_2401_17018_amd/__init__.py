@@ -82,6 +82,7 @@ class BatchOutput:
     upd_count: Optional[np.ndarray] = None
     upd_hash_sum: Optional[np.ndarray] = None
     upd_hash_xor: Optional[np.ndarray] = None
+    upd_open: Optional[np.ndarray] = None  # [n_canonical] uint8: 1 = search work of that update did not finish
     stats: dict = field(default_factory=dict)
 
     @property
@@ -192,7 +193,6 @@ class Context:
                     per_update: bool = False, canonical: bool = False, dry_run: bool = False,
                     delete_vertices=None, elab=None) -> BatchOutput:
         """Apply one batch (dry_run: search it without committing it).
-
         delete_vertices: ids whose incident edges are all deleted in the same
         batch, appended after the explicit updates (gamma_apply_batch_vertices).
         elab: the edge label of each update (edge-labelled graphs)."""
@@ -232,6 +232,13 @@ class Context:
             err.stats = {name: getattr(res.stats, name) for name, _ in capi.BatchStats._fields_
                          if not name.startswith("reserved")}
             err.counts = [[res.queries[i].count[sg] for sg in range(2)] for i in range(int(res.n_queries))]
+            nc = int(res.n_canonical)
+            if per_update and nc and res.upd_count:
+                # partial attribution: updates whose search finished (upd_open 0) are exact
+                err.upd_count = np.ctypeslib.as_array(res.upd_count, (nc,)).copy()
+                err.upd_hash_sum = np.ctypeslib.as_array(res.upd_hash_sum, (nc,)).copy()
+                err.upd_hash_xor = np.ctypeslib.as_array(res.upd_hash_xor, (nc,)).copy()
+                err.upd_open = np.ctypeslib.as_array(res.upd_open, (nc,)).copy()
             raise err
         _check(self._lib, self._ptr, st, "apply_batch")
         nq = int(res.n_queries)
@@ -260,8 +267,10 @@ class Context:
                 out.upd_count = np.ctypeslib.as_array(res.upd_count, (nc,)).copy()
                 out.upd_hash_sum = np.ctypeslib.as_array(res.upd_hash_sum, (nc,)).copy()
                 out.upd_hash_xor = np.ctypeslib.as_array(res.upd_hash_xor, (nc,)).copy()
+                out.upd_open = np.ctypeslib.as_array(res.upd_open, (nc,)).copy()
             else:
                 out.upd_count = out.upd_hash_sum = out.upd_hash_xor = np.zeros(0, np.uint64)
+                out.upd_open = np.zeros(0, np.uint8)
         if tuples:
             nt, w = int(res.n_tuples), int(res.tuple_width)
             t = np.zeros((nt, w), dtype=np.uint32)

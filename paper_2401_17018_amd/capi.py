@@ -174,6 +174,7 @@ class BatchResult(ctypes.Structure):
         ("upd_hash_sum", ctypes.POINTER(ctypes.c_uint64)),
         ("upd_hash_xor", ctypes.POINTER(ctypes.c_uint64)),
         ("stats", BatchStats),
+        ("upd_open", ctypes.POINTER(ctypes.c_uint8)),
     ]
 
 

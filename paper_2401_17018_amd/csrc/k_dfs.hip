@@ -35,6 +35,7 @@
 // Termination: `pending` counts unfinished work items (initially the seeds);
 // the wave that finishes the last one sends every wave the stop message.
 #include "dev_common.h"
+#include "handover.h"
 #include "kernels.h"
 
 namespace {
@@ -42,7 +43,6 @@ namespace {
 constexpr int DFS_THREADS = 256;
 constexpr int DFS_WAVES = DFS_THREADS / GM_WAVE;
 constexpr int MAX_OTH = 120;  // >= |E(Q)| - 1 for any simple query with k <= 16
-constexpr int TASK_WORDS = 32;
 constexpr uint32_t MSG_TASK = 1, MSG_STOP = 3;
 // the idle count is kept in IDLE_REPS copies, one per 128-byte line; a wave
 // polls the copy of its XCD
@@ -73,6 +73,21 @@ constexpr uint32_t PACK_MAX = GM_PACK_MAX;
 #define GM_POLL_STEPS 4
 #endif
 constexpr uint32_t POLL_STEPS = GM_POLL_STEPS;
+
+// Algorithmic bytes, counted in eighths of a byte by a fixed model of what
+// the method must read, whatever this kernel's layout makes it read: per
+// candidate examined, its 4-byte id, a 1-byte label and 1 bit of the
+// candidate table; per lower-bound search in another neighbour list of
+// length n, ceil(log2 n) + 1 reads of 4 bytes; 16 bytes per batch-hash probe
+// of a flagged entry; 4 bytes per tuple element written (and 4 for its
+// attributed update).  External ids (a consequence of the label-grouped
+// renumbering) and level set-up reads are not counted.
+constexpr uint64_t MB_CAND = 41;         // (4 + 1 + 1/8) * 8
+constexpr uint64_t MB_HASH_PROBE = 128;  // 16 * 8
+constexpr uint64_t MB_WORD = 32;         // 4 * 8
+__device__ inline uint32_t mb_search(uint32_t n) {  // ceil(log2 n) + 1 for n >= 1
+  return (n > 1 ? 32u - (uint32_t)__clz((int)(n - 1)) : 0u) + 1u;
+}
 
 struct WaveState {
   uint32_t f[GM_MAX_K];    // internal data vertex of each query vertex
@@ -125,6 +140,15 @@ __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstla
 __device__ inline uint64_t uni64(uint64_t x) {
   return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
+
+struct WaveView {
+  const WaveState& S;
+  __device__ uint32_t cur(uint32_t x) const { return uni(S.cur[x]); }
+  __device__ uint32_t len(uint32_t x) const { return uni(S.len[x]); }
+  __device__ uint64_t mask(uint32_t x) const { return uni64(S.mask[x]); }
+  __device__ uint32_t pvalid() const { return uni(S.pvalid); }
+  __device__ uint32_t pidx() const { return uni(S.pidx); }
+};
 // value of lane i (i uniform)
 __device__ inline uint32_t lane_val(uint32_t x, uint32_t i) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)i);
@@ -169,47 +193,12 @@ __device__ inline uint64_t ld_coherent64(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wave-cooperative lower bound in a sorted (masked) list: first index whose
-// value >= key.  Each step samples 64 evenly spaced entries (64-ary search).
-__device__ inline uint32_t wave_lb(const uint32_t* __restrict__ col, uint64_t base, uint32_t len,
-                                   uint32_t key, int lane, uint64_t& bytes) {
-  uint32_t lo = 0, hi = len;
-  while (hi - lo > GM_WAVE) {
-    const uint32_t step = (hi - lo + GM_WAVE - 1) / GM_WAVE;
-    const uint32_t pos = lo + (uint32_t)lane * step;
-    const bool in = pos < hi;
-    uint32_t val = 0;
-    if (in) {
-      val = col[base + pos] & GM_IDMASK;
-      bytes += 4;
-    }
-    const uint32_t c = (uint32_t)__popcll(__ballot(in && val < key));
-    if (c == 0) return lo;
-    const uint32_t pos_c = lo + c * step;
-    const uint32_t nlo = lo + (c - 1) * step + 1;
-    hi = (c < GM_WAVE && pos_c < hi) ? pos_c : hi;
-    lo = nlo;
-  }
-  if (hi > lo) {
-    const uint32_t pos = lo + (uint32_t)lane;
-    const bool in = pos < hi;
-    uint32_t val = 0;
-    if (in) {
-      val = col[base + pos] & GM_IDMASK;
-      bytes += 4;
-    }
-    lo += (uint32_t)__popcll(__ballot(in && val < key));
-  }
-  return lo;
-}
-
 // Per-lane lower bound (binary search) in a sorted (masked) list.
 __device__ inline uint32_t lane_lb(const uint32_t* __restrict__ col, uint64_t base, uint32_t len,
-                                   uint32_t key, uint64_t& bytes) {
+                                   uint32_t key) {
   uint32_t lo = 0, n = len;
   while (n > 0) {
     const uint32_t half = n >> 1;
-    bytes += 4;
     if ((col[base + lo + half] & GM_IDMASK) < key) {
       lo += half + 1;
       n -= half + 1;
@@ -223,14 +212,13 @@ __device__ inline uint32_t lane_lb(const uint32_t* __restrict__ col, uint64_t ba
 // Is batch edge {a, c} usable by the seed (ord, sign)?
 __device__ inline bool visible(const GmBatchHash& H, uint32_t a, uint32_t c, uint32_t ord,
                                uint32_t sign, uint64_t& bytes) {
+  bytes += MB_HASH_PROBE;
   const uint64_t key = gm_edge_key(a, c);
   uint32_t slot = gm_hash_slot(key, H.mask);
   for (uint32_t p = 0; p <= H.mask; ++p) {
     const uint64_t k = H.keys[slot];
-    bytes += 8;
     if (k == key) {
       const uint32_t v = H.vals[slot];
-      bytes += 4;
       return ((v & 1u) == sign) && ((v >> 1) > ord);
     }
     if (k == GM_EMPTY64) return false;
@@ -269,20 +257,21 @@ __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
 // permutation pi whose match f o pi is emitted (tuple position j holds
 // f(pi(j))), and hu = pi^-1(u), the position the candidate's term takes in
 // the checksum (hpre then holds the other positions' terms for pi).
-__device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t k, uint32_t u, bool ok,
+__device__ inline void emit(const GmDfsParams& P, uint32_t flags, WaveState& S, Acc& A, uint32_t k, uint32_t u,
+                            bool ok,
                             uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q, uint32_t sign,
                             uint32_t ord, int lane, uint64_t lt, uint64_t& bytes, uint32_t p2 = 0xFFFFFFFFu,
                             uint32_t x2 = 0, CPerm pf = nullptr, uint32_t hu = 0xFFFFFFFFu) {
   if (ok) A.cnt += 1;
   uint64_t h = 0;
-  if (P.flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
+  if (flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
     if (ok) {
       h = gm_mix64(hpre + elem_hash(cx, hu == 0xFFFFFFFFu ? u : hu));  // hpre: terms of every other position
       A.sum += h;
       A.xr ^= h;
     }
   }
-  if (P.flags & GM_F_TUPLES) {
+  if (flags & GM_F_TUPLES) {
     const uint32_t nok = (uint32_t)__popcll(m);
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&P.ctr->tuples_found, (unsigned long long)nok);
@@ -295,11 +284,11 @@ __device__ inline void emit(const GmDfsParams& P, WaveState& S, Acc& A, uint32_t
         row[j] = j < k ? (src == u ? cx : (src == p2 ? x2 : S.fx[src])) : 0xFFFFFFFFu;
       }
       P.tmeta[pos] = (q << 1) | sign;
-      if (P.flags & GM_F_SEED_ATTR) P.tord[pos] = ord;
-      bytes += 4ull * P.twidth + 8;
+      if (flags & GM_F_SEED_ATTR) P.tord[pos] = ord;
+      bytes += MB_WORD * (k + ((flags & GM_F_SEED_ATTR) ? 1u : 0u));
     }
   }
-  if (P.flags & GM_F_PER_UPDATE) {
+  if (flags & GM_F_PER_UPDATE) {
     const uint64_t c = (uint64_t)__popcll(m);
     const uint64_t s = wave_sum64(ok ? h : 0);
     const uint64_t x = wave_xor64(ok ? h : 0);
@@ -326,7 +315,16 @@ __device__ inline void broadcast_stop(const GmDfsParams& P, int lane) {
 #endif
 #define GM_DFS_ATTR __attribute__((amdgpu_waves_per_eu(GM_DFS_WAVES_PER_EU)))
 
+// Two builds of one body.  FULL = false is the lean search: no coalesced
+// plans, no edge labels, no tuple output (counts, checksums and per-update
+// attribution only), which leaves those paths out of its register budget.
+// FULL = true takes every feature.  The host launches the lean one whenever
+// a batch needs none of them.
+template <bool FULL>
 __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) {
+  const uint32_t coal = FULL ? P.coalesce : 0u;
+  const uint32_t elb = FULL ? P.G.elb : 0u;
+  const uint32_t flags = FULL ? P.flags : (P.flags & ~(uint32_t)(GM_F_TUPLES | GM_F_SEED_ATTR));
   __shared__ WaveState WS[DFS_WAVES];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
@@ -381,6 +379,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     uint32_t tword = 0;  // handed-over work: lane w holds word w of the task record
     bool handed = false;
     bool ptask = false;  // the handed work is a share of another wave's core permutations
+    uint32_t item_seed = 0;  // the seed this work item belongs to (completion tracking)
     if (seeds_left) {
       if (P.deadline_ticks && wall_clock64() - t_start > P.deadline_ticks) {
         if (lane == 0) atomicExch(&P.ctr->aborted, 1u);
@@ -390,6 +389,8 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       if (lane == 0) t = atomicAdd(&P.ctr->seed_head, 1ull);
       t = lane_val64(t, 0);
       if (t < n_seeds) {
+        item_seed = (uint32_t)t;
+        if (P.seed_open && lane == 0) atomicExch(&P.seed_open[t], 1u);
         const GmSeed sd = P.seeds[t];
         q = uni(sd.qd >> 8);
         dq = uni(sd.qd & 255u);
@@ -435,30 +436,32 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       // MSG_TASK: the donor cleared our bit and lowered the idle count;
       // its release store on the flag orders the task record before it
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      tword = lane < TASK_WORDS ? P.mbox[(uint64_t)slot * TASK_WORDS + lane] : 0;
+      tword = lane < HO_WORDS ? P.mbox[(uint64_t)slot * HO_WORDS + lane] : 0;
       if (lane == 0) __hip_atomic_store(&P.mflag[slot], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t w = tword;
-      q = lane_val(w, 0) >> 8;
-      dq = lane_val(w, 0) & 255u;
-      const uint32_t os = lane_val(w, 1);
+      q = lane_val(w, HO_W_QD) >> 8;
+      dq = lane_val(w, HO_W_QD) & 255u;
+      const uint32_t os = lane_val(w, HO_W_OS);
       ord = os >> 1;
       sign = os & 1u;
-      const uint32_t w2 = lane_val(w, 2);
-      ptask = (w2 >> 31) != 0u;
+      const uint32_t w2 = lane_val(w, HO_W_LV);
+      ptask = FULL && (w2 >> 31) != 0u;
       base_l = w2 & 0x7FFFFFFFu;
-      if (lane >= 8 && lane < 8 + GM_MAX_K) S.f[lane - 8] = w;
+      item_seed = lane_val(w, HO_W_SEED);
+      if (lane >= HO_W_F && lane < HO_W_F + GM_MAX_K) S.f[lane - HO_W_F] = w;
       handed = true;
     }
 
     CPlan pl = (CPlan)P.plans + ((CQuery)P.queries)[q].plan_base + dq;
     const uint32_t k = uni(pl->k);
     // coalesced search: this plan's matches stand for nperm permutations
-    const uint32_t nperm = P.coalesce ? uni(pl->n_perm) : 1u;
-    CPerm perm0 = (CPerm)P.perms + (P.coalesce ? uni(pl->perm_base) : 0u);
+    const uint32_t nperm = coal ? uni(pl->n_perm) : 1u;
+    CPerm perm0 = (CPerm)P.perms + (coal ? uni(pl->perm_base) : 0u);
     // coalescing over the core: after the n_core core levels, level L0 is
     // entered once per permutation of the core prefix
-    const uint32_t ncp = P.coalesce >= 2 ? uni(pl->n_cperm) : 1u;
+    const uint32_t ncp = coal >= 2 ? uni(pl->n_cperm) : 1u;
     const uint32_t L0 = ncp > 1 ? uni(pl->n_core) : 0xFFFFFFFFu;
+    const bool core = FULL && ncp > 1;  // (constant false in the lean build)
     CPerm cperm0 = (CPerm)P.perms + (ncp > 1 ? uni(pl->cperm_base) : 0u);
     const uint32_t key = (q << 1) | sign;
     if (key != A.key) {
@@ -472,21 +475,21 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       S.fo[lane] = fu;
       S.fx[u] = P.G.old_of_new[fu];
     }
-    st_bytes += 4ull * base_l;
 
     if (k == 2) {
       // the seed itself is the whole match (and, coalesced, its mirror image)
       if (nperm == 1) {
         const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], 0);
-        emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
+        emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
       } else {
         for (uint32_t pi = 0; pi < nperm; ++pi) {
           CPerm pp = perm0 + pi;
           const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], uni(pp->inv[0]));
-          emit(P, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu, 0, pp,
+          emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu, 0, pp,
                uni(pp->inv[1]));
         }
       }
+      if (P.seed_open && lane == 0) atomicSub(&P.seed_open[item_seed], 1u);
       if (P.donate) {
         unsigned long long left = 1;
         if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
@@ -571,18 +574,17 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         // with edge labels the list is the row of f(w) for the label of
         // the query edge between w and the vertex being matched
         uint32_t row = v;
-        if (P.G.elb) {
+        if (elb) {
           // lanes 32-63 serve the last vertex: select per lane between the
           // two wave-uniform query vertices
           const uint32_t ut = hi ? uni(pl->order[k - 1]) : uni(pl->order[l]);
-          row = (v << P.G.elb) | P.qel[(q * GM_MAX_K + ut) * GM_MAX_K + w];
+          row = (v << elb) | P.qel[(q * GM_MAX_K + ut) * GM_MAX_K + w];
         }
         const uint64_t off = P.G.row_off[row];
         const uint64_t li = P.lix[(uint64_t)row * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
         base = off + (uint32_t)li;
         sub = (uint32_t)(li >> 32);
       }
-      st_bytes += 16ull * (nb + nb1);
       // an empty list leaves no candidate (for a static list of the last
       // level: no candidate for any extension of this prefix)
       if (__ballot(act && sub == 0)) return false;
@@ -661,14 +663,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         uint32_t sub = 0;
         if (dyn) {
           uint32_t row = c;
-          if (P.G.elb) row = (c << P.G.elb) | P.qel[(q * GM_MAX_K + uni(pl->order[k - 1])) * GM_MAX_K + u];
+          if (elb) row = (c << elb) | P.qel[(q * GM_MAX_K + uni(pl->order[k - 1])) * GM_MAX_K + u];
           const uint64_t off = P.G.row_off[row];
           const uint64_t li = P.lix[(uint64_t)row * P.lix_slots + ls1];
           base = off + (uint32_t)li;
           sub = (uint32_t)(li >> 32);
-          st_bytes += 16;
         }
-        st_bytes += 4;
         S.pf_c[lane] = c;
         S.pf_x[lane] = x;
         S.pf_base[lane] = base;
@@ -695,7 +695,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       uint32_t e = 0;
       if (ok) {
         e = col[uni64(S.drv[l]) + idx];
-        st_bytes += 4;
+        st_bytes += MB_CAND;
         ++st_scan;
       }
       const uint32_t c = e & GM_IDMASK;
@@ -705,7 +705,6 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         // (a representative's core vertex passes for any of its positions)
         const uint32_t om = ncp > 1 ? uni(pl->omask[u]) : 1u << u;
         ok = (P.cand[(uint64_t)q * n + c] & om) != 0u;
-        st_bytes += 2;
       }
       if (ok && (e & GM_FLAG)) ok = visible(P.H, S.drvv[l], c, ord, sign, st_bytes);
       const uint32_t on = uni(S.oth_n[l]);
@@ -715,12 +714,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (ok) {
           const uint64_t base = S.oth_base[ob + i];
           const uint32_t olen = S.oth_len[ob + i];
-          const uint32_t p = lane_lb(col, base, olen, c, st_bytes);
+          st_bytes += MB_WORD * mb_search(olen);
+          const uint32_t p = lane_lb(col, base, olen, c);
           if (p >= olen) {
             ok = false;
           } else {
             const uint32_t e2 = col[base + p];
-            st_bytes += 4;
             if ((e2 & GM_IDMASK) != c)
               ok = false;
             else if (e2 & GM_FLAG)
@@ -736,49 +735,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 
     // ---- hand the upper half of the shallowest unexplored work to an idle wave
     auto try_donate_impl = [&](uint32_t lcur) {
-      uint32_t lv = 0xFFFFFFFFu, kind = 0, mid = 0, old_len = 0;
-      uint64_t give = 0;
-      for (uint32_t x = base_l; x <= lcur; ++x) {
-        if (x == L0 && base_l < L0) {
-          // the permutations of the core prefix not yet entered (each a
-          // whole subtree), when at least two are left: the upper half of
-          // them.  The donor keeps at least one, so a single permutation is
-          // never passed on (a wave that has just received one polls before
-          // entering it, and would hand it on again, and so on, for as long
-          // as some wave is idle).
-          const uint32_t pi = uni(S.pidx);
-          const uint32_t rem = uni(S.pvalid) & (pi == 0xFFFFFFFFu ? 0xFFFFFFFFu : ~((2u << pi) - 1u));
-          if (__popc(rem) >= 2) {
-            uint32_t g = rem;
-            for (int i = 0, h = (__popc(rem) + 1) / 2; i < h; ++i) g &= g - 1;  // drop the lower half
-            lv = x;
-            kind = 3;
-            give = g;
-            break;
-          }
-        }
-        const uint32_t cur = uni(S.cur[x]), len = uni(S.len[x]);
-        const uint32_t min_split = (x == k - 1) ? P.split_leaf : P.split_inner;
-        if (len > cur && len - cur >= min_split) {
-          lv = x;
-          kind = 1;
-          mid = cur + ((len - cur) >> 1);
-          old_len = len;
-          break;
-        }
-        if (x + 1 < k) {
-          const uint64_t m = uni64(S.mask[x]);
-          const int pc = __popcll(m);
-          if (pc >= 2) {
-            uint64_t hi = m;
-            for (int i = 0; i < (pc + 1) / 2; ++i) hi &= hi - 1;  // drop the lower half
-            lv = x;
-            kind = 2;
-            give = hi;
-            break;
-          }
-        }
-      }
+      // the shallowest splittable work (rules shared with the host model)
+      const HoSplit sp = ho_choose(WaveView{S}, base_l, lcur, k, core, L0, P.split_leaf, P.split_inner,
+                                   ho_rule_default());
+      const uint32_t lv = sp.lv, kind = sp.kind;
+      const uint64_t give = sp.give;
       if (kind == 0) return;
       // claim an idle wave: scan the bitmap (64 words per coherent load) from
       // a pseudo-random word, clear one set bit with an atomic AND.  No waiting.
@@ -808,24 +769,23 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       if (target < 0) return;
       if ((uint32_t)lane < IDLE_REPS) atomicSub(&P.idle_rep[lane * IDLE_STRIDE], 1u);
-      if (kind == 1)
-        S.len[lv] = mid;
-      else if (kind == 2)
+      if (kind == HO_RANGE)
+        S.len[lv] = sp.mid;
+      else if (kind == HO_SURV)
         S.mask[lv] = uni64(S.mask[lv]) & ~give;
       else
         S.pvalid = uni(S.pvalid) & ~(uint32_t)give;
-      uint32_t w = 0;
-      if (lane == 0) w = (q << 8) | dq;
-      else if (lane == 1) w = (ord << 1) | sign;
-      else if (lane == 2) w = kind == 3 ? (lv | 0x80000000u) : lv;
-      else if (lane == 3) w = kind == 2 ? uni(S.chunk[lv]) : 0u;
-      else if (lane == 4) w = (uint32_t)give;
-      else if (lane == 5) w = (uint32_t)(give >> 32);
-      else if (lane == 6) w = kind == 1 ? mid : 0u;
-      else if (lane == 7) w = kind == 1 ? old_len : 0u;
-      else if (lane < 8 + GM_MAX_K) w = (kind == 3 || (lv < L0 && lcur >= L0)) ? S.fcore[lane - 8] : S.f[lane - 8];
+      // the partial match: the core prefix as found when the work lies in
+      // or above a core being permuted
+      const uint32_t fi = (lane >= HO_W_F && lane < HO_W_F + GM_MAX_K)
+                              ? ((kind == HO_PERMS || (core && lv < L0 && lcur >= L0)) ? S.fcore[lane - HO_W_F]
+                                                                                       : S.f[lane - HO_W_F])
+                              : 0u;
+      const uint32_t w = ho_task_word((uint32_t)lane, q, dq, ord, sign, sp, kind == HO_SURV ? uni(S.chunk[lv]) : 0u,
+                                      fi, item_seed);
       if (lane == 0) atomicAdd(&P.ctr->pending, 1ull);
-      if (lane < TASK_WORDS) P.mbox[(uint64_t)target * TASK_WORDS + lane] = w;
+      if (P.seed_open && lane == 0) atomicAdd(&P.seed_open[item_seed], 1u);
+      if (lane < HO_WORDS) P.mbox[(uint64_t)target * HO_WORDS + lane] = w;
       if (lane == 0) {
         __hip_atomic_store(&P.mflag[target], MSG_TASK, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         S.tally[6] += 1;
@@ -837,12 +797,10 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // LEAF_UNROLL lower-bound searches run interleaved.
     auto probe_list = [&](bool (&ok)[LEAF_UNROLL], const uint32_t (&e)[LEAF_UNROLL], uint64_t base, uint32_t olen,
                           uint32_t wv) {
-      // a lower-bound search over olen entries reads at most
-      // bit_length(olen) entries, plus the entry it lands on
       uint32_t n_probe = 0;
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
-      u_bytes += 4ull * n_probe * (uint32_t)(33 - __clz((int)olen));
+      u_bytes += MB_WORD * n_probe * mb_search(olen);
       CNT(2, n_probe);
       CNT(4, olen);
       uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
@@ -898,7 +856,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint64_t drv = uni64(S.drv[l]);
       const uint32_t on = uni(S.oth_n[l]);
       const uint32_t ob = uni(pl->bofs[l]);
-      const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
+      const bool need_x = (flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
       uint32_t e[LEAF_UNROLL], x[LEAF_UNROLL];
       bool ok[LEAF_UNROLL];
       // branch-free: lanes past the end read the last entry (len >= 1) and
@@ -924,7 +882,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j) n_in += (uint32_t)__popcll(__ballot(ok[j]));
       u_scan += n_in;
-      u_bytes += (uint64_t)n_in * (need_x ? 8u : 4u);
+      u_bytes += (uint64_t)n_in * MB_CAND;
       CNT(0, 1);
       CNT(3, n_in);
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
@@ -949,7 +907,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) {
           const uint64_t m = __ballot(ok[j]);
-          if (m) emit(P, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
+          if (m) emit(P, flags, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
         }
       } else {
         // coalesced plan: every match found stands for nperm permuted ones
@@ -959,7 +917,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           if (m)
             for (uint32_t pi = 0; pi < nperm; ++pi) {
               CPerm pp = perm0 + pi;
-              emit(P, S, A, k, u, ok[j], m, x[j], uni64(S.hpp[pi]), q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu,
+              emit(P, flags, S, A, k, u, ok[j], m, x[j], uni64(S.hpp[pi]), q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu,
                    0, pp, uni(pp->inv[u]));
             }
         }
@@ -1028,7 +986,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint32_t nb1 = uni(S.st_n);
       const uint64_t st_h = uni64(S.st_h);
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
-      const bool need_x = (P.flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
+      const bool need_x = (flags & (GM_F_HASH | GM_F_TUPLES | GM_F_PER_UPDATE)) != 0;
       for (uint32_t t0 = 0; t0 < T; t0 += LEAF_UNROLL * GM_WAVE) {
         // the cycle-counter read behind a poll is a scalar memory access:
         // every 4th step is often enough
@@ -1068,7 +1026,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) n_in += (uint32_t)__popcll(__ballot(ok[j]));
         u_scan += n_in;
-        u_bytes += (uint64_t)n_in * (need_x ? 8u : 4u);
+        u_bytes += (uint64_t)n_in * MB_CAND;
         CNT(0, 1);
         CNT(3, n_in);
         // injectivity against order[0 .. k-3] (a neighbour of the survivor
@@ -1093,8 +1051,8 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           const uint64_t mm = __ballot(ok[j]);
           if (mm) {
             const uint64_t hpre = st_h + S.pf_h[sl[j]];
-            const uint32_t x2 = (P.flags & GM_F_TUPLES) ? S.pf_x[sl[j]] : 0u;
-            emit(P, S, A, k, u, ok[j], mm, x[j], hpre, q, sign, ord, lane, lt, st_bytes, u2, x2);
+            const uint32_t x2 = (flags & GM_F_TUPLES) ? S.pf_x[sl[j]] : 0u;
+            emit(P, flags, S, A, k, u, ok[j], mm, x[j], hpre, q, sign, ord, lane, lt, st_bytes, u2, x2);
           }
         }
       }
@@ -1164,7 +1122,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         S.fcore[v] = S.f[v];
         S.fxcore[v] = S.fx[v];
       }
-      S.pvalid = lane_val(tword, 4);
+      S.pvalid = lane_val(tword, HO_W_GIVE_LO);
       S.pidx = 0xFFFFFFFFu;
       base_l = L0 - 1;
       S.cur[L0 - 1] = 0;
@@ -1182,11 +1140,11 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       // an empty first level (a seed with no extension)
     } else {
       if (handed && !ptask) {
-        S.cur[l] = lane_val(tword, 6);
-        S.len[l] = lane_val(tword, 7);
-        S.chunk[l] = lane_val(tword, 3);
-        const uint32_t mlo = lane_val(tword, 4);
-        const uint32_t mhi = lane_val(tword, 5);
+        S.cur[l] = lane_val(tword, HO_W_CUR);
+        S.len[l] = lane_val(tword, HO_W_END);
+        S.chunk[l] = lane_val(tword, HO_W_CHUNK);
+        const uint32_t mlo = lane_val(tword, HO_W_GIVE_LO);
+        const uint32_t mhi = lane_val(tword, HO_W_GIVE_HI);
         S.mask[l] = ((uint64_t)mhi << 32) | mlo;
       }
       for (;;) {
@@ -1206,7 +1164,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
             // the core prefix's next permutation that puts every data
             // vertex where the filter admits it (a received task starting
             // at L0 searches its own permuted prefix only).  pidx + 1 <= 16.
-            if (l == L0 && (uni(S.pvalid) >> (uni(S.pidx) + 1)) != 0u) {
+            if (core && l == L0 && (uni(S.pvalid) >> (uni(S.pidx) + 1)) != 0u) {
               const uint32_t p0 = uni(S.pidx) + 1;
               const uint32_t p = p0 + (uint32_t)__builtin_ctz(uni(S.pvalid) >> p0);
               S.pidx = p;
@@ -1214,7 +1172,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
               l = L0 - 1;
               nl = L0;
             } else {
-              if (l == L0) restore_core();
+              if (core && l == L0) restore_core();
               --l;
               continue;
             }
@@ -1263,8 +1221,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           S.f[u] = c;
           S.fo[l] = c;
           S.fx[u] = uni(ext[at]);
-          st_bytes += 8;
-          if (l + 1 == L0) {
+          if (core && l + 1 == L0) {
             // a core match: keep it with its vertices' filter words and
             // stand at level L0 used up under a permutation -1, so that the
             // step back above enters the permutations from the identity on
@@ -1274,7 +1231,6 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
               S.fcore[v] = fv;
               S.fxcore[v] = S.fx[v];
               S.ccw[v] = P.cand[(uint64_t)q * n + fv];
-              st_bytes += 2;
             }
             S.pvalid = cperm_valid();
             S.pidx = 0xFFFFFFFFu;
@@ -1290,7 +1246,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         // is called, and each copy costs registers)
         if (init_level(nl, true)) {
           l = nl;
-        } else if (nl == L0) {
+        } else if (core && nl == L0) {
           // no candidate under this permutation: stand at level L0 used up,
           // so that the next pass tries the next permutation
           l = L0;
@@ -1302,6 +1258,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     }
     if (abort_now) break;
     // ---- work item finished
+    if (P.seed_open && lane == 0) atomicSub(&P.seed_open[item_seed], 1u);
     if (P.donate) {
       unsigned long long left = 1;
       if (lane == 0) left = atomicAdd(&P.ctr->pending, ~0ull);
@@ -1322,6 +1279,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
   }
 }
 
+__global__ void k_upd_open(const GmSeed* __restrict__ seeds, const GmCounters* __restrict__ ctr, uint64_t seed_cap,
+                           const uint32_t* __restrict__ seed_open, uint8_t* __restrict__ upd_open) {
+  const uint64_t ns = ctr->n_seeds < seed_cap ? ctr->n_seeds : seed_cap;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x)
+    if (seed_open[t] != 0u) upd_open[seeds[t].os >> 1] = 1u;
+}
+
 }  // namespace
 
 namespace gm {
@@ -1330,8 +1294,22 @@ unsigned dfs_block_threads() { return DFS_THREADS; }
 unsigned dfs_waves_per_block() { return DFS_WAVES; }
 uint32_t dfs_slots(unsigned blocks) { return 8u * ((blocks + 7) / 8) * DFS_WAVES; }
 
+bool dfs_lean(const GmDfsParams& P) {
+  return P.coalesce == 0 && P.G.elb == 0 && (P.flags & (GM_F_TUPLES | GM_F_SEED_ATTR)) == 0;
+}
+
+void launch_upd_open(const GmSeed* seeds, const GmCounters* ctr, uint64_t seed_cap, const uint32_t* seed_open,
+                     uint8_t* upd_open, hipStream_t s) {
+  const uint64_t want = (seed_cap + 255) / 256;
+  const unsigned blocks = (unsigned)(want < 4096 ? (want ? want : 1) : 4096);
+  k_upd_open<<<blocks, 256, 0, s>>>(seeds, ctr, seed_cap, seed_open, upd_open);
+}
+
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s) {
-  k_dfs<<<blocks, DFS_THREADS, 0, s>>>(P);
+  if (dfs_lean(P))
+    k_dfs<false><<<blocks, DFS_THREADS, 0, s>>>(P);
+  else
+    k_dfs<true><<<blocks, DFS_THREADS, 0, s>>>(P);
 }
 
 }  // namespace gm

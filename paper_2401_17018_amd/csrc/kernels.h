@@ -88,6 +88,10 @@ struct GmDfsParams {
                                   // 2: also permute core prefixes (plans with n_cperm >= 2)
   uint32_t pad3;
   const uint8_t* qel;             // [nq][16][16] edge label of query edge {u, w} (used when G.elb > 0)
+  // per seed, its work items not yet finished (the seed's own item plus one
+  // per hand-over of its work); 0xFFFFFFFF = not started.  NULL: untracked.
+  // A seed at 0 when the search ends (also past a deadline) is complete.
+  uint32_t* seed_open;
 };
 
 namespace gm {
@@ -196,6 +200,10 @@ void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_
 
 // search (k_dfs.hip)
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);
+// upd_open[ord] = 1 for every canonical update with a seed whose search did
+// not finish (seed_open != 0); upd_open must be zeroed first
+void launch_upd_open(const GmSeed* seeds, const GmCounters* ctr, uint64_t seed_cap, const uint32_t* seed_open,
+                     uint8_t* upd_open, hipStream_t s);
 unsigned dfs_block_threads();
 unsigned dfs_waves_per_block();
 // mailbox slots needed for a grid of `blocks` search blocks

@@ -50,6 +50,7 @@ int bits_for(uint64_t x) {  // bits to hold any value < x (at least 1)
   return b;
 }
 
+
 }  // namespace
 
 struct gamma_ctx {
@@ -86,7 +87,7 @@ struct gamma_ctx {
   DevBuf runvals, runscan, touched, run_start, run_end, sizes, r1off, r2_off, r2_len;
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr, seeds_tmp, gkeys, gkeys_tmp;
   DevBuf tmp64a, tmp64b, tmp32a;
-  DevBuf mbox, mflag, idle_bits, idle_rep;
+  DevBuf mbox, mflag, idle_bits, idle_rep, seed_open, upd_open;
   DevBuf lix, lix_lab, r0_off, r0_len, permtab, qeltab;
   DevBuf vx_src, vx_dst, vx_op, vx_el, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
   uint32_t wall_khz = 100000;
@@ -101,6 +102,7 @@ struct gamma_ctx {
   std::vector<uint8_t> h_canon_sign;
   std::vector<uint64_t> h_upd;  // n_canon * 3
   std::vector<uint64_t> h_upd_cnt, h_upd_sum, h_upd_xor;
+  std::vector<uint8_t> h_upd_open;
   bool has_result = false;
   uint64_t last_tuples = 0;
   uint32_t last_twidth = 0;
@@ -117,9 +119,10 @@ struct gamma_ctx {
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
                       &runvals, &runscan, &touched, &run_start, &run_end, &sizes, &r1off, &r2_off,
                       &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &seeds_tmp, &gkeys, &gkeys_tmp, &tmp64a,
-                      &tmp64b, &tmp32a};
+                      &tmp64b, &tmp32a, &seed_open, &upd_open};
     for (DevBuf* b : list) all.push_back(b);
   }
+
 
   template <typename T>
   T* ensure(DevBuf& b, size_t count, bool keep_contents = false) {
@@ -778,13 +781,35 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       compact_arena(c, r1_total + r2_total);
       G = C.G();
     }
+    // every buffer the rest of the batch needs is sized here, before the
+    // graph is touched, so that running out of memory leaves it unchanged
     const uint64_t base1 = C.arena_top, base2 = base1 + r1_total;
     uint64_t* r2o = C.ensure<uint64_t>(C.r2_off, std::max<uint32_t>(n_touched, 1));
     uint32_t* r2l = C.ensure<uint32_t>(C.r2_len, std::max<uint32_t>(n_touched, 1));
-    G = C.G();
-    gm::launch_merge(dk, rsc, tch, rs_, re_, r1, n_touched, r1_total, base1, base2, ib, G, s);
     uint64_t* r0o = C.ensure<uint64_t>(C.r0_off, std::max<uint32_t>(n_touched, 1));
     uint32_t* r0l = C.ensure<uint32_t>(C.r0_len, std::max<uint32_t>(n_touched, 1));
+    const uint64_t seed_cap = std::max<uint64_t>((uint64_t)n_canon * C.total_plans, 1);
+    GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
+    const size_t qres_n = std::max<size_t>((size_t)nq * 6, 6);
+    unsigned long long* qres = C.ensure<unsigned long long>(C.qres, qres_n);
+    unsigned long long* upd = nullptr;
+    uint32_t* sopen = nullptr;  // per-seed completion, tracked with per-update results
+    uint8_t* uopen = nullptr;
+    const size_t uopen_words = ((size_t)n_canon + 3) / 4 + 1;
+    if (flags & GAMMA_F_PER_UPDATE) {
+      upd = C.ensure<unsigned long long>(C.upd_res, std::max<size_t>((size_t)n_canon * 3, 3));
+      sopen = C.ensure<uint32_t>(C.seed_open, seed_cap);
+      uopen = (uint8_t*)C.ensure<uint32_t>(C.upd_open, uopen_words);
+    }
+    const uint32_t wpc = C.tun.waves_per_cu;
+    const unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / gm::dfs_waves_per_block());
+    const uint32_t slots = gm::dfs_slots(blocks);
+    uint32_t* d_mbox = C.ensure<uint32_t>(C.mbox, (size_t)slots * 32);
+    uint32_t* d_mflag = C.ensure<uint32_t>(C.mflag, slots);
+    unsigned long long* d_idle_bits = (unsigned long long*)C.ensure<uint64_t>(C.idle_bits, (slots + 63) / 64);
+    uint32_t* d_idle_rep = C.ensure<uint32_t>(C.idle_rep, 256);
+    G = C.G();
+    gm::launch_merge(dk, rsc, tch, rs_, re_, r1, n_touched, r1_total, base1, base2, ib, G, s);
     gm::launch_rows_save(tch, n_touched, G, r0o, r0l, s);
     gm::launch_rows_set(tch, rs_, re_, rsc, r1, n_touched, base1, base2, G, r2o, r2l, s);
     C.touched_label_index(tch, n_touched);
@@ -801,8 +826,6 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     // ---------------------------------------------------------- seeds
     // (one launch per query: each query's seeds are generated right before
     // its own search launch, so that time falls in the search phase)
-    const uint64_t seed_cap = std::max<uint64_t>((uint64_t)n_canon * C.total_plans, 1);
-    GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
     const bool per_query = C.tun.query_launch == 2 && nq > 1;
     gm::launch_seed_window(ctr, s);
     if (nq && !per_query) {
@@ -833,14 +856,9 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     chk(hipEventRecord(C.ev[4], s), "event");
 
     // ---------------------------------------------------------- search
-    const size_t qres_n = std::max<size_t>((size_t)nq * 6, 6);
-    unsigned long long* qres = C.ensure<unsigned long long>(C.qres, qres_n);
     gm::fill_u64((uint64_t*)qres, 0, qres_n, s);
-    unsigned long long* upd = nullptr;
-    if (flags & GAMMA_F_PER_UPDATE) {
-      upd = C.ensure<unsigned long long>(C.upd_res, std::max<size_t>((size_t)n_canon * 3, 3));
-      gm::fill_u64((uint64_t*)upd, 0, (size_t)n_canon * 3, s);
-    }
+    if (upd) gm::fill_u64((uint64_t*)upd, 0, (size_t)n_canon * 3, s);
+    if (sopen) gm::fill_u32(sopen, 0xFFFFFFFFu, seed_cap, s);
     const uint32_t tw = C.kmax;
     uint64_t tcap = 0;
     if (flags & GAMMA_F_TUPLES) {
@@ -868,13 +886,10 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.tord = (uint32_t*)C.tord.p;
       P.tcap = tcap;
       P.upd_res = upd;
-      const uint32_t wpc = C.tun.waves_per_cu;
-      unsigned blocks = (unsigned)std::max<uint64_t>(1, (uint64_t)C.n_cu * wpc / gm::dfs_waves_per_block());
-      const uint32_t slots = gm::dfs_slots(blocks);
-      P.mbox = C.ensure<uint32_t>(C.mbox, (size_t)slots * 32);
-      P.mflag = C.ensure<uint32_t>(C.mflag, slots);
-      P.idle_bits = (unsigned long long*)C.ensure<uint64_t>(C.idle_bits, (slots + 63) / 64);
-      P.idle_rep = C.ensure<uint32_t>(C.idle_rep, 256);
+      P.mbox = d_mbox;
+      P.mflag = d_mflag;
+      P.idle_bits = d_idle_bits;
+      P.idle_rep = d_idle_rep;
       P.n_slots = slots;
       P.donate = C.tun.steal == 1 ? 1u : 0u;
       P.deadline_ticks = (uint64_t)C.opt.deadline_ms * C.wall_khz;
@@ -883,8 +898,15 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.split_leaf = C.tun.split_leaf;
       P.gate = C.tun.handover_gate;
       P.perms = (const GmPerm*)C.permtab.p;
-      P.coalesce = C.tun.coalesced_search - 1;
+      // plans permute matches only when some query (or core) has symmetries;
+      // without them coalescing changes nothing and the lean search applies
+      uint32_t coal = C.tun.coalesced_search - 1;
+      bool permutes = false;
+      for (const auto& hq : C.queries)
+        for (const auto& pl : hq.plans) permutes = permutes || pl.n_perm >= 2 || (coal >= 2 && pl.n_cperm >= 2);
+      P.coalesce = permutes ? coal : 0u;
       P.qel = (const uint8_t*)C.qeltab.p;
+      P.seed_open = sopen;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
@@ -900,6 +922,10 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       }
     }
     chk(hipEventRecord(C.ev[5], s), "event");
+    if (uopen) {
+      gm::fill_u32((uint32_t*)uopen, 0, uopen_words, s);
+      if (nq && n_canon) gm::launch_upd_open(sd, ctr, seed_cap, sopen, uopen, s);
+    }
 
     // ---------------------------------------------------------- commit G', refresh filter on G'
     // a dry run (or a search past its deadline) puts the saved rows back
@@ -914,7 +940,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
 
     // ---------------------------------------------------------- results to host
     size_t hbytes = qres_n * 8 + sizeof(GmCounters);
-    if (flags & GAMMA_F_PER_UPDATE) hbytes += (size_t)n_canon * 24;
+    if (flags & GAMMA_F_PER_UPDATE) hbytes += (size_t)n_canon * 25;
     if (flags & GAMMA_F_CANONICAL) hbytes += (size_t)n_canon * 9;
     char* hp = (char*)C.pinned(hbytes);
     uint64_t* h_qres = (uint64_t*)hp;
@@ -927,6 +953,12 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       h_upd = (uint64_t*)tail;
       chk(hipMemcpyAsync(h_upd, upd, (size_t)n_canon * 24, hipMemcpyDeviceToHost, s), "d2h");
       tail += (size_t)n_canon * 24;
+    }
+    uint8_t* h_uopen = nullptr;
+    if ((flags & GAMMA_F_PER_UPDATE) && n_canon) {
+      h_uopen = (uint8_t*)tail;
+      chk(hipMemcpyAsync(h_uopen, uopen, n_canon, hipMemcpyDeviceToHost, s), "d2h");
+      tail += n_canon;
     }
     uint32_t* h_clo = nullptr;
     if ((flags & GAMMA_F_CANONICAL) && n_canon) {
@@ -983,6 +1015,8 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       out->upd_count = C.h_upd_cnt.data();
       out->upd_hash_sum = C.h_upd_sum.data();
       out->upd_hash_xor = C.h_upd_xor.data();
+      C.h_upd_open.assign(h_uopen, h_uopen ? h_uopen + n_canon : nullptr);
+      out->upd_open = C.h_upd_open.data();
     }
     gamma_batch_stats& st = out->stats;
     st.n_input = n_upd;
@@ -1003,7 +1037,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     st.cyc_handover = h_ctr->cyc[4];
     st.tasks_received = h_ctr->cyc[5];
     st.seeds_started = std::min<uint64_t>(h_ctr->seed_head, h_ctr->n_seeds);
-    st.bytes_alg_dfs = h_ctr->bytes_alg;
+    st.bytes_alg_dfs = (h_ctr->bytes_alg + 4) / 8;  // the kernel counts eighths of a byte
     // merge: read old rows, write R1 and R2; commit: row pointers only
     st.bytes_alg_update = (r1_total - 2ull * n_insert) * 4 + r1_total * 4 + r2_total * 4 + (uint64_t)n_upd * 9;
     float ms = 0;

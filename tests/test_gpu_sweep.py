@@ -4,8 +4,10 @@ Each case draws a graph (ER or R-MAT-like skew, 1 to 3 vertex labels, with
 or without edge labels), a connected query of 2 to 7 vertices and a batch
 (insertions only, deletions only, mixed, with duplicates and no-ops, or
 empty), then compares tuple sets, counts, checksums, the canonical batch and
-per-update attribution with O2 (tuple sets below 10^6 matches).  All cases
-run in this one process."""
+per-update attribution with O2 (tuple sets below 10^6 matches), and the
+same batch searched for counts, checksums and attribution only (no tuples:
+the lean build of the search kernel on graphs without edge labels).  All
+cases run in this one process."""
 import numpy as np
 import pytest
 
@@ -89,6 +91,9 @@ def test_random_sweep(block):
         with make_ctx(cap=1 << 22) as ctx:
             ctx.load_graph(g.row_ptr, g.col, g.labels, elabels=g.elab, n_elabels=g.n_elabels)
             ctx.register_query(q.k, q.labels, q.edges, elabels=q.elabels)
+            # counts, checksums and attribution alone (the lean search build
+            # when the graph has no edge labels), as a dry run first
+            lean = ctx.apply_batch(b.src, b.dst, b.op, elab=b.elab, per_update=True, dry_run=True)
             res = ctx.apply_batch(b.src, b.dst, b.op, elab=b.elab, tuples=True, seed_attr=True, per_update=True,
                                   canonical=True)
         small = int(res.counts.sum()) < 1_000_000 and not res.truncated
@@ -101,3 +106,7 @@ def test_random_sweep(block):
                 assert res.tuple_set(0, sign, q.k) == ref.tuple_set(sign), (seed, sign)
         assert np.array_equal(res.canon_lo, ref.canon_lo) and np.array_equal(res.canon_hi, ref.canon_hi)
         assert np.array_equal(res.upd_count, ref.seed_count) and np.array_equal(res.upd_hash_xor, ref.seed_hxor)
+        assert np.array_equal(lean.counts, res.counts), seed
+        assert np.array_equal(lean.hash_sum, res.hash_sum) and np.array_equal(lean.hash_xor, res.hash_xor), seed
+        assert np.array_equal(lean.upd_count, ref.seed_count) and np.array_equal(lean.upd_hash_sum, ref.seed_hsum)
+        assert np.array_equal(lean.upd_hash_xor, ref.seed_hxor), seed

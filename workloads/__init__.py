@@ -529,8 +529,10 @@ def tiny(seed: int = 0) -> Workload:
 def rmat_stream(scale: int, m_graph: int, L: int, zipf_s: float, n_ins: int, n_del: int,
                 n_batches: int, queries_spec: Sequence[Tuple[int, str]], seed: int = 0,
                 pool_batches: Optional[int] = None, name: str = "", threads: int = 0,
-                query_min_label: int = 0) -> Workload:
-    """R-MAT graph, a stream of mixed batches, and queries extracted on G u I_0."""
+                query_min_label=0) -> Workload:
+    """R-MAT graph, a stream of mixed batches, and queries extracted on G u I_0.
+    query_min_label: one lowest label rank for every query's walk, or a
+    sequence with one per query."""
     pool_batches = pool_batches or n_batches
     if n_batches > pool_batches:
         raise ValueError("more batches than the hold-out pool covers")
@@ -541,8 +543,8 @@ def rmat_stream(scale: int, m_graph: int, L: int, zipf_s: float, n_ins: int, n_d
     queries = []
     protect = set()
     for qi, (k, kind) in enumerate(queries_spec):
-        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)),
-                          min_label=query_min_label)
+        ml = query_min_label[qi] if isinstance(query_min_label, (list, tuple)) else query_min_label
+        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)), min_label=ml)
         queries.append(q)
         for (x, y) in q.edges.tolist():
             a, b = q.planted[x], q.planted[y]
@@ -566,19 +568,25 @@ def mid(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
                        pool_batches=max(64, n_batches), name="mid-rmat20", threads=threads)
 
 
-LARGE_QUERY_MIN_LABEL = 12  # Zipf(1.0) over 32 labels: each label >= 12 covers <= 1.9% of vertices
+# Zipf(1.0) over 32 labels: each label of rank >= 12 covers <= 1.9 % of the
+# vertices, each of rank >= 20 <= 1.2 %
+LARGE_QUERY_MIN_LABEL = 12         # the dense query's walk
+LARGE_SPARSE_QUERY_MIN_LABEL = 20  # the sparse query's walk
 
 
 def large(seed: int = 0, n_batches: int = 1, threads: int = 0) -> Workload:
     """R-MAT scale 24, |E| = 16 * 2^24 (average degree 32 = 2^29 CSR
     entries), 32 Zipf(1.0) labels, two 8-vertex queries (sparse: tree + one
     cycle; dense: 17 edges), batches of 90,000 insertions and 10,000 deletions.
-    The query walks visit only vertices of the rarer labels (>= 12): with
-    walks through the most frequent labels, 100 of a batch's 10^5 updates
-    already gave 1.4 * 10^12 incremental matches before a 60 s deadline."""
+    The query walks visit only vertices of the rarer labels: with walks
+    through the most frequent labels, 100 of a batch's 10^5 updates already
+    gave 1.4 * 10^12 incremental matches before a 60 s deadline.  The dense
+    query's walk keeps to labels of rank >= 12; the sparse query, with 8
+    edges instead of 17, has far more matches for the same labels, and its
+    walk keeps to labels of rank >= 20."""
     return rmat_stream(24, 16 << 24, 32, 1.0, 90000, 10000, n_batches, [(8, "sparse"), (8, "dense")],
                        seed, pool_batches=max(16, n_batches), name="large-rmat24", threads=threads,
-                       query_min_label=LARGE_QUERY_MIN_LABEL)
+                       query_min_label=(LARGE_SPARSE_QUERY_MIN_LABEL, LARGE_QUERY_MIN_LABEL))
 
 
 BATCHED_QUERY_MIN_LABEL = 8  # Zipf(1.2) over 16 labels: each label >= 8 covers <= 2.6% of vertices
