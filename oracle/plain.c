@@ -69,6 +69,11 @@
  * seed_incomplete, its tuples are dropped, and it contributes nothing to
  * the per-pass totals; its seed_count holds seed_cap + 1, a lower bound of
  * its true count.  Every seed that is not flagged is exact.
+ *
+ * Ord list (a sampling control too): with ords != NULL only the canonical
+ * updates whose ords are listed are searched; the canonical batch, G' and
+ * the visibility of every batch edge are those of the whole batch, so each
+ * searched seed's figures are exactly its figures in the full run.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -351,6 +356,7 @@ typedef struct {
   uint32_t qid;
   int mutant, want_tuples;
   uint32_t sample_mod, sample_rem;
+  const uint8_t* pick; /* per canonical ord: 1 = searched (NULL: every ord) */
   uint64_t seed_cap; /* 0: none */
   /* work distribution */
   uint32_t next; /* atomic counter over canonical updates */
@@ -451,6 +457,7 @@ static void* worker_main(void* arg) {
     uint32_t i = __atomic_fetch_add(&sh->next, 1, __ATOMIC_RELAXED);
     if (i >= sh->c->n) break;
     if (sh->sample_mod > 1 && i % sh->sample_mod != sh->sample_rem) continue;
+    if (sh->pick && !sh->pick[i]) continue;
     int sign = sh->c->sign[i];
     uint32_t lo = sh->c->lo[i], hi = sh->c->hi[i], el = sh->c->e[i];
     const uint64_t n_out0 = w->out.n;
@@ -527,7 +534,8 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
               uint32_t L, const uint32_t* elab, uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m,
               const uint32_t* qedges, const uint32_t* qelab, uint32_t n_upd, const uint32_t* src,
               const uint32_t* dst, const uint8_t* op, const uint32_t* uelab, int threads, uint32_t sample_mod,
-              uint32_t sample_rem, uint64_t seed_cap, int want_tuples, int mutant, o2_result* res) {
+              uint32_t sample_rem, uint64_t seed_cap, const uint32_t* ords, uint32_t n_ords, int want_tuples,
+              int mutant, o2_result* res) {
   struct timespec t0, t1, tp;
   clock_gettime(CLOCK_MONOTONIC, &t0);
   memset(res, 0, sizeof(*res));
@@ -601,6 +609,13 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   sh.want_tuples = want_tuples;
   sh.sample_mod = sample_mod;
   sh.sample_rem = sample_rem;
+  uint8_t* pick = NULL;
+  if (ords) {
+    pick = (uint8_t*)calloc(c.n ? c.n : 1, 1);
+    for (uint32_t j = 0; j < n_ords; ++j)
+      if (ords[j] < c.n) pick[ords[j]] = 1;
+  }
+  sh.pick = pick;
   sh.seed_cap = seed_cap;
   uint32_t nc = c.n ? c.n : 1;
   sh.seed_count = (uint64_t*)calloc(nc, 8);
@@ -658,6 +673,7 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   res->threads_used = threads;
   free(ws);
   free(th);
+  free(pick);
   free(rp2);
   free(col2);
   free(key);
@@ -674,7 +690,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
            int threads, uint32_t sample_mod, uint32_t sample_rem, int want_tuples, int mutant,
            o2_result* res) {
   return o2_run_el(n, row_ptr, col, labels, 1, NULL, qid, k, qlabels, m, qedges, NULL, n_upd, src, dst, op, NULL,
-                   threads, sample_mod, sample_rem, 0, want_tuples, mutant, res);
+                   threads, sample_mod, sample_rem, 0, NULL, 0, want_tuples, mutant, res);
 }
 
 /* G' as a CSR for callers that chain batches (row_ptr n+1; col and, when

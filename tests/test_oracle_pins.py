@@ -371,3 +371,27 @@ def test_correct_oracle_passes_compact_pins():
                                     O2.MUT_KEEP_NOOPS])
 def test_planted_mistake_is_caught(mutant):
     assert not _pins_pass(mutant)
+
+
+def test_ord_list_sample_keeps_full_batch_figures():
+    """The ord-list sample (a sampling control) searches only the listed
+    canonical updates, each with exactly its figures of the full run (the
+    whole batch stays visible to the order rule)."""
+    g, q, b = W.random_small(17, n=40, p=0.3, n_labels=2, k=4, extra_q_edges=1, n_ins=30, n_del=20)
+    full = _check_o2_equals_o1(g, q, b)
+    pick = np.nonzero(full.seed_count > 0)[0][::2]
+    assert len(pick) >= 2
+    for threads in (1, 4):
+        r = O2.run(g, q, b, threads=threads, ords=pick.tolist())
+        assert r.status == 0 and r.n_canonical == full.n_canonical
+        sel = np.zeros(full.n_canonical, bool)
+        sel[pick] = True
+        assert np.array_equal(r.seed_count[sel], full.seed_count[sel]) and not r.seed_count[~sel].any()
+        assert np.array_equal(r.seed_hsum[sel], full.seed_hsum[sel])
+        assert np.array_equal(r.seed_hxor[sel], full.seed_hxor[sel])
+        for sign in (0, 1):
+            keep = np.isin(full.ord, pick) & (full.sign == sign)
+            assert r.tuple_set(sign) == {tuple(int(x) for x in t) for t in full.tuples[keep]}
+    # ords past the batch are ignored; an empty list searches nothing
+    r = O2.run(g, q, b, ords=[full.n_canonical + 5])
+    assert tuple(r.count) == (0, 0)
