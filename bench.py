@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("k_dfs.hip", "dev_common.h", "kernels.h")
+KERNEL_SOURCES = ("k_dfs.hip", "handover.h", "dev_common.h", "kernels.h")
 
 
 def kernel_source_hash() -> str:
@@ -107,6 +107,87 @@ def _planted_ord(g, q, b):
     return min(ords) if ords else None
 
 
+def host_cpu():
+    """(logical CPUs, CPU model) of this host."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def stored_attribution_sample(w, queries, b):
+    """For the large workload's first batch: per timed query, the canonical
+    updates that the oracle's own full-batch run (stored under tests/golden
+    by make_large_golden.py, which runs the oracle only) found to carry
+    between 1 and its per-seed cap of matches, when the stored inputs are
+    this run's; else None."""
+    if not w.name.startswith("large-rmat24") or b is not w.batches[0]:
+        return None
+    gdir = os.path.join(ROOT, "tests", "golden")
+    sys.path.insert(0, gdir)
+    try:
+        import make_large_golden as MG
+    finally:
+        sys.path.remove(gdir)
+    out = {}
+    for qi, q in enumerate(queries):
+        path = MG.path_of(q.kind)
+        if not os.path.exists(path):
+            return None
+        with open(path) as fh:
+            gold = json.load(fh)
+        if MG.input_fingerprints(w, q, b) != gold["inputs"]:
+            return None
+        out[qi] = ([int(r[0]) for r in gold["nonzero"]], int(gold["cap"]))
+    return out
+
+
+def cpu_baseline_stored(w, queries, b, sample):
+    """The oracle on the updates of `sample` (both queries), on every core
+    this host gives it (at most 16) and on one thread."""
+    from oracle import plain as O2
+    nproc, model = host_cpu()
+    threads = min(nproc, 16)
+    res = {}
+    for nt in (threads, 1):
+        mat = srch = prep = 0.0
+        n_up = 0
+        for qi, q in enumerate(queries):
+            ords, cap = sample[qi]
+            r = O2.run(w.graph, q, b, qid=qi, threads=nt, want_tuples=False, ords=ords)
+            mat += r.count[0] + r.count[1]
+            srch += r.seconds_search
+            prep += r.seconds_prep
+            n_up += len(ords)
+        res[nt] = (mat, srch, prep, n_up)
+        print("[bench] oracle on %d thread(s): %d matches in %.2f s of search (+%.1f s graph update)" % (
+            nt, mat, srch, prep), file=sys.stderr, flush=True)
+    mat, srch, prep, n_up = res[threads]
+    m1, s1, p1, _ = res[1]
+    return {
+        "value": mat / srch if srch > 0 else None,
+        "unit": "matches/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("first batch, both queries: the %d canonical updates that the oracle's own full-batch run "
+                   "(tests/golden/large_rmat24_*_batch0.json, per-seed cap %d) found to carry 1 to %d matches; "
+                   "%d matches; value = matches / search time" % (n_up, sample[0][1], sample[0][1], mat)),
+        "search_s": srch,
+        "graph_update_s": prep,
+        "nproc": nproc,
+        "cpu_model": model,
+        "one_thread": {"value": m1 / s1 if s1 > 0 else None, "unit": "matches/s", "search_s": s1,
+                       "graph_update_s": p1},
+        "speedup_all_threads": (s1 / srch) if srch > 0 else None,
+    }
+
+
 def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     """Time the oracle on a deterministic 1-in-M sample of the first batch's
     seeds (by canonical ord), shrinking M until the run takes a few seconds
@@ -116,8 +197,12 @@ def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     same oracle on one thread is timed on a sub-sample (the same residue
     class modulo a multiple of M that keeps the sample's busiest update)."""
     from oracle import plain as O2
-    threads = min(os.cpu_count() or 1, 16)
     g, b = w.graph, (w.batches[0] if batch is None else batch)
+    sample = stored_attribution_sample(w, queries, b)
+    if sample is not None:
+        return cpu_baseline_stored(w, queries, b, sample)
+    nproc, model = host_cpu()
+    threads = min(nproc, 16)
 
     per_ord = {}  # matches per sampled canonical ord (the oracle's own attribution)
 
@@ -171,6 +256,8 @@ def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
         "kind": "oracle",
         "sample": "first batch, %s (%d of %d updates), the timed queries; "
                   "%d matches in %.2f s including the oracle's own graph update" % (how, n_seeds, len(b), matches, secs),
+        "nproc": nproc,
+        "cpu_model": model,
         **({"one_thread": {"value": (one[0] / one[1]) if one[1] > 0 and one[0] > 0 else None,
                            "unit": "matches/s",
                            "sample": "ord %% %d == %d (%d updates): %d matches in %.2f s" % (
