@@ -270,6 +270,30 @@ gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* s
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);
 
+/* gamma_apply_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same batch semantics and results, with every per-batch
+ * device buffer taken from a static 64 MiB array in the library (one per
+ * GPU, held until the process ends) instead of the context's buffers.  It
+ * calls no hipMalloc, hipFree or hipHostMalloc (results are staged through
+ * the context's pinned buffer when it is large enough, else through
+ * pageable host memory).
+ *   Same arguments as gamma_apply_batch.  TUPLES and SEED_ATTR are not
+ *   available (EUNSUPPORTED); grouping of seeds (group_seeds = 2) is skipped.
+ * Errors: ENOMEM, with the graph unchanged, when the batch's buffers exceed
+ * the array (about 270 bytes per update plus 16 per update and directed
+ * query edge: roughly 120,000 updates for one 8-vertex, 8-edge query) or
+ * when the graph's arena has no
+ * room for the batch's rows (a gamma_apply_batch call compacts it);
+ * EDEVICE when the array's address could not be found on this device.
+ * The array is shared by every context on a GPU and keeps the last call's
+ * contents (each call clears what it needs): calls that overlap on one GPU,
+ * from several threads or contexts, race and must be serialised by the
+ * caller. */
+gamma_status gamma_apply_batch_noalloc(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
+                                       const uint32_t* dst, const uint8_t* op, gamma_mem where,
+                                       uint32_t flags, gamma_batch_result* out);
+
 /* As gamma_apply_batch on an edge-labelled graph: update i names the
  * triple {src[i], dst[i], elab[i]} (elab NULL: all 0; a label >= n_elabels
  * gives EINVAL).  Two updates of one pair in a batch must name the same

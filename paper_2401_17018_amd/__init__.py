@@ -191,8 +191,12 @@ class Context:
 
     def apply_batch(self, src, dst, op, hash: bool = True, tuples: bool = False, seed_attr: bool = False,
                     per_update: bool = False, canonical: bool = False, dry_run: bool = False,
-                    delete_vertices=None, elab=None) -> BatchOutput:
+                    delete_vertices=None, elab=None, noalloc: bool = False) -> BatchOutput:
         """Apply one batch (dry_run: search it without committing it).
+
+        noalloc: through gamma_apply_batch_noalloc, which allocates no device
+        memory (counts, checksums and attribution only; no edge labels or
+        vertex deletions).
         delete_vertices: ids whose incident edges are all deleted in the same
         batch, appended after the explicit updates (gamma_apply_batch_vertices).
         elab: the edge label of each update (edge-labelled graphs)."""
@@ -218,7 +222,12 @@ class Context:
         flags |= F_CANONICAL if canonical else 0
         flags |= F_DRY_RUN if dry_run else 0
         res = capi.BatchResult()
-        if delete_vertices is None:
+        if noalloc:
+            if delete_vertices is not None or elab is not None:
+                raise ValueError("noalloc takes plain edge updates only")
+            st = self._lib.gamma_apply_batch_noalloc(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
+                                                     o if n_upd else None, w1, flags, ctypes.byref(res))
+        elif delete_vertices is None:
             st = self._lib.gamma_apply_batch_el(self._ptr, n_upd, s if n_upd else None, d if n_upd else None,
                                                 o if n_upd else None, el if n_upd else None, w1, flags,
                                                 ctypes.byref(res))

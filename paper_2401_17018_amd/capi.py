@@ -24,7 +24,7 @@ F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL, F_DRY_RUN = 1
 EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
     "gamma_load_graph_el", "gamma_register_query_el", "gamma_apply_batch_el", "gamma_export_graph_el",
-    "gamma_apply_batch_vertices", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
+    "gamma_apply_batch_vertices", "gamma_apply_batch_noalloc", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
     "gamma_serve_create", "gamma_serve_submit", "gamma_serve_submit_el", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
     "gamma_serve_get_batch", "gamma_serve_get_tuples", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
@@ -203,6 +203,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_register_query.argtypes = [P, u32, P, u32, P, ctypes.POINTER(u32)]
     lib.gamma_apply_batch.restype = st
     lib.gamma_apply_batch.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, ctypes.POINTER(BatchResult)]
+    lib.gamma_apply_batch_noalloc.restype = st
+    lib.gamma_apply_batch_noalloc.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, ctypes.POINTER(BatchResult)]
     lib.gamma_apply_batch_vertices.restype = st
     lib.gamma_apply_batch_vertices.argtypes = [P, u32, P, P, P, P, u32, P, ctypes.c_int, u32,
                                                ctypes.POINTER(BatchResult)]

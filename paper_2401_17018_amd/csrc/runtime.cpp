@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -50,6 +51,51 @@ int bits_for(uint64_t x) {  // bits to hold any value < x (at least 1)
   return b;
 }
 
+// Device memory of gamma_apply_batch_noalloc: every per-batch buffer of that
+// entry point (staged inputs, canonical batch, batch hash, sort and scan
+// space, merge bookkeeping, seeds, counters, hand-over mailboxes, per-query
+// and per-update results) is carved from this array.  Each GPU the library
+// runs on holds its own copy until the process ends.  Host code never passes
+// the array's name to the device: scratch_attach() looks up its address on
+// each device once, and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES] = {};
+
+// With `dev` current: the device address of `scratch` on it (once per device).
+void scratch_attach(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    return;
+  }
+  g_scratch_ptr[dev] = p;
+  g_scratch_err[dev] = hipSuccess;
+}
+
+void* scratch_of(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+
+// Bump allocation inside the scratch array for one no-allocation call: a
+// per-batch buffer asked for again gets its earlier piece when that is
+// large enough, else a new one.
+struct NoAllocArena {
+  char* base = nullptr;
+  size_t cap = 0, top = 0;
+  std::vector<std::pair<const DevBuf*, DevBuf>> given;
+};
 
 }  // namespace
 
@@ -90,6 +136,11 @@ struct gamma_ctx {
   DevBuf mbox, mflag, idle_bits, idle_rep, seed_open, upd_open;
   DevBuf lix, lix_lab, r0_off, r0_len, permtab, qeltab;
   DevBuf vx_src, vx_dst, vx_op, vx_el, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
+  // set during gamma_apply_batch_noalloc: per-batch buffers come from the
+  // static scratch array, and nothing may be allocated
+  NoAllocArena* na = nullptr;
+  std::vector<const DevBuf*> batch_bufs;  // the per-batch buffers
+  std::vector<char> h_pageable;           // result staging when the pinned buffer is too small
   uint32_t wall_khz = 100000;
   gamma_tuning tun{};                // search tunables (never change results)
   std::vector<uint32_t> lix_labels;  // labels used by registered queries (label-index slots)
@@ -121,13 +172,47 @@ struct gamma_ctx {
                       &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &seeds_tmp, &gkeys, &gkeys_tmp, &tmp64a,
                       &tmp64b, &tmp32a, &seed_open, &upd_open};
     for (DevBuf* b : list) all.push_back(b);
+    const DevBuf* per_batch[] = {&b_src, &b_dst, &b_op, &b_el, &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp,
+                                 &keep, &ords, &canon_lo, &canon_hi, &canon_sign, &canon_a, &canon_b, &canon_e,
+                                 &hkeys, &hvals, &dkeys, &dkeys_tmp, &runvals, &runscan, &touched, &run_start,
+                                 &run_end, &sizes, &r1off, &r2_off, &r2_len, &r0_off, &r0_len, &seeds, &seeds_tmp,
+                                 &gkeys, &gkeys_tmp, &qres, &upd_res, &ctr, &tmp64a, &tmp64b, &tmp32a, &mbox,
+                                 &mflag, &idle_bits, &idle_rep, &seed_open, &upd_open};
+    for (const DevBuf* b : per_batch) batch_bufs.push_back(b);
   }
 
+  bool is_batch_buf(const DevBuf* b) const {
+    return std::find(batch_bufs.begin(), batch_bufs.end(), b) != batch_bufs.end();
+  }
+
+  void* noalloc_piece(const DevBuf& b, size_t need) {
+    for (auto& g : na->given)
+      if (g.first == &b && g.second.bytes >= need) return g.second.p;
+    const size_t at = (na->top + 255) & ~(size_t)255;
+    if (at > na->cap || need > na->cap - at)
+      throw StatusError{GAMMA_ENOMEM, "apply_batch_noalloc: the batch needs more than the " +
+                                          std::to_string(na->cap >> 20) +
+                                          " MiB of the library's no-allocation scratch"};
+    na->top = at + need;
+    DevBuf d{na->base + at, need};
+    for (auto& g : na->given)
+      if (g.first == &b) {
+        g.second = d;
+        return d.p;
+      }
+    na->given.push_back({&b, d});
+    return d.p;
+  }
 
   template <typename T>
   T* ensure(DevBuf& b, size_t count, bool keep_contents = false) {
     size_t need = count * sizeof(T);
     if (need == 0) need = sizeof(T);
+    if (na) {
+      if (is_batch_buf(&b)) return (T*)noalloc_piece(b, need);
+      if (b.bytes >= need) return (T*)b.p;
+      throw StatusError{GAMMA_ENOMEM, "apply_batch_noalloc: the context's own device storage would have to grow"};
+    }
     if (b.bytes >= need) return (T*)b.p;
     size_t alloc = std::max(need, b.bytes + b.bytes / 2);
     void* p = nullptr;
@@ -162,6 +247,11 @@ struct gamma_ctx {
   }
 
   void* pinned(size_t bytes) {
+    if (na && h_pinned_bytes < bytes) {
+      // no pinned allocation during a no-allocation call: pageable staging
+      if (h_pageable.size() < bytes) h_pageable.resize(bytes);
+      return h_pageable.data();
+    }
     if (h_pinned_bytes < bytes) {
       if (h_pinned) (void)hipHostFree(h_pinned);
       h_pinned = nullptr;
@@ -425,6 +515,7 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
       delete c;
       return GAMMA_EDEVICE;
     }
+  scratch_attach(c->device);  // the no-allocation entry point's scratch on this device
   // defaults from a sweep on the mid workload: 12 waves per CU (all of them
   // resident at the kernel's register use), few hand-over attempts per idle
   // wave (contending donors cost more than they save), a 10 us poll
@@ -778,6 +869,9 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     // ---------------------------------------------------------- delta-merge
     const uint64_t r2_total = r1_total - 2ull * n_delete;
     if (C.arena_top + r1_total + r2_total > C.arena_cap) {
+      if (C.na)
+        return fail(c, GAMMA_ENOMEM, "apply_batch_noalloc: the graph's arena is full (a gamma_apply_batch call "
+                                     "compacts it)");
       compact_arena(c, r1_total + r2_total);
       G = C.G();
     }
@@ -832,7 +926,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                        (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, 0xFFFFFFFFu,
                        C.tun.coalesced_search - 1, s);
-      if (C.tun.group_seeds == 2) {
+      if (C.tun.group_seeds == 2 && !C.na) {  // (a tunable: off in a no-allocation call)
         // update-edge grouping: a stable sort of the seeds by their first
         // data vertex (keys: position << ibr | a, ibr = ib rounded up to the
         // sort's 8-bit digits so that no digit mixes in position bits),
@@ -1086,6 +1180,28 @@ extern "C" {
 gamma_status gamma_apply_batch(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
                                const uint8_t* op, gamma_mem where, uint32_t flags, gamma_batch_result* out) {
   return gamma_apply_batch_el(c, n_upd, src, dst, op, nullptr, where, flags, out);
+}
+
+gamma_status gamma_apply_batch_noalloc(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
+                                       const uint8_t* op, gamma_mem where, uint32_t flags,
+                                       gamma_batch_result* out) {
+  if (!c) return GAMMA_EINVAL;
+  if (flags & (GAMMA_F_TUPLES | GAMMA_F_SEED_ATTR))
+    return fail(c, GAMMA_EUNSUPPORTED, "apply_batch_noalloc: counts, checksums and attribution only (no TUPLES)");
+  void* base = scratch_of(c->device);
+  if (!base) {
+    c->last_error = std::string("apply_batch_noalloc: no scratch address on this device: ") +
+                    hipGetErrorString(g_scratch_err[c->device >= 0 && c->device < NOALLOC_MAX_DEVICES ? c->device : 0]);
+    return GAMMA_EDEVICE;
+  }
+  NoAllocArena na;
+  na.base = (char*)base;
+  na.cap = NOALLOC_SCRATCH_BYTES;
+  na.given.reserve(64);
+  c->na = &na;
+  const gamma_status st = gamma_apply_batch_el(c, n_upd, src, dst, op, nullptr, where, flags, out);
+  c->na = nullptr;
+  return st;
 }
 
 gamma_status gamma_apply_batch_vertices(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, const uint32_t* dst,
