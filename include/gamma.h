@@ -70,8 +70,9 @@ typedef struct gamma_options {
   int32_t device;            /* HIP device ordinal */
   void* stream;              /* hipStream_t to run on; NULL = library-created stream */
   uint64_t tuple_capacity;   /* max tuple records stored per batch (0 = no tuple buffer) */
-  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default 12; more than the
-                                kernel's register use lets reside add nothing) */
+  uint32_t waves_per_cu;     /* persistent DFS waves per CU (0 = default: as many as stay
+                                resident with the lean search build's register use, 16 on
+                                gfx950; more than can reside add nothing) */
   uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
   uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
   uint32_t deadline_ms;      /* search deadline per batch (0 = none); past it the batch
@@ -112,10 +113,14 @@ typedef struct gamma_tuning {
                                 permuted by the core's automorphisms and the removed vertices
                                 are matched anew for each permutation; 1 = off.  Results are
                                 identical in every mode */
-  uint32_t group_seeds;   /* 2 = seeds sorted (stably) by their first data vertex before the
-                             search, so that waves starting together share rows (update-edge
-                             grouping); 1 = generation order (default).  With query_launch = 2
-                             seeds stay in generation order. */
+  uint32_t group_seeds;   /* update-edge grouping (Alg. 1's loop over update edges).  3 = seeds
+                             grouped by (query, directed query edge (x, y), data vertex a of x);
+                             a group of two or more whose level 2 has a list from a gets that
+                             list built once, filtered by the candidate table, and its seeds
+                             search level 2 from it.  2 = seeds only sorted (stably) by a, so
+                             that waves starting together share rows.  1 = generation order
+                             (default).  With query_launch = 2 seeds stay in generation order.
+                             Results are identical in every mode. */
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),
@@ -136,7 +141,8 @@ typedef struct gamma_batch_stats {
   uint32_t n_noop;         /* +e with e in E, or -e with e not in E (skipped) */
   uint32_t n_duplicate;    /* repeated updates collapsed */
   uint32_t n_touched;      /* vertices whose neighbour list changed */
-  uint32_t reserved0;
+  uint32_t n_groups;       /* update-edge grouping (group_seeds = 3): groups of seeds by
+                              (query, directed query edge, a); 0 when not grouped */
   uint64_t n_seeds;        /* (batch edge x directed query edge) pairs that pass the filter */
   uint64_t dfs_nodes;      /* partial matches extended (levels >= 2) */
   uint64_t steals;         /* successful work steals */

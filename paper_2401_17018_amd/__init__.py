@@ -319,7 +319,8 @@ class Context:
         """Set search tunables (waves_per_cu, steal 1/2, poll_cycles, split_inner,
         split_leaf, query_launch 1/2, handover_gate, coalesced_search 1 off / 2
         whole-query automorphisms / 3 also symmetric cores, group_seeds 1 generation
-        order / 2 by first data vertex);
+        order / 2 sorted by first data vertex / 3 grouped by (query, directed query
+        edge, first data vertex) with level 2's list built once per group);
         unnamed ones keep their value.  No tunable changes results."""
         t = capi.Tuning()
         for name, v in kw.items():

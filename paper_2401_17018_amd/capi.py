@@ -130,7 +130,7 @@ class BatchStats(ctypes.Structure):
         ("n_noop", ctypes.c_uint32),
         ("n_duplicate", ctypes.c_uint32),
         ("n_touched", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32),
+        ("n_groups", ctypes.c_uint32),
         ("n_seeds", ctypes.c_uint64),
         ("dfs_nodes", ctypes.c_uint64),
         ("steals", ctypes.c_uint64),

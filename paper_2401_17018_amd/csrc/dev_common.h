@@ -60,6 +60,10 @@ struct alignas(16) GmPlan {
   // (the positions pi^-1(u) over its permutations: any of them is where a
   // permuted prefix may put it).  1 << u otherwise.
   uint32_t omask[GM_MAX_K];
+  // Injectivity: a candidate of level l carries order[l]'s label, so it can
+  // only equal the data vertex of an earlier level with the same label.
+  // Bit j (j < l) set: level j's query vertex has order[l]'s label.
+  uint32_t injm[GM_MAX_K];
 };
 
 #define GM_MAX_PERM 16

@@ -135,6 +135,9 @@ GmPlan make_plan(const HostQuery& q, uint32_t qindex, uint32_t x, uint32_t y, ui
     p.back[l] = l >= 2 ? (adjm[u] & placed) : 0;
     p.bofs[l] = bofs;
     if (l >= 2) bofs += __builtin_popcount(p.back[l]);
+    p.injm[l] = 0;
+    for (uint32_t j = 0; j < l; ++j)
+      if (q.labels[p.order[j]] == q.labels[u]) p.injm[l] |= 1u << j;
     placed |= 1u << u;
   }
   p.n_core = k;

@@ -73,6 +73,12 @@ constexpr uint32_t PACK_MAX = GM_PACK_MAX;
 #define GM_POLL_STEPS 4
 #endif
 constexpr uint32_t POLL_STEPS = GM_POLL_STEPS;
+// a probed neighbour list of at most this many entries is read into the
+// wave's LDS window in one coalesced round trip and searched there
+#ifndef GM_WIN_MAX
+#define GM_WIN_MAX 256
+#endif
+constexpr uint32_t WIN_MAX = GM_WIN_MAX;
 
 // Algorithmic bytes, counted in eighths of a byte by a fixed model of what
 // the method must read, whatever this kernel's layout makes it read: per
@@ -128,6 +134,7 @@ struct WaveState {
   uint32_t ccw[GM_MAX_K];  // candidate-filter word of each core vertex's data vertex
   uint32_t pidx;
   uint32_t pvalid;  // bit p: permutation p puts every core data vertex where the filter admits it
+  uint32_t win[WIN_MAX];  // a short probed list, copied from HBM for the searches of one step
 };
 
 // Plans and query records are never written during a search: reading them
@@ -211,8 +218,7 @@ __device__ inline uint32_t lane_lb(const uint32_t* __restrict__ col, uint64_t ba
 
 // Is batch edge {a, c} usable by the seed (ord, sign)?
 __device__ inline bool visible(const GmBatchHash& H, uint32_t a, uint32_t c, uint32_t ord,
-                               uint32_t sign, uint64_t& bytes) {
-  bytes += MB_HASH_PROBE;
+                               uint32_t sign) {
   const uint64_t key = gm_edge_key(a, c);
   uint32_t slot = gm_hash_slot(key, H.mask);
   for (uint32_t p = 0; p <= H.mask; ++p) {
@@ -239,7 +245,7 @@ struct Acc {
 };
 
 __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
-  const uint64_t c = wave_sum64(A.cnt);
+  const uint64_t c = A.cnt;  // wave-uniform
   const uint64_t s = wave_sum64(A.sum);
   const uint64_t x = wave_xor64(A.xr);
   if (lane == 0 && A.key != 0xFFFFFFFFu && c) {
@@ -260,9 +266,9 @@ __device__ inline void flush_acc(const GmDfsParams& P, Acc& A, int lane) {
 __device__ inline void emit(const GmDfsParams& P, uint32_t flags, WaveState& S, Acc& A, uint32_t k, uint32_t u,
                             bool ok,
                             uint64_t m, uint32_t cx, uint64_t hpre, uint32_t q, uint32_t sign,
-                            uint32_t ord, int lane, uint64_t lt, uint64_t& bytes, uint32_t p2 = 0xFFFFFFFFu,
+                            uint32_t ord, int lane, uint64_t lt, uint64_t& ubytes, uint32_t p2 = 0xFFFFFFFFu,
                             uint32_t x2 = 0, CPerm pf = nullptr, uint32_t hu = 0xFFFFFFFFu) {
-  if (ok) A.cnt += 1;
+  A.cnt += (uint64_t)__popcll(m);  // m: the ballot of ok
   uint64_t h = 0;
   if (flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
     if (ok) {
@@ -277,6 +283,7 @@ __device__ inline void emit(const GmDfsParams& P, uint32_t flags, WaveState& S, 
     if (lane == 0) base = atomicAdd(&P.ctr->tuples_found, (unsigned long long)nok);
     base = lane_val64(base, 0);
     const uint64_t pos = base + (uint64_t)__popcll(m & lt);
+    ubytes += MB_WORD * (k + ((flags & GM_F_SEED_ATTR) ? 1u : 0u)) * (uint64_t)__popcll(__ballot(ok && pos < P.tcap));
     if (ok && pos < P.tcap) {
       uint32_t* row = P.tuples + pos * P.twidth;
       for (uint32_t j = 0; j < P.twidth; ++j) {
@@ -285,7 +292,6 @@ __device__ inline void emit(const GmDfsParams& P, uint32_t flags, WaveState& S, 
       }
       P.tmeta[pos] = (q << 1) | sign;
       if (flags & GM_F_SEED_ATTR) P.tord[pos] = ord;
-      bytes += MB_WORD * (k + ((flags & GM_F_SEED_ATTR) ? 1u : 0u));
     }
   }
   if (flags & GM_F_PER_UPDATE) {
@@ -307,13 +313,18 @@ __device__ inline void broadcast_stop(const GmDfsParams& P, int lane) {
     __hip_atomic_store(&P.mflag[s], MSG_STOP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Three waves per SIMD (12 per CU, the default launch) stay resident: the
-// register budget is held to 512 / 3 VGPRs, which this kernel meets without
-// spilling (left to itself the allocator lands just above it).
-#ifndef GM_DFS_WAVES_PER_EU
-#define GM_DFS_WAVES_PER_EU 3
+// Register budgets: the lean build is held to 512 / 4 = 128 VGPRs, so four
+// waves per SIMD (16 per CU, the default launch) stay resident, which it
+// meets without spilling; the full build, which carries every feature, to
+// 512 / 3 (three waves per SIMD).
+#ifndef GM_DFS_WAVES_PER_EU_LEAN
+#define GM_DFS_WAVES_PER_EU_LEAN 4
 #endif
-#define GM_DFS_ATTR __attribute__((amdgpu_waves_per_eu(GM_DFS_WAVES_PER_EU)))
+#ifndef GM_DFS_WAVES_PER_EU_FULL
+#define GM_DFS_WAVES_PER_EU_FULL 3
+#endif
+#define GM_DFS_ATTR \
+  __attribute__((amdgpu_waves_per_eu(FULL ? GM_DFS_WAVES_PER_EU_FULL : GM_DFS_WAVES_PER_EU_LEAN)))
 
 // Two builds of one body.  FULL = false is the lean search: no coalesced
 // plans, no edge labels, no tuple output (counts, checksums and per-update
@@ -338,8 +349,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
   const uint32_t bpx = (gridDim.x + 7) / 8;
   const uint32_t slot = ((blockIdx.x & 7) * bpx + (blockIdx.x >> 3)) * DFS_WAVES + wid;
   Acc A{0, 0, 0, 0xFFFFFFFFu};
-  uint64_t st_scan = 0, st_bytes = 0;  // per lane
-  uint64_t u_scan = 0, u_bytes = 0;    // wave-uniform (last level)
+  uint64_t u_scan = 0, u_bytes = 0;  // candidates examined and model bytes (wave-uniform)
   // per-wave tallies live in LDS (keeps scalar registers free).  The cycle
   // split (slots 0-4) is only collected in builds with GM_DFS_PROFILE=1.
   if (lane < 8) S.tally[lane] = 0;
@@ -454,6 +464,15 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 
     CPlan pl = (CPlan)P.plans + ((CQuery)P.queries)[q].plan_base + dq;
     const uint32_t k = uni(pl->k);
+    // the seed's group list (update-edge grouping), for a set-up of level 2
+    uint32_t grp_len = GM_NO_GROUP;
+    uint64_t grp_base = 0;
+    bool pre2 = false;  // level 2 drives from the group's prefiltered list
+    if (P.seed_group && base_l == 2) {
+      const GmGroupList gr = P.group_list[P.seed_group[item_seed]];
+      grp_len = uni(gr.len);
+      grp_base = uni64(gr.base);
+    }
     // coalesced search: this plan's matches stand for nperm permutations
     const uint32_t nperm = coal ? uni(pl->n_perm) : 1u;
     CPerm perm0 = (CPerm)P.perms + (coal ? uni(pl->perm_base) : 0u);
@@ -480,12 +499,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       // the seed itself is the whole match (and, coalesced, its mirror image)
       if (nperm == 1) {
         const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], 0);
-        emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes);
+        emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, u_bytes);
       } else {
         for (uint32_t pi = 0; pi < nperm; ++pi) {
           CPerm pp = perm0 + pi;
           const uint64_t hp = gm_mix64(((uint64_t)q << 1) | sign) + elem_hash(S.fx[0], uni(pp->inv[0]));
-          emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu, 0, pp,
+          emit(P, flags, S, A, 2, 1, lane == 0, 1ull, S.fx[1], hp, q, sign, ord, lane, lt, u_bytes, 0xFFFFFFFFu, 0, pp,
                uni(pp->inv[1]));
         }
       }
@@ -584,7 +603,14 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         const uint64_t li = P.lix[(uint64_t)row * P.lix_slots + (hi ? ls1 : uni(pl->lslot[l]))];
         base = off + (uint32_t)li;
         sub = (uint32_t)(li >> 32);
+        // update-edge grouping: level 2's list from a = f(x) is the
+        // group's, built once and already filtered by the candidate table
+        if (l == 2 && grp_len != GM_NO_GROUP && !hi && w == uni(pl->x)) {
+          base = grp_base;
+          sub = grp_len;
+        }
       }
+      if (l == 2) pre2 = grp_len != GM_NO_GROUP;
       // an empty list leaves no candidate (for a static list of the last
       // level: no candidate for any extension of this prefix)
       if (__ballot(act && sub == 0)) return false;
@@ -693,39 +719,47 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       const uint32_t idx = cur + (uint32_t)lane;
       bool ok = idx < len;
       uint32_t e = 0;
-      if (ok) {
-        e = col[uni64(S.drv[l]) + idx];
-        st_bytes += MB_CAND;
-        ++st_scan;
+      {
+        const uint32_t nin = (uint32_t)__popcll(__ballot(ok));
+        u_scan += nin;
+        u_bytes += MB_CAND * nin;
       }
+      if (ok) e = col[uni64(S.drv[l]) + idx];
       const uint32_t c = e & GM_IDMASK;
+      // injectivity: only earlier levels with order[l]'s label can collide
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
-      for (uint32_t j = 0; j < l; ++j) ok = ok && (c != lane_val(fo_all, j));
-      if (ok && l + 1 < k) {
+      for (uint32_t im = uni(pl->injm[l]); im; im &= im - 1) ok = ok && (c != lane_val(fo_all, __builtin_ctz(im)));
+      if (ok && l + 1 < k && !(l == 2 && pre2)) {
         // (a representative's core vertex passes for any of its positions)
         const uint32_t om = ncp > 1 ? uni(pl->omask[u]) : 1u << u;
         ok = (P.cand[(uint64_t)q * n + c] & om) != 0u;
       }
-      if (ok && (e & GM_FLAG)) ok = visible(P.H, S.drvv[l], c, ord, sign, st_bytes);
+      u_bytes += MB_HASH_PROBE * (uint64_t)__popcll(__ballot(ok && (e & GM_FLAG)));
+      if (ok && (e & GM_FLAG)) ok = visible(P.H, S.drvv[l], c, ord, sign);
       const uint32_t on = uni(S.oth_n[l]);
       const uint32_t ob = uni(pl->bofs[l]);
       for (uint32_t i = 0; i < on; ++i) {
-        if (!__ballot(ok)) break;
+        const uint64_t act = __ballot(ok);
+        if (!act) break;
+        const uint32_t olen = uni(S.oth_len[ob + i]);
+        u_bytes += MB_WORD * mb_search(olen) * (uint64_t)__popcll(act);
+        bool fl = false;
         if (ok) {
           const uint64_t base = S.oth_base[ob + i];
-          const uint32_t olen = S.oth_len[ob + i];
-          st_bytes += MB_WORD * mb_search(olen);
           const uint32_t p = lane_lb(col, base, olen, c);
           if (p >= olen) {
             ok = false;
           } else {
             const uint32_t e2 = col[base + p];
-            if ((e2 & GM_IDMASK) != c)
+            if ((e2 & GM_IDMASK) != c) {
               ok = false;
-            else if (e2 & GM_FLAG)
-              ok = visible(P.H, S.oth_v[ob + i], c, ord, sign, st_bytes);
+            } else if (e2 & GM_FLAG) {
+              fl = true;
+              ok = visible(P.H, S.oth_v[ob + i], c, ord, sign);
+            }
           }
         }
+        u_bytes += MB_HASH_PROBE * (uint64_t)__popcll(__ballot(fl));
       }
       c_out = c;
       e_idx = idx;
@@ -809,41 +843,79 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         lo[j] = 0;
         cnt[j] = ok[j] ? olen : 0u;
       }
-      for (;;) {
-        uint32_t v[LEAF_UNROLL];
-        bool any = false;
+      uint32_t e2[LEAF_UNROLL];
+      if (olen <= WIN_MAX) {
+        // a short list: all of it into the wave's LDS window (every load
+        // issued before any store, so one memory round trip), then the
+        // lower-bound searches run on LDS
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
-          // clamped so a finished search still reads inside the list (olen >= 1)
-          const uint32_t at = lo[j] + (cnt[j] >> 1);
-          v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
+        for (uint32_t r = 0; r < WIN_MAX / GM_WAVE; ++r) {
+          const uint32_t i = r * GM_WAVE + (uint32_t)lane;
+          if (i < olen) S.win[i] = col[base + i];
         }
-        CNT(1, LEAF_UNROLL);
+        for (;;) {
+          bool any = false;
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
-          if (cnt[j]) {
-            any = true;
-            const uint32_t half = cnt[j] >> 1;
-            if (v[j] < (e[j] & GM_IDMASK)) {
-              lo[j] += half + 1;
-              cnt[j] -= half + 1;
-            } else {
-              cnt[j] = half;
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            if (cnt[j]) {
+              any = true;
+              const uint32_t half = cnt[j] >> 1;
+              if ((S.win[lo[j] + half] & GM_IDMASK) < (e[j] & GM_IDMASK)) {
+                lo[j] += half + 1;
+                cnt[j] -= half + 1;
+              } else {
+                cnt[j] = half;
+              }
             }
           }
+          if (!__ballot(any)) break;
         }
-        if (!__ballot(any)) break;
-      }
-      uint32_t e2[LEAF_UNROLL];
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) {
-        const bool in = lo[j] < olen;
-        e2[j] = col[base + (in ? lo[j] : olen - 1)];
-        if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const bool in = lo[j] < olen;
+          e2[j] = S.win[in ? lo[j] : olen - 1];
+          if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
+        }
+      } else {
+        for (;;) {
+          uint32_t v[LEAF_UNROLL];
+          bool any = false;
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            // clamped so a finished search still reads inside the list (olen >= 1)
+            const uint32_t at = lo[j] + (cnt[j] >> 1);
+            v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
+          }
+          CNT(1, LEAF_UNROLL);
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) {
+            if (cnt[j]) {
+              any = true;
+              const uint32_t half = cnt[j] >> 1;
+              if (v[j] < (e[j] & GM_IDMASK)) {
+                lo[j] += half + 1;
+                cnt[j] -= half + 1;
+              } else {
+                cnt[j] = half;
+              }
+            }
+          }
+          if (!__ballot(any)) break;
+        }
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          const bool in = lo[j] < olen;
+          e2[j] = col[base + (in ? lo[j] : olen - 1)];
+          if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
+        }
       }
+      uint32_t nfl = 0;
+#pragma unroll
+      for (int j = 0; j < LEAF_UNROLL; ++j) nfl += (uint32_t)__popcll(__ballot(ok[j] && (e2[j] & GM_FLAG)));
+      u_bytes += MB_HASH_PROBE * nfl;
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j)
-        if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+        if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign);
     };
 
     // ---- last level: LEAF_UNROLL chunks per step.  Ids and external ids are
@@ -886,15 +958,21 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       CNT(0, 1);
       CNT(3, n_in);
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
-      for (uint32_t jj = 0; jj < l; ++jj) {
-        const uint32_t fv = lane_val(fo_all, jj);
+      for (uint32_t im = uni(pl->injm[l]); im; im &= im - 1) {
+        const uint32_t fv = lane_val(fo_all, __builtin_ctz(im));
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
       }
       const uint32_t fdrv = uni(S.drvv[l]);
+      {
+        uint32_t nfl = 0;
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) nfl += (uint32_t)__popcll(__ballot(ok[j] && (e[j] & GM_FLAG)));
+        u_bytes += MB_HASH_PROBE * nfl;
+      }
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j)
-        if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, fdrv, e[j] & GM_IDMASK, ord, sign, st_bytes);
+        if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, fdrv, e[j] & GM_IDMASK, ord, sign);
       for (uint32_t i = 0; i < on; ++i) {
         bool anyok = false;
 #pragma unroll
@@ -907,7 +985,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) {
           const uint64_t m = __ballot(ok[j]);
-          if (m) emit(P, flags, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, st_bytes);
+          if (m) emit(P, flags, S, A, k, u, ok[j], m, x[j], hpre, q, sign, ord, lane, lt, u_bytes);
         }
       } else {
         // coalesced plan: every match found stands for nperm permuted ones
@@ -917,7 +995,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           if (m)
             for (uint32_t pi = 0; pi < nperm; ++pi) {
               CPerm pp = perm0 + pi;
-              emit(P, flags, S, A, k, u, ok[j], m, x[j], uni64(S.hpp[pi]), q, sign, ord, lane, lt, st_bytes, 0xFFFFFFFFu,
+              emit(P, flags, S, A, k, u, ok[j], m, x[j], uni64(S.hpp[pi]), q, sign, ord, lane, lt, u_bytes, 0xFFFFFFFFu,
                    0, pp, uni(pp->inv[u]));
             }
         }
@@ -1029,16 +1107,22 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         u_bytes += (uint64_t)n_in * MB_CAND;
         CNT(0, 1);
         CNT(3, n_in);
-        // injectivity against order[0 .. k-3] (a neighbour of the survivor
-        // is never the survivor itself)
-        for (uint32_t jj = 0; jj < l; ++jj) {
-          const uint32_t fv = lane_val(fo_all, jj);
+        // injectivity against order[0 .. k-3] with the last vertex's label
+        // (a neighbour of the survivor is never the survivor itself)
+        for (uint32_t im = uni(pl->injm[lf]) & ((1u << l) - 1u); im; im &= im - 1) {
+          const uint32_t fv = lane_val(fo_all, __builtin_ctz(im));
 #pragma unroll
           for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
         }
+        {
+          uint32_t nfl = 0;
+#pragma unroll
+          for (int j = 0; j < LEAF_UNROLL; ++j) nfl += (uint32_t)__popcll(__ballot(ok[j] && (e[j] & GM_FLAG)));
+          u_bytes += MB_HASH_PROBE * nfl;
+        }
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j)
-          if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, cs[j], e[j] & GM_IDMASK, ord, sign, st_bytes);
+          if (ok[j] && (e[j] & GM_FLAG)) ok[j] = visible(P.H, cs[j], e[j] & GM_IDMASK, ord, sign);
         for (uint32_t i = 0; i < nb1; ++i) {
           bool anyok = false;
 #pragma unroll
@@ -1052,7 +1136,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           if (mm) {
             const uint64_t hpre = st_h + S.pf_h[sl[j]];
             const uint32_t x2 = (flags & GM_F_TUPLES) ? S.pf_x[sl[j]] : 0u;
-            emit(P, flags, S, A, k, u, ok[j], mm, x[j], hpre, q, sign, ord, lane, lt, st_bytes, u2, x2);
+            emit(P, flags, S, A, k, u, ok[j], mm, x[j], hpre, q, sign, ord, lane, lt, u_bytes, u2, x2);
           }
         }
       }
@@ -1269,7 +1353,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #undef TALLY
 #undef TALLY_ALWAYS
 #undef CYCLES
-  const uint64_t ss = wave_sum64(st_scan) + u_scan, sb = wave_sum64(st_bytes) + u_bytes;
+  const uint64_t ss = u_scan, sb = u_bytes;
   if (lane < 6) atomicAdd(&P.ctr->cyc[lane], (unsigned long long)S.tally[lane]);
   if (lane == 0) {
     atomicAdd(&P.ctr->steals, (unsigned long long)S.tally[6]);
@@ -1291,6 +1375,17 @@ __global__ void k_upd_open(const GmSeed* __restrict__ seeds, const GmCounters* _
 namespace gm {
 
 unsigned dfs_block_threads() { return DFS_THREADS; }
+// Waves per CU that stay resident with the lean build's register use (the
+// default launch width); 12 if the runtime cannot tell.
+unsigned dfs_resident_waves_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_dfs<false>, DFS_THREADS, 0) != hipSuccess ||
+      blocks <= 0) {
+    (void)hipGetLastError();
+    return 12;
+  }
+  return (unsigned)blocks * DFS_WAVES;
+}
 unsigned dfs_waves_per_block() { return DFS_WAVES; }
 uint32_t dfs_slots(unsigned blocks) { return 8u * ((blocks + 7) / 8) * DFS_WAVES; }
 

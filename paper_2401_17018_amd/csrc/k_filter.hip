@@ -153,6 +153,120 @@ __global__ void k_seed_gather(const GmSeed* __restrict__ in, const uint64_t* __r
     out[i] = in[keys[i] >> ib];
 }
 
+// ---- update-edge grouping (Alg. 1's loop over update edges: seeds that map
+// the same directed query edge (x, y) with x onto the same data vertex a
+// share every candidate of level 2 that comes from a's row)
+
+__global__ void k_group_keys(const GmSeed* __restrict__ seeds, uint64_t n, int ib, int pb,
+                             uint64_t* __restrict__ keys) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    keys[i] = ((uint64_t)(seeds[i].qd & 0xFFFFu) << (ib + pb)) | ((uint64_t)seeds[i].a << pb) | i;
+}
+
+__global__ void k_group_lead(const uint64_t* __restrict__ keys, uint64_t n, int pb, uint32_t* __restrict__ lead) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    lead[i] = (i == 0 || (keys[i] >> pb) != (keys[i - 1] >> pb)) ? 1u : 0u;
+}
+
+// the arena range of a's label subrange for the level-2 vertex, or len 0
+// when level 2 has no list from a
+__device__ inline uint32_t group_range(const GmSeed& sd, const GmPlan& P, GmGraphDev G,
+                                       const unsigned long long* lix, uint32_t lix_slots, const uint8_t* qel,
+                                       uint32_t q, uint64_t& base) {
+  if (P.k < 3 || !((P.back[2] >> P.x) & 1u)) return 0u;
+  uint32_t row = sd.a;
+  if (G.elb) row = (row << G.elb) | qel[(q * GM_MAX_K + P.order[2]) * GM_MAX_K + P.x];
+  const unsigned long long li = lix[(uint64_t)row * lix_slots + P.lslot[2]];
+  base = G.row_off[row] + (uint32_t)li;
+  return (uint32_t)(li >> 32);
+}
+
+__global__ void k_group_gather(const GmSeed* __restrict__ in, const uint64_t* __restrict__ keys, uint64_t n, int pb,
+                               GmSeed* __restrict__ out) {
+  const uint64_t pm = (1ull << pb) - 1ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = in[keys[i] & pm];
+}
+
+// group of seed i: excl[i] (leaders before i) + lead[i] - 1
+__global__ void k_group_assign(const uint32_t* __restrict__ excl, const uint32_t* __restrict__ lead, uint64_t n,
+                               uint32_t* __restrict__ seed_group) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    seed_group[i] = excl[i] + lead[i] - 1u;
+}
+
+__global__ void k_group_len(const GmSeed* __restrict__ seeds, const uint32_t* __restrict__ excl,
+                            const uint32_t* __restrict__ lead, uint64_t n,
+                            const GmPlan* __restrict__ plans, const GmQueryDev* __restrict__ qs, GmGraphDev G,
+                            const unsigned long long* __restrict__ lix, uint32_t lix_slots,
+                            const uint8_t* __restrict__ qel, unsigned long long* __restrict__ glen) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    if (!lead[i]) continue;
+    const uint32_t g = excl[i];
+    const bool pair = i + 1 < n && !lead[i + 1];
+    uint64_t len = 0;
+    if (pair) {
+      const GmSeed sd = seeds[i];
+      const uint32_t q = sd.qd >> 8;
+      const GmPlan& P = plans[qs[q].plan_base + (sd.qd & 255u)];
+      uint64_t base = 0;
+      len = group_range(sd, P, G, lix, lix_slots, qel, q, base);
+    }
+    glen[g] = len;
+  }
+}
+
+// one wave per group: its list, compacted in the order of a's row
+__global__ void k_group_fill(const GmSeed* __restrict__ seeds, const uint32_t* __restrict__ excl,
+                             const uint32_t* __restrict__ lead, uint64_t n, const GmPlan* __restrict__ plans,
+                             const GmQueryDev* __restrict__ qs, GmGraphDev G,
+                             const unsigned long long* __restrict__ lix, uint32_t lix_slots,
+                             const uint8_t* __restrict__ qel, const uint16_t* __restrict__ cand, uint32_t coalesce,
+                             const unsigned long long* __restrict__ glen, const unsigned long long* __restrict__ goff,
+                             uint64_t dst0, GmGroupList* __restrict__ lists) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint64_t i = wave; i < n; i += nwaves) {
+    if (!lead[i]) continue;
+    const uint32_t g = excl[i];
+    GmGroupList rec;
+    rec.base = dst0 + goff[g];
+    rec.len = GM_NO_GROUP;
+    rec.pad = 0;
+    if (glen[g]) {
+      const GmSeed sd = seeds[i];
+      const uint32_t q = sd.qd >> 8;
+      const GmPlan& P = plans[qs[q].plan_base + (sd.qd & 255u)];
+      uint64_t base = 0;
+      const uint32_t len = group_range(sd, P, G, lix, lix_slots, qel, q, base);
+      const uint32_t u2 = P.order[2];
+      const uint32_t om = (coalesce >= 2 && P.n_cperm >= 2) ? P.omask[u2] : (1u << u2);
+      uint32_t out = 0;
+      for (uint32_t c0 = 0; c0 < len; c0 += 64) {
+        const uint32_t idx = c0 + (uint32_t)lane;
+        bool keep = false;
+        uint32_t e = 0, x = 0;
+        if (idx < len) {
+          e = G.col[base + idx];
+          x = G.ext[base + idx];
+          keep = (cand[(uint64_t)q * G.n + (e & GM_IDMASK)] & om) != 0u;
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+          const uint64_t at = rec.base + out + (uint64_t)__popcll(m & lt);
+          G.col[at] = e;
+          G.ext[at] = x;
+        }
+        out += (uint32_t)__popcll(m);
+      }
+      rec.len = out;
+    }
+    if (lane == 0) lists[g] = rec;
+  }
+}
+
 // The search starts with one unfinished work item per seed of its window.
 __global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds - ctr->seed_begin; }
 
@@ -193,6 +307,39 @@ void launch_seed_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int 
   k_seed_gather<<<grid_for(n, 256), 256, 0, s>>>(in, keys, n, ib, out);
 }
 void launch_seed_window(GmCounters* ctr, hipStream_t s) { k_seed_window<<<1, 1, 0, s>>>(ctr); }
+
+void launch_group_keys(const GmSeed* seeds, uint64_t n, int ib, int pb, uint64_t* keys, hipStream_t s) {
+  if (!n) return;
+  k_group_keys<<<grid_for(n, 256), 256, 0, s>>>(seeds, n, ib, pb, keys);
+}
+void launch_group_lead(const uint64_t* keys, uint64_t n, int pb, uint32_t* lead, hipStream_t s) {
+  if (!n) return;
+  k_group_lead<<<grid_for(n, 256), 256, 0, s>>>(keys, n, pb, lead);
+}
+void launch_group_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int pb, GmSeed* out, hipStream_t s) {
+  if (!n) return;
+  k_group_gather<<<grid_for(n, 256), 256, 0, s>>>(in, keys, n, pb, out);
+}
+void launch_group_assign(const uint32_t* excl, const uint32_t* lead, uint64_t n, uint32_t* seed_group,
+                         hipStream_t s) {
+  if (!n) return;
+  k_group_assign<<<grid_for(n, 256), 256, 0, s>>>(excl, lead, n, seed_group);
+}
+void launch_group_len(const GmSeed* seeds, const uint32_t* excl, const uint32_t* lead, uint64_t n,
+                      const GmPlan* plans, const GmQueryDev* qs, GmGraphDev G, const unsigned long long* lix,
+                      uint32_t lix_slots, const uint8_t* qel, unsigned long long* glen, hipStream_t s) {
+  if (!n) return;
+  k_group_len<<<grid_for(n, 256), 256, 0, s>>>(seeds, excl, lead, n, plans, qs, G, lix, lix_slots, qel, glen);
+}
+void launch_group_fill(const GmSeed* seeds, const uint32_t* excl, const uint32_t* lead, uint64_t n,
+                       const GmPlan* plans, const GmQueryDev* qs, GmGraphDev G, const unsigned long long* lix,
+                       uint32_t lix_slots, const uint8_t* qel, const uint16_t* cand, uint32_t coalesce,
+                       const unsigned long long* glen, const unsigned long long* goff, uint64_t dst0,
+                       GmGroupList* lists, hipStream_t s) {
+  if (!n) return;
+  k_group_fill<<<grid_for(n * 64, 256), 256, 0, s>>>(seeds, excl, lead, n, plans, qs, G, lix, lix_slots, qel, cand,
+                                                     coalesce, glen, goff, dst0, lists);
+}
 
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
                         uint32_t n_slots, unsigned long long* lix, hipStream_t s) {

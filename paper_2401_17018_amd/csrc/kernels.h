@@ -53,6 +53,13 @@ struct GmCounters {
   unsigned long long t_start;     // device wall clock when the batch's search began (deadline origin)
 };
 
+constexpr uint32_t GM_NO_GROUP = 0xFFFFFFFFu;
+struct GmGroupList {
+  unsigned long long base;  // arena index of the list's first entry
+  uint32_t len;             // entries (GM_NO_GROUP: none)
+  uint32_t pad;
+};
+
 struct GmDfsParams {
   GmGraphDev G;
   const unsigned long long* lix;  // [rows][lix_slots]: label subrange of each row, start | len << 32
@@ -92,6 +99,12 @@ struct GmDfsParams {
   // per hand-over of its work); 0xFFFFFFFF = not started.  NULL: untracked.
   // A seed at 0 when the search ends (also past a deadline) is complete.
   uint32_t* seed_open;
+  // Update-edge grouping (seeds sharing query, directed query edge and
+  // first data vertex a): per seed its group, per group the arena range of
+  // a's level-2 candidates, already filtered by the candidate table (len
+  // GM_NO_GROUP: level 2 is set up as usual).  NULL: no grouping.
+  const uint32_t* seed_group;
+  const GmGroupList* group_list;
 };
 
 namespace gm {
@@ -189,6 +202,29 @@ void launch_seed_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int 
 // opens the seed window of the next search launch: seed_begin = seed_head =
 // n_seeds; sets the deadline origin on the first call of a batch
 void launch_seed_window(GmCounters* ctr, hipStream_t s);
+// Update-edge grouping by (query, directed query edge, a).  keys: qd << (ib +
+// pb) | a << pb | position (sorted by the caller over 16 + ib + pb bits);
+// gather as for the sort by a (low pb bits = position).
+void launch_group_keys(const GmSeed* seeds, uint64_t n, int ib, int pb, uint64_t* keys, hipStream_t s);
+void launch_group_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int pb, GmSeed* out, hipStream_t s);
+// after the gather: lead[i] = 1 when seed i starts a group; excl = the
+// exclusive scan of lead (a leader's group index)
+void launch_group_lead(const uint64_t* keys, uint64_t n, int pb, uint32_t* lead, hipStream_t s);
+void launch_group_assign(const uint32_t* excl, const uint32_t* lead, uint64_t n, uint32_t* seed_group,
+                         hipStream_t s);
+// per group: the length of a's level-2 subrange when the group has >= 2
+// seeds and a is a back-neighbour of the plan's level 2, else 0
+void launch_group_len(const GmSeed* seeds, const uint32_t* excl, const uint32_t* lead, uint64_t n,
+                      const GmPlan* plans, const GmQueryDev* qs, GmGraphDev G, const unsigned long long* lix,
+                      uint32_t lix_slots, const uint8_t* qel, unsigned long long* glen, hipStream_t s);
+// per group with a length: its candidates written from arena index dst0 +
+// goff[g] on (col and ext), those that pass the candidate table for the
+// level-2 vertex (any position of its mask); the list records
+void launch_group_fill(const GmSeed* seeds, const uint32_t* excl, const uint32_t* lead, uint64_t n,
+                       const GmPlan* plans, const GmQueryDev* qs, GmGraphDev G, const unsigned long long* lix,
+                       uint32_t lix_slots, const uint8_t* qel, const uint16_t* cand, uint32_t coalesce,
+                       const unsigned long long* glen, const unsigned long long* goff, uint64_t dst0,
+                       GmGroupList* lists, hipStream_t s);
 // label index: for rows `verts` (or all rows), the subrange of each indexed label
 void launch_label_index(GmGraphDev G, const uint32_t* verts, uint32_t nv, const uint32_t* slot_labels,
                         uint32_t n_slots, unsigned long long* lix, hipStream_t s);
@@ -205,6 +241,7 @@ void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);
 void launch_upd_open(const GmSeed* seeds, const GmCounters* ctr, uint64_t seed_cap, const uint32_t* seed_open,
                      uint8_t* upd_open, hipStream_t s);
 unsigned dfs_block_threads();
+unsigned dfs_resident_waves_per_cu();
 unsigned dfs_waves_per_block();
 // mailbox slots needed for a grid of `blocks` search blocks
 uint32_t dfs_slots(unsigned blocks);

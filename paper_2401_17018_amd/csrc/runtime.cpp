@@ -134,6 +134,7 @@ struct gamma_ctx {
   DevBuf seeds, qres, upd_res, tuples, tmeta, tord, ctr, seeds_tmp, gkeys, gkeys_tmp;
   DevBuf tmp64a, tmp64b, tmp32a;
   DevBuf mbox, mflag, idle_bits, idle_rep, seed_open, upd_open;
+  DevBuf grp_lead, grp_excl, grp_len, grp_off, grp_lists, seed_grp;  // update-edge grouping
   DevBuf lix, lix_lab, r0_off, r0_len, permtab, qeltab;
   DevBuf vx_src, vx_dst, vx_op, vx_el, vx_del, vx_len, vx_off, vx_mark;  // vertex deletions expanded to edges
   // set during gamma_apply_batch_noalloc: per-batch buffers come from the
@@ -170,7 +171,8 @@ struct gamma_ctx {
                       &canon_hi, &canon_sign, &canon_a, &canon_b, &hkeys, &hvals, &dkeys, &dkeys_tmp,
                       &runvals, &runscan, &touched, &run_start, &run_end, &sizes, &r1off, &r2_off,
                       &r2_len, &seeds, &qres, &upd_res, &tuples, &tmeta, &tord, &ctr, &seeds_tmp, &gkeys, &gkeys_tmp, &tmp64a,
-                      &tmp64b, &tmp32a, &seed_open, &upd_open};
+                      &tmp64b, &tmp32a, &seed_open, &upd_open, &grp_lead, &grp_excl, &grp_len, &grp_off,
+                      &grp_lists, &seed_grp};
     for (DevBuf* b : list) all.push_back(b);
     const DevBuf* per_batch[] = {&b_src, &b_dst, &b_op, &b_el, &keys, &keys_tmp, &hist, &hist_scan, &scan_tmp,
                                  &keep, &ords, &canon_lo, &canon_hi, &canon_sign, &canon_a, &canon_b, &canon_e,
@@ -516,10 +518,12 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
       return GAMMA_EDEVICE;
     }
   scratch_attach(c->device);  // the no-allocation entry point's scratch on this device
-  // defaults from a sweep on the mid workload: 12 waves per CU (all of them
-  // resident at the kernel's register use), few hand-over attempts per idle
-  // wave (contending donors cost more than they save), a 10 us poll
-  c->tun.waves_per_cu = c->opt.waves_per_cu ? std::min<uint32_t>(c->opt.waves_per_cu, 32) : 12;
+  // defaults: as many waves per CU as stay resident with the search
+  // kernel's register use (16 for the lean build), few hand-over attempts
+  // per idle wave (contending donors cost more than they save, measured on
+  // the mid workload), a 10 us poll
+  c->tun.waves_per_cu = c->opt.waves_per_cu ? std::min<uint32_t>(c->opt.waves_per_cu, 32)
+                                            : std::min<uint32_t>(gm::dfs_resident_waves_per_cu(), 32);
   c->tun.steal = (c->opt.steal_set && !c->opt.steal) ? 2 : 1;
   c->tun.poll_cycles = 24000;  // ~10 us at 2.4 GHz
   c->tun.split_inner = 128;
@@ -921,6 +925,9 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     // (one launch per query: each query's seeds are generated right before
     // its own search launch, so that time falls in the search phase)
     const bool per_query = C.tun.query_launch == 2 && nq > 1;
+    const uint32_t* grp_seed = nullptr;  // update-edge grouping, when built
+    const GmGroupList* grp_lists = nullptr;
+    uint32_t n_groups = 0;
     gm::launch_seed_window(ctr, s);
     if (nq && !per_query) {
       gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
@@ -946,6 +953,58 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
           chk(hipMemcpyAsync(sd, so, ns * sizeof(GmSeed), hipMemcpyDeviceToDevice, s), "copy");
         }
       }
+      if (C.tun.group_seeds == 3 && !C.na) {
+        // update-edge grouping (Alg. 1 runs its loop over update edges; seeds
+        // that map the same directed query edge (x, y) with x onto the same
+        // data vertex a share a's candidates for level 2): the seeds are
+        // sorted by (query, directed query edge, a), and every group of two
+        // or more whose level 2 has a list from a gets that list built once,
+        // filtered by the candidate table, in arena space past the batch's
+        // rows; its seeds then drive level 2 from it.  Skipped when the
+        // arena lacks the room (a tunable: results are the same either way).
+        unsigned long long hn = 0;
+        chk(hipMemcpyAsync(&hn, &ctr->n_seeds, 8, hipMemcpyDeviceToHost, s), "d2h");
+        chk(hipStreamSynchronize(s), "sync");
+        const uint64_t ns = std::min<uint64_t>(hn, seed_cap);
+        const int pb = bits_for(ns);
+        if (ns > 1 && 16 + ib + pb <= 64) {
+          uint64_t* gk = C.ensure<uint64_t>(C.gkeys, ns);
+          uint64_t* gt = C.ensure<uint64_t>(C.gkeys_tmp, ns);
+          GmSeed* so = C.ensure<GmSeed>(C.seeds_tmp, ns);
+          gm::launch_group_keys(sd, ns, ib, pb, gk, s);
+          C.sort_keys(gk, gt, ns, 16 + ib + pb);
+          gm::launch_group_gather(sd, gk, ns, pb, so, s);
+          chk(hipMemcpyAsync(sd, so, ns * sizeof(GmSeed), hipMemcpyDeviceToDevice, s), "copy");
+          uint32_t* lead = C.ensure<uint32_t>(C.grp_lead, ns);
+          uint32_t* excl = C.ensure<uint32_t>(C.grp_excl, ns + 1);
+          gm::launch_group_lead(gk, ns, pb, lead, s);
+          C.scan32(lead, excl, ns);
+          uint32_t ng = 0;
+          chk(hipMemcpyAsync(&ng, excl + ns, 4, hipMemcpyDeviceToHost, s), "d2h");
+          chk(hipStreamSynchronize(s), "sync");
+          unsigned long long* glen = (unsigned long long*)C.ensure<uint64_t>(C.grp_len, std::max<uint32_t>(ng, 1));
+          unsigned long long* goff = (unsigned long long*)C.ensure<uint64_t>(C.grp_off, (size_t)ng + 1);
+          gm::launch_group_len(sd, excl, lead, ns, (const GmPlan*)C.plans.p, (const GmQueryDev*)C.qdev.p, G,
+                               (const unsigned long long*)C.lix.p, (uint32_t)C.lix_labels.size(),
+                               (const uint8_t*)C.qeltab.p, glen, s);
+          C.scan64((const uint64_t*)glen, (uint64_t*)goff, ng);
+          uint64_t gtotal = 0;
+          chk(hipMemcpyAsync(&gtotal, goff + ng, 8, hipMemcpyDeviceToHost, s), "d2h");
+          chk(hipStreamSynchronize(s), "sync");
+          if (C.arena_top + gtotal <= C.arena_cap) {
+            GmGroupList* lists = C.ensure<GmGroupList>(C.grp_lists, std::max<uint32_t>(ng, 1));
+            uint32_t* sg = C.ensure<uint32_t>(C.seed_grp, ns);
+            gm::launch_group_fill(sd, excl, lead, ns, (const GmPlan*)C.plans.p, (const GmQueryDev*)C.qdev.p, G,
+                                  (const unsigned long long*)C.lix.p, (uint32_t)C.lix_labels.size(),
+                                  (const uint8_t*)C.qeltab.p, (const uint16_t*)C.cand.p,
+                                  C.tun.coalesced_search - 1, glen, goff, C.arena_top, lists, s);
+            gm::launch_group_assign(excl, lead, ns, sg, s);
+            grp_seed = sg;
+            grp_lists = lists;
+            n_groups = ng;
+          }
+        }
+      }
     }
     chk(hipEventRecord(C.ev[4], s), "event");
 
@@ -962,7 +1021,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       if (flags & GAMMA_F_SEED_ATTR) C.ensure<uint32_t>(C.tord, tcap);
     }
     if (nq && n_canon) {
-      GmDfsParams P;
+      GmDfsParams P{};  // every field defined (pointers the kernel tests stay null unless set)
       P.G = G;
       P.lix = (const unsigned long long*)C.lix.p;
       P.lix_slots = (uint32_t)C.lix_labels.size();
@@ -1001,6 +1060,8 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.coalesce = permutes ? coal : 0u;
       P.qel = (const uint8_t*)C.qeltab.p;
       P.seed_open = sopen;
+      P.seed_group = grp_seed;
+      P.group_list = grp_lists;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
           if (qi) gm::launch_seed_window(ctr, s);
@@ -1120,6 +1181,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     st.n_noop = hc.n_noop;
     st.n_duplicate = hc.n_dup;
     st.n_touched = n_touched;
+    st.n_groups = n_groups;
     st.n_seeds = h_ctr->n_seeds;
     st.dfs_nodes = h_ctr->dfs_nodes;
     st.steals = h_ctr->steals;
@@ -1314,7 +1376,7 @@ bool tuning_ok(const gamma_tuning& t) {
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
          (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
-         t.coalesced_search >= 1 && t.coalesced_search <= 3 && (t.group_seeds == 1 || t.group_seeds == 2);
+         t.coalesced_search >= 1 && t.coalesced_search <= 3 && t.group_seeds >= 1 && t.group_seeds <= 3;
 }
 }  // namespace
 
@@ -1401,10 +1463,10 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
         }
       }
     };
-    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1, 3}, gs_v[] = {1, 2};
+    const uint32_t ql_v[] = {1, 2}, steal_v[] = {1, 2}, cs_v[] = {2, 1, 3}, gs_v[] = {1, 2, 3};
     if (many_q) sweep(&gamma_tuning::query_launch, ql_v, 2);
     sweep(&gamma_tuning::coalesced_search, cs_v, 3);
-    if (cur.query_launch == 1) sweep(&gamma_tuning::group_seeds, gs_v, 2);
+    if (cur.query_launch == 1) sweep(&gamma_tuning::group_seeds, gs_v, 3);
     sweep(&gamma_tuning::steal, steal_v, 2);
     sweep(&gamma_tuning::waves_per_cu, wpc_v, 5);
     if (cur.steal == 1) {

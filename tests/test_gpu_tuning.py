@@ -77,7 +77,10 @@ def test_per_query_launches_identical():
 
 TUNINGS = [
     dict(waves_per_cu=4, steal=1, poll_cycles=500, split_inner=2, split_leaf=2, handover_gate=1024),  # hand over almost anything
-    dict(waves_per_cu=8, steal=1, group_seeds=2),  # seeds grouped by their first data vertex
+    dict(waves_per_cu=8, steal=1, group_seeds=2),  # seeds sorted by their first data vertex
+    dict(waves_per_cu=8, steal=1, group_seeds=3),  # grouped by (query, edge, a), shared level-2 lists
+    dict(waves_per_cu=4, steal=1, poll_cycles=500, split_inner=2, split_leaf=2, handover_gate=1024,
+         group_seeds=3),  # ... with level-2 ranges of group lists handed over
     dict(waves_per_cu=32, steal=1, poll_cycles=1000000, split_inner=1 << 20, split_leaf=1 << 20),
     dict(waves_per_cu=12, steal=2),
     dict(waves_per_cu=1, steal=1, poll_cycles=3000, handover_gate=1),
@@ -99,7 +102,8 @@ def test_tunables_do_not_change_results(seed):
             outs.append(ctx.apply_batch(b.src, b.dst, b.op, per_update=True, tuples=True, dry_run=True))
     for o in outs[1:]:
         _same(outs[0], o)
-    assert outs[0].stats["steals"] > 0 and outs[3].stats["steals"] == 0
+    assert outs[0].stats["steals"] > 0 and outs[5].stats["steals"] == 0
+    assert 0 < outs[2].stats["n_groups"] < outs[2].stats["n_seeds"]
     check_against_o2(outs[0], g, q, b, check_tuples=not outs[0].truncated)
 
 
@@ -107,7 +111,7 @@ def test_set_tuning_rejects_out_of_range():
     with make_ctx(cap=0) as ctx:
         before = ctx.get_tuning()
         for bad in (dict(split_inner=1), dict(waves_per_cu=33), dict(steal=3), dict(query_launch=7),
-                    dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=3)):
+                    dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=4)):
             with pytest.raises(GammaError) as ei:
                 ctx.set_tuning(**bad)
             assert ei.value.status == capi.GAMMA_EINVAL
@@ -156,3 +160,66 @@ def test_deadline_with_per_query_launches():
         assert ei.value.status == capi.GAMMA_ETIMEDOUT
         erp, ecol, _ = ctx.export_graph()
         assert np.array_equal(erp, g.row_ptr) and np.array_equal(ecol, g.col)
+
+
+def _hub_batch(g, hubs, per_hub, seed):
+    """Insertions of absent edges at a few hub vertices (many seeds share a
+    first data vertex), plus deletions at the same hubs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    E = set(g.edge_keys().tolist())
+    ups = []
+    for h in hubs:
+        others = rng.permutation(g.n)
+        n_ins = 0
+        for v in others.tolist():
+            if v == h:
+                continue
+            key = (min(h, v) << 32) | max(h, v)
+            if key not in E and n_ins < per_hub:
+                ups.append(("+", h, v))
+                n_ins += 1
+        row = g.neighbors(h)[: per_hub // 3]
+        ups += [("-", h, int(v)) for v in row.tolist()]
+    keys = set()
+    out = []
+    for op, a, b in ups:
+        k = (min(a, b), max(a, b))
+        if k not in keys:
+            keys.add(k)
+            out.append((op, a, b))
+    return W.batch_from_list(out)
+
+
+@pytest.mark.parametrize("qname", ["triangle", "path", "diamond"])
+def test_update_edge_grouping_shares_level_two(qname):
+    """Grouping by (query, directed query edge, a) with level 2's list built
+    once per group (group_seeds = 3): batches whose updates share hub
+    endpoints form groups; counts, checksums, per-update attribution and
+    tuples equal the ungrouped search and the oracle, in the lean build
+    (attribution only) and the full one (tuples), with hand-over forced."""
+    g = _skewed_graph(7)
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    hubs = np.argsort(-deg)[:4].tolist()
+    b = _hub_batch(g, hubs, 60, 3)
+    q = {"triangle": W.query_from_edges(3, [(0, 1), (1, 2), (0, 2)], (0, 0, 0)),
+         "path": W.query_from_edges(4, [(0, 1), (1, 2), (2, 3)], (0, 0, 0, 0)),
+         "diamond": W.query_from_edges(4, [(0, 1), (1, 2), (2, 3), (0, 3), (0, 2)], (0, 0, 0, 0))}[qname]
+    with make_ctx(cap=1 << 22) as ctx:
+        ctx.load_graph(g.row_ptr, g.col, g.labels)
+        ctx.register_query(q.k, q.labels, q.edges)
+        res = {}
+        for name, t in [("plain", dict(group_seeds=1)), ("grouped", dict(group_seeds=3)),
+                        ("grouped_handover", dict(group_seeds=3, poll_cycles=500, split_inner=2, split_leaf=2,
+                                                  handover_gate=1024, waves_per_cu=4))]:
+            ctx.set_tuning(**t)
+            lean = ctx.apply_batch(b.src, b.dst, b.op, per_update=True, dry_run=True)
+            full = ctx.apply_batch(b.src, b.dst, b.op, per_update=True, tuples=True, dry_run=True)
+            res[name] = (lean, full)
+    plain_lean, plain_full = res["plain"]
+    for name in ("grouped", "grouped_handover"):
+        lean, full = res[name]
+        assert 0 < lean.stats["n_groups"] < lean.stats["n_seeds"], lean.stats
+        _same(plain_lean, lean)
+        _same(plain_full, full)
+    assert int(plain_lean.counts.sum()) > 0
+    check_against_o2(res["grouped_handover"][1], g, q, b, check_tuples=not res["grouped_handover"][1].truncated)
