@@ -12,9 +12,9 @@ These pin the oracle with facts that do not come from running a matcher:
   * label-preserving automorphisms of Q act freely on the match set, so every
     result is closed under them and its size is a multiple of |Aut_L(Q)|.
 The multiset hash (a checksum of this project, not part of the paper) sums
-position-salted SplitMix64-finaliser hashes of the tuple's elements (Vigna,
-public domain constants) under one final finaliser; it lets results be
-compared at sizes where the tuples are not materialised.
+the tuple's elements times odd position keys (each key a SplitMix64-finaliser
+value, Vigna, public domain constants) under one final finaliser; it lets
+results be compared at sizes where the tuples are not materialised.
 """
 from __future__ import annotations
 
@@ -37,11 +37,16 @@ def _mix_py(z: int) -> int:
     return z
 
 
+def _term_key(j: int) -> int:
+    """K_j = mix(GOLDEN * (j + 1)) | 1: odd, so (v + 1) * K_j is a bijection of v mod 2^64."""
+    return _mix_py((GOLDEN * (j + 1)) & M64) | 1
+
+
 def tuple_hash(qid: int, sign: int, f) -> int:
-    """h = mix(mix(qid << 1 | sign) + sum_j mix(f_j + GOLDEN * (j + 1))), sums mod 2^64."""
+    """h = mix(mix(qid << 1 | sign) + sum_j (f_j + 1) * K_j), sums and products mod 2^64."""
     s = _mix_py((qid << 1) | (1 if sign else 0))
     for j, v in enumerate(f):
-        s = (s + _mix_py((int(v) + GOLDEN * (j + 1)) & M64)) & M64
+        s = (s + (int(v) + 1) * _term_key(j)) & M64
     return _mix_py(s)
 
 
@@ -62,7 +67,7 @@ def multiset_hash(tuples: np.ndarray, qid: int, sign: int) -> Tuple[int, int, in
     with np.errstate(over="ignore"):
         acc = np.full(t.shape[0], _mix_py((qid << 1) | (1 if sign else 0)), dtype=np.uint64)
         for j in range(t.shape[1]):
-            acc = acc + _mix_np(t[:, j] + np.uint64((GOLDEN * (j + 1)) & M64))
+            acc = acc + (t[:, j] + np.uint64(1)) * np.uint64(_term_key(j))
         h = _mix_np(acc)
         s = int(np.sum(h, dtype=np.uint64))
     x = int(np.bitwise_xor.reduce(h))

@@ -55,10 +55,11 @@
  * Output per pass: the tuples (f(0), ..., f(k-1)) with their seed ord, and
  * count / sum / xor of a per-tuple checksum built from the SplitMix64
  * finaliser `mix` (a checksum of this project, not part of the paper):
- *   h = mix( mix(qid << 1 | sign) + sum_j mix(f(j) + G * (j + 1)) ),
- *   sums mod 2^64, G = 0x9E3779B97F4A7C15, sign = 1 for insertions and 0 for
- *   deletions.  Position salts make it order-sensitive; the outer mix makes
- *   it non-linear in the tuple.
+ *   h = mix( mix(qid << 1 | sign) + sum_j (f(j) + 1) * K_j ),
+ *   K_j = mix(G * (j + 1)) | 1, sums and products mod 2^64,
+ *   G = 0x9E3779B97F4A7C15, sign = 1 for insertions and 0 for deletions.
+ *   Position keys make it order-sensitive; the outer mix makes it
+ *   non-linear in the tuple.
  *
  * A `mutant` argument plants a known mistake (tests use it to show that the
  * pins catch each one); 0 is the correct oracle.
@@ -126,9 +127,13 @@ static uint64_t mix(uint64_t z) {
   return z;
 }
 
+/* The project's tuple checksum (not part of the method): position j's
+ * element term is (f_j + 1) * K_j, K_j = mix(G (j + 1)) | 1 (odd, so the
+ * term is a bijection of f_j), and h = mix(mix(q << 1 | sign) + sum of the
+ * terms), sums mod 2^64. */
 static uint64_t tuple_hash(uint32_t qid, int sign, const uint32_t* f, uint32_t k) {
   uint64_t s = mix(((uint64_t)qid << 1) | (uint64_t)(sign ? 1 : 0));
-  for (uint32_t j = 0; j < k; ++j) s += mix((uint64_t)f[j] + 0x9E3779B97F4A7C15ull * (j + 1));
+  for (uint32_t j = 0; j < k; ++j) s += ((uint64_t)f[j] + 1u) * (mix(0x9E3779B97F4A7C15ull * (j + 1)) | 1u);
   return mix(s);
 }
 

@@ -395,3 +395,35 @@ def test_ord_list_sample_keeps_full_batch_figures():
     # ords past the batch are ignored; an empty list searches nothing
     r = O2.run(g, q, b, ords=[full.n_canonical + 5])
     assert tuple(r.count) == (0, 0)
+
+
+def test_checksum_definition_and_copies_agree():
+    """The project's tuple checksum (not part of the method): the C oracle's
+    and the Python copies agree with a direct evaluation of the definition,
+    and it separates tuples that differ by a swap of positions or by a
+    balanced change of two elements."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    M = (1 << 64) - 1
+
+    def direct(q, s, f):
+        z = CF._mix_py((q << 1) | s)
+        for j, v in enumerate(f):
+            z = (z + (int(v) + 1) * (CF._mix_py((0x9E3779B97F4A7C15 * (j + 1)) & M) | 1)) & M
+        return CF._mix_py(z)
+
+    for _ in range(50):
+        k = int(rng.integers(2, 17))
+        f = [int(x) for x in rng.integers(0, 1 << 31, k)]
+        q, s = int(rng.integers(0, 64)), int(rng.integers(0, 2))
+        assert O2.tuple_hash(q, s, f) == CF.tuple_hash(q, s, f) == direct(q, s, f)
+    t = rng.integers(0, 1 << 24, (200, 6)).astype(np.uint32)
+    cnt, hs, hx = CF.multiset_hash(t, 3, 1)
+    hh = [CF.tuple_hash(3, 1, row) for row in t.tolist()]
+    assert cnt == 200 and hs == sum(hh) % (1 << 64)
+    x = 0
+    for h in hh:
+        x ^= h
+    assert hx == x
+    assert CF.tuple_hash(0, 1, [1, 2, 3]) != CF.tuple_hash(0, 1, [2, 1, 3])
+    assert CF.tuple_hash(0, 1, [10, 20]) != CF.tuple_hash(0, 1, [13, 17])
+    assert CF.tuple_hash(0, 1, [5, 6]) != CF.tuple_hash(0, 0, [5, 6])
