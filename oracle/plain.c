@@ -71,6 +71,13 @@
  * the per-pass totals; its seed_count holds seed_cap + 1, a lower bound of
  * its true count.  Every seed that is not flagged is exact.
  *
+ * Scan cap (the same kind of control, for searches that are long without
+ * finding matches): with scan_cap > 0 a seed is given up once its search
+ * has examined scan_cap neighbour-list entries.  It is flagged 2 in
+ * seed_incomplete (1 marks the seed cap) and treated like a seed given up
+ * at the seed cap, except that its seed_count holds only the matches found
+ * before it was given up: a lower bound of its true count.
+ *
  * Ord list (a sampling control too): with ords != NULL only the canonical
  * updates whose ords are listed are searched; the canonical batch, G' and
  * the visibility of every batch edge are those of the whole batch, so each
@@ -111,7 +118,7 @@ typedef struct {
   double seconds;
   int32_t threads_used;
   uint32_t* canon_e; /* n_canonical: edge label of each canonical update */
-  uint8_t* seed_incomplete; /* n_canonical: 1 = given up at the seed cap */
+  uint8_t* seed_incomplete; /* n_canonical: 1 = given up at the seed cap, 2 = at the scan cap */
   uint64_t n_incomplete;
   double seconds_prep; /* keys, canonical batch and G' (the oracle's own graph update) */
 } o2_result;
@@ -363,6 +370,7 @@ typedef struct {
   uint32_t sample_mod, sample_rem;
   const uint8_t* pick; /* per canonical ord: 1 = searched (NULL: every ord) */
   uint64_t seed_cap; /* 0: none */
+  uint64_t scan_cap; /* 0: none */
   /* work distribution */
   uint32_t next; /* atomic counter over canonical updates */
   /* per seed totals */
@@ -374,7 +382,8 @@ typedef struct {
   shared_t* sh;
   tbuf_t out;
   uint64_t count[2], hsum[2], hxor[2];
-  int give_up; /* the current seed passed the seed cap */
+  int give_up;      /* the current seed passed the seed cap (1) or the scan cap (2) */
+  uint64_t scanned; /* neighbour-list entries the current seed's search has examined */
 } worker_t;
 
 static void emit(worker_t* w, int sign, uint32_t ord, const uint32_t* f) {
@@ -431,6 +440,10 @@ static void extend(worker_t* w, int sign, uint32_t ord, const uint32_t* pi, uint
   uint32_t a0 = f[back[0]];
   const int any_el = sh->mutant == MUT_NO_EDGE_LABEL_CHECK;
   for (uint64_t t = H->rp[a0]; t < H->rp[a0 + 1] && !w->give_up; ++t) {
+    if (sh->scan_cap && ++w->scanned > sh->scan_cap) {
+      w->give_up = 2;
+      return;
+    }
     uint32_t c = H->col[t] / sh->L, ce = H->col[t] % sh->L;
     if (!any_el && ce != q->qel[u][back[0]]) continue;
     if (sh->mutant != MUT_NO_LABEL_CHECK && sh->labels[c] != q->qlab[u]) continue;
@@ -467,6 +480,7 @@ static void* worker_main(void* arg) {
     uint32_t lo = sh->c->lo[i], hi = sh->c->hi[i], el = sh->c->e[i];
     const uint64_t n_out0 = w->out.n;
     w->give_up = 0;
+    w->scanned = 0;
     for (uint32_t d = 0; d < q->n_dqe && !w->give_up; ++d) {
       uint32_t x = q->dx[d], y = q->dy[d];
       if (sh->labels[lo] != q->qlab[x] || sh->labels[hi] != q->qlab[y]) continue;
@@ -476,8 +490,8 @@ static void* worker_main(void* arg) {
       extend(w, sign, i, q->order[d], 2, f);
     }
     if (w->give_up) {
-      /* given up at the seed cap: drop what it found */
-      sh->seed_incomplete[i] = 1;
+      /* given up at the seed or scan cap: drop what it found */
+      sh->seed_incomplete[i] = (uint8_t)w->give_up;
       w->out.n = n_out0;
       continue;
     }
@@ -539,8 +553,8 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
               uint32_t L, const uint32_t* elab, uint32_t qid, uint32_t k, const uint32_t* qlabels, uint32_t m,
               const uint32_t* qedges, const uint32_t* qelab, uint32_t n_upd, const uint32_t* src,
               const uint32_t* dst, const uint8_t* op, const uint32_t* uelab, int threads, uint32_t sample_mod,
-              uint32_t sample_rem, uint64_t seed_cap, const uint32_t* ords, uint32_t n_ords, int want_tuples,
-              int mutant, o2_result* res) {
+              uint32_t sample_rem, uint64_t seed_cap, uint64_t scan_cap, const uint32_t* ords, uint32_t n_ords,
+              int want_tuples, int mutant, o2_result* res) {
   struct timespec t0, t1, tp;
   clock_gettime(CLOCK_MONOTONIC, &t0);
   memset(res, 0, sizeof(*res));
@@ -622,6 +636,7 @@ int o2_run_el(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const ui
   }
   sh.pick = pick;
   sh.seed_cap = seed_cap;
+  sh.scan_cap = scan_cap;
   uint32_t nc = c.n ? c.n : 1;
   sh.seed_count = (uint64_t*)calloc(nc, 8);
   sh.seed_hsum = (uint64_t*)calloc(nc, 8);
@@ -695,7 +710,7 @@ int o2_run(uint32_t n, const uint64_t* row_ptr, const uint32_t* col, const uint3
            int threads, uint32_t sample_mod, uint32_t sample_rem, int want_tuples, int mutant,
            o2_result* res) {
   return o2_run_el(n, row_ptr, col, labels, 1, NULL, qid, k, qlabels, m, qedges, NULL, n_upd, src, dst, op, NULL,
-                   threads, sample_mod, sample_rem, 0, NULL, 0, want_tuples, mutant, res);
+                   threads, sample_mod, sample_rem, 0, 0, NULL, 0, want_tuples, mutant, res);
 }
 
 /* G' as a CSR for callers that chain batches (row_ptr n+1; col and, when

@@ -75,7 +75,7 @@ def _L():
         u32 = ctypes.c_uint32
         lib.o2_run_el.restype = ctypes.c_int
         lib.o2_run_el.argtypes = [u32, P, P, P, u32, P, u32, u32, P, u32, P, P, u32, P, P, P, P, ctypes.c_int,
-                                  u32, u32, ctypes.c_uint64, P, u32, ctypes.c_int, ctypes.c_int,
+                                  u32, u32, ctypes.c_uint64, ctypes.c_uint64, P, u32, ctypes.c_int, ctypes.c_int,
                                   ctypes.POINTER(_Res)]
         lib.o2_free.restype = None
         lib.o2_free.argtypes = [ctypes.POINTER(_Res)]
@@ -125,7 +125,7 @@ class O2Result:
     seed_hxor: np.ndarray
     seconds: float
     threads: int
-    seed_incomplete: Optional[np.ndarray] = None  # [n_canonical] uint8: 1 = given up at the seed cap
+    seed_incomplete: Optional[np.ndarray] = None  # [n_canonical] uint8: 1 = given up at the seed cap, 2 = scan cap
     n_incomplete: int = 0
     seconds_prep: float = 0.0  # the oracle's own graph update (keys, canonical batch, G')
 
@@ -156,12 +156,16 @@ def _p(a):
 
 
 def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1, sample_rem: int = 0,
-        want_tuples: bool = True, mutant: int = MUT_NONE, seed_cap: int = 0, ords=None) -> O2Result:
+        want_tuples: bool = True, mutant: int = MUT_NONE, seed_cap: int = 0, ords=None,
+        scan_cap: int = 0) -> O2Result:
     """Run O2 on (graph, query, batch); graph/query/batch are workloads types
     (edge labels when they carry them).  seed_cap > 0 gives up every seed
     with more than seed_cap matches (flagged in seed_incomplete, left out of
-    the totals and tuples); every other seed's figures are exact.  ords: only
-    these canonical updates are searched (each with its full-batch figures)."""
+    the totals and tuples); every other seed's figures are exact.  scan_cap
+    > 0 likewise gives up a seed whose search examines more than scan_cap
+    neighbour-list entries (flagged 2; its count is only a lower bound).  ords:
+    only these canonical updates are searched (each with its full-batch
+    figures)."""
     L = _L()
     n_el, gel, qel, bel = _labels_of(graph, query, batch)
     rp = np.ascontiguousarray(graph.row_ptr, dtype=np.uint64)
@@ -183,7 +187,7 @@ def run(graph, query, batch, qid: int = 0, threads: int = 1, sample_mod: int = 1
     r = _Res()
     rc = L.o2_run_el(graph.n, _ptr(rp), _ptr(col), _ptr(lab), n_el, _p(gel), qid, query.k, _ptr(ql), query.m,
                      _ptr(qe), _p(qel), n_upd, _ptr(src), _ptr(dst), _ptr(op), _p(bel) if n_upd else None,
-                     int(threads), int(sample_mod), int(sample_rem), int(seed_cap),
+                     int(threads), int(sample_mod), int(sample_rem), int(seed_cap), int(scan_cap),
                      _ptr(ord_arr) if ord_arr is not None else None, len(ord_arr) if ord_arr is not None else 0,
                      1 if want_tuples else 0, int(mutant), ctypes.byref(r))
     if rc == -3:

@@ -133,6 +133,28 @@ def test_seed_cap_keeps_completed_seeds_exact(cap):
     assert 0 < r.seconds_prep <= r.seconds
 
 
+@pytest.mark.parametrize("scan_cap", [20, 200])
+def test_scan_cap_keeps_completed_seeds_exact(scan_cap):
+    """The scan cap gives up a seed whose search examines more than scan_cap
+    neighbour-list entries (flag 2); its count is then at most the true count,
+    every other seed is exact, and a cap no search reaches changes nothing."""
+    g, q, b = W.random_small(11, n=40, p=0.3, n_labels=2, k=4, extra_q_edges=1, n_ins=30, n_del=20)
+    full = _check_o2_equals_o1(g, q, b)
+    for threads in (1, 4):
+        r = O2.run(g, q, b, threads=threads, scan_cap=scan_cap, want_tuples=False)
+        inc = r.seed_incomplete
+        assert set(np.unique(inc).tolist()) <= {0, 2} and (inc == 2).any() and (inc == 0).any()
+        done = inc == 0
+        assert np.array_equal(r.seed_count[done], full.seed_count[done])
+        assert np.array_equal(r.seed_hsum[done], full.seed_hsum[done])
+        assert np.all(r.seed_count[~done] <= full.seed_count[~done])
+        for sign in (0, 1):
+            sel = done & (full.canon_sign == sign)
+            assert r.count[sign] == int(full.seed_count[sel].sum())
+    r = O2.run(g, q, b, scan_cap=10 ** 12, want_tuples=False)
+    assert r.n_incomplete == 0 and r.count == full.count and r.hsum == full.hsum
+
+
 # ---------------------------------------------------------------- closed forms
 
 
