@@ -75,8 +75,12 @@ typedef struct gamma_options {
                                 gfx950; more than can reside add nothing) */
   uint32_t steal;            /* 0 = no work stealing, 1 = on (default when unset: see below) */
   uint32_t steal_set;        /* nonzero: honour `steal`; zero: library default (on) */
-  uint32_t deadline_ms;      /* search deadline per batch (0 = none); past it the batch
-                                returns GAMMA_ETIMEDOUT and is not committed */
+  uint32_t deadline_ms;      /* search deadline (0 = none), counted from the start of each
+                                search launch: the batch's one launch, or with
+                                query_launch = 2 each query's own launch (a time limit
+                                per query, Sec. VI-A).  A query whose search passes it is
+                                unsolved (open_seeds > 0); the batch then returns
+                                GAMMA_ETIMEDOUT and is not committed */
   uint32_t reserved[7];
 } gamma_options;
 
@@ -121,6 +125,11 @@ typedef struct gamma_tuning {
                              that waves starting together share rows.  1 = generation order
                              (default).  With query_launch = 2 seeds stay in generation order.
                              Results are identical in every mode. */
+  uint32_t shared_leaf;   /* 2 = on (default): when none of the last query vertex's lists comes
+                             from the vertex matched just before it, its candidates are read
+                             and filtered once per chunk of 64 partial matches and paired with
+                             each of them; 1 = off (each partial match walks them itself).
+                             Results are identical either way. */
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),
@@ -131,6 +140,11 @@ typedef struct gamma_query_result {
   uint64_t count[2];
   uint64_t hash_sum[2];  /* sum mod 2^64 of the per-tuple hash (GAMMA_F_HASH) */
   uint64_t hash_xor[2];  /* xor of the per-tuple hash (GAMMA_F_HASH) */
+  /* seeds of this query whose search did not finish before the deadline
+   * (tracked when a deadline is set or with GAMMA_F_PER_UPDATE): 0 = the
+   * figures above are exact, > 0 = the query is unsolved and they are a
+   * lower bound of what the search found */
+  uint64_t open_seeds;
 } gamma_query_result;
 
 typedef struct gamma_batch_stats {
@@ -268,10 +282,12 @@ gamma_status gamma_register_query_el(gamma_ctx* ctx, uint32_t k, const uint32_t*
  * in E are skipped as no-ops; a self loop or an id >= n gives EINVAL; +e
  * together with -e gives ECONFLICT.  Either error leaves the graph unchanged.
  * Returns OK or TRUNCATED (tuple capacity reached; counts and hashes exact).
- * With a deadline (gamma_options.deadline_ms) the search stops cooperatively
- * once it passes; the call then returns GAMMA_ETIMEDOUT, the graph keeps its
- * state from before the batch, and `out` holds the partial statistics
- * (stats.seeds_started tells how far the search got). */
+ * With a deadline (gamma_options.deadline_ms, gamma_set_deadline) a search
+ * launch stops cooperatively once it passes; the call then returns
+ * GAMMA_ETIMEDOUT, the graph keeps its state from before the batch, and
+ * `out` holds the partial statistics (stats.seeds_started tells how far the
+ * search got) and every query's figures: those with open_seeds = 0 finished
+ * and are exact (with query_launch = 2 every query gets its own time). */
 gamma_status gamma_apply_batch(gamma_ctx* ctx, uint32_t n_upd, const uint32_t* src,
                                const uint32_t* dst, const uint8_t* op, gamma_mem where,
                                uint32_t flags, gamma_batch_result* out);
@@ -353,6 +369,18 @@ gamma_status gamma_get_tuning(const gamma_ctx* ctx, gamma_tuning* out);
  * value outside the ranges in gamma_tuning; nothing changed). */
 gamma_status gamma_set_tuning(gamma_ctx* ctx, const gamma_tuning* in);
 
+/* Pause (active = 0) or resume a standing query.  A paused query's
+ * candidate table is kept current with every batch, but it gets no seeds:
+ * its results are 0 until it is resumed, and later batches report it again
+ * (matches of the batches it missed are not replayed).  Errors: EINVAL
+ * (NULL ctx, no such qid), EDEVICE. */
+gamma_status gamma_set_query_active(gamma_ctx* ctx, uint32_t qid, uint32_t active);
+
+/* Set the search deadline of later batches, as gamma_options.deadline_ms
+ * (0 = none; with query_launch = 2 it is a time limit per query, after
+ * which the query is reported unsolved, Sec. VI-A).  Errors: EINVAL (NULL). */
+gamma_status gamma_set_deadline(gamma_ctx* ctx, uint32_t deadline_ms);
+
 /* Tune the search for the current graph and queries on a calibration batch.
  * Every evaluation is a dry run (GAMMA_F_DRY_RUN with `flags`) of the batch,
  * timed as the median device time of `reps` runs (1..9).  Coordinate
@@ -390,7 +418,11 @@ typedef struct gamma_serve_options {
   uint32_t coalesce;          /* 1 = continuous batching (default), 2 = one request per batch */
   uint32_t tuple_fill_pct;    /* with TUPLES: admission keeps a batch's estimated tuples within
                                  this share of the context's tuple_capacity, 1..100 (0 = 50) */
-  uint32_t reserved[4];
+  uint32_t max_batch_ms;      /* admission by estimated work, in every mode: keeps a batch's
+                                 estimated device time (a moving estimate of device ms per
+                                 update over the batches so far) within this budget; the first
+                                 request of a batch is always admitted (0 = no limit) */
+  uint32_t reserved[3];
 } gamma_serve_options;
 
 /* A committed request. */

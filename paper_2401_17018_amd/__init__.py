@@ -83,6 +83,7 @@ class BatchOutput:
     upd_hash_sum: Optional[np.ndarray] = None
     upd_hash_xor: Optional[np.ndarray] = None
     upd_open: Optional[np.ndarray] = None  # [n_canonical] uint8: 1 = search work of that update did not finish
+    open_seeds: Optional[np.ndarray] = None  # [n_queries]: seeds left unfinished (tracked under a deadline)
     stats: dict = field(default_factory=dict)
 
     @property
@@ -241,6 +242,10 @@ class Context:
             err.stats = {name: getattr(res.stats, name) for name, _ in capi.BatchStats._fields_
                          if not name.startswith("reserved")}
             err.counts = [[res.queries[i].count[sg] for sg in range(2)] for i in range(int(res.n_queries))]
+            err.hash_sum = [[res.queries[i].hash_sum[sg] for sg in range(2)] for i in range(int(res.n_queries))]
+            err.hash_xor = [[res.queries[i].hash_xor[sg] for sg in range(2)] for i in range(int(res.n_queries))]
+            # per query: seeds left unfinished (0 = solved: its figures are exact)
+            err.open_seeds = np.array([res.queries[i].open_seeds for i in range(int(res.n_queries))], dtype=np.uint64)
             nc = int(res.n_canonical)
             if per_update and nc and res.upd_count:
                 # partial attribution: updates whose search finished (upd_open 0) are exact
@@ -254,14 +259,17 @@ class Context:
         counts = np.zeros((nq, 2), dtype=np.uint64)
         hs = np.zeros((nq, 2), dtype=np.uint64)
         hx = np.zeros((nq, 2), dtype=np.uint64)
+        op_ = np.zeros(nq, dtype=np.uint64)
         for i in range(nq):
             q = res.queries[i]
+            op_[i] = q.open_seeds
             for sg in range(2):
                 counts[i, sg] = q.count[sg]
                 hs[i, sg] = q.hash_sum[sg]
                 hx[i, sg] = q.hash_xor[sg]
         out = BatchOutput(status=int(st), counts=counts, hash_sum=hs, hash_xor=hx, n_tuples=int(res.n_tuples),
                           n_tuples_found=int(res.n_tuples_found))
+        out.open_seeds = op_
         nc = int(res.n_canonical)
         if canonical and nc:
             out.canon_lo = np.ctypeslib.as_array(res.canon_lo, (nc,)).copy()
@@ -314,6 +322,19 @@ class Context:
         t = capi.Tuning()
         _check(self._lib, self._ptr, self._lib.gamma_get_tuning(self._ptr, ctypes.byref(t)), "get_tuning")
         return t.as_dict()
+
+    def set_deadline(self, ms: int) -> None:
+        """Search deadline of later batches in ms (0 = none).  With
+        query_launch = 2 each query's search gets this time on its own; a
+        query that passes it is unsolved (open_seeds > 0) and the batch
+        raises GammaError(GAMMA_ETIMEDOUT) without being committed."""
+        _check(self._lib, self._ptr, self._lib.gamma_set_deadline(self._ptr, int(ms)), "set_deadline")
+
+    def set_query_active(self, qid: int, active: bool) -> None:
+        """Pause or resume a standing query (a paused query is kept current
+        but not searched; its results are 0)."""
+        _check(self._lib, self._ptr, self._lib.gamma_set_query_active(self._ptr, int(qid), 1 if active else 0),
+               "set_query_active")
 
     def set_tuning(self, **kw) -> dict:
         """Set search tunables (waves_per_cu, steal 1/2, poll_cycles, split_inner,
@@ -410,10 +431,12 @@ class Server:
     through it."""
 
     def __init__(self, ctx: Context, max_batch_updates: int = 0, hash: bool = True, per_update: bool = False,
-                 coalesce: bool = True, tuples: bool = False, seed_attr: bool = False, tuple_fill_pct: int = 0):
+                 coalesce: bool = True, tuples: bool = False, seed_attr: bool = False, tuple_fill_pct: int = 0,
+                 max_batch_ms: int = 0):
         """tuples: keep every batch's match records (the context needs a
         tuple_capacity); admission then also bounds a batch's estimated
-        records by tuple_fill_pct of that capacity."""
+        records by tuple_fill_pct of that capacity.  max_batch_ms: admission
+        also bounds a batch's estimated device time (0 = no bound)."""
         self._lib = ctx._lib
         self.ctx = ctx
         o = capi.ServeOptions()
@@ -422,6 +445,7 @@ class Server:
                    (F_TUPLES if tuples else 0) | (F_SEED_ATTR if tuples and seed_attr else 0))
         o.coalesce = 1 if coalesce else 2
         o.tuple_fill_pct = int(tuple_fill_pct)
+        o.max_batch_ms = int(max_batch_ms)
         self._ptr = ctypes.c_void_p()
         _check(self._lib, ctx._ptr, self._lib.gamma_serve_create(ctx._ptr, ctypes.byref(o), ctypes.byref(self._ptr)),
                "serve_create")

@@ -24,7 +24,7 @@ F_COUNT, F_HASH, F_TUPLES, F_SEED_ATTR, F_PER_UPDATE, F_CANONICAL, F_DRY_RUN = 1
 EXPORTS = [
     "gamma_create", "gamma_destroy", "gamma_load_graph", "gamma_register_query", "gamma_apply_batch",
     "gamma_load_graph_el", "gamma_register_query_el", "gamma_apply_batch_el", "gamma_export_graph_el",
-    "gamma_apply_batch_vertices", "gamma_apply_batch_noalloc", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_autotune",
+    "gamma_apply_batch_vertices", "gamma_apply_batch_noalloc", "gamma_add_vertices", "gamma_get_tuning", "gamma_set_tuning", "gamma_set_deadline", "gamma_set_query_active", "gamma_autotune",
     "gamma_serve_create", "gamma_serve_submit", "gamma_serve_submit_el", "gamma_serve_poll", "gamma_serve_drain", "gamma_serve_counts",
     "gamma_serve_get_batch", "gamma_serve_get_tuples", "gamma_serve_destroy",
     "gamma_copy_tuples", "gamma_result_release", "gamma_export_graph", "gamma_validate_graph",
@@ -64,10 +64,11 @@ class Tuning(ctypes.Structure):
         ("handover_gate", ctypes.c_uint32),
         ("coalesced_search", ctypes.c_uint32),
         ("group_seeds", ctypes.c_uint32),
+        ("shared_leaf", ctypes.c_uint32),
     ]
 
     FIELDS = ("waves_per_cu", "steal", "poll_cycles", "split_inner", "split_leaf", "query_launch", "handover_gate",
-              "coalesced_search", "group_seeds")
+              "coalesced_search", "group_seeds", "shared_leaf")
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f in self.FIELDS}
@@ -79,7 +80,8 @@ class ServeOptions(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("coalesce", ctypes.c_uint32),
         ("tuple_fill_pct", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 4),
+        ("max_batch_ms", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 3),
     ]
 
 
@@ -118,6 +120,7 @@ class QueryResult(ctypes.Structure):
         ("count", ctypes.c_uint64 * 2),
         ("hash_sum", ctypes.c_uint64 * 2),
         ("hash_xor", ctypes.c_uint64 * 2),
+        ("open_seeds", ctypes.c_uint64),
     ]
 
 
@@ -223,6 +226,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gamma_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.gamma_set_tuning.restype = st
     lib.gamma_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.gamma_set_deadline.restype = st
+    lib.gamma_set_deadline.argtypes = [P, ctypes.c_uint32]
+    lib.gamma_set_query_active.restype = st
+    lib.gamma_set_query_active.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32]
     lib.gamma_autotune.restype = st
     lib.gamma_autotune.argtypes = [P, u32, P, P, P, ctypes.c_int, u32, u32, u32, ctypes.POINTER(Tuning),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]

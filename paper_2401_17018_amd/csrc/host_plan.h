@@ -19,6 +19,7 @@ struct HostQuery {
   std::vector<GmPlan> plans;                          // one per directed edge
   std::vector<GmPerm> perms;                          // coalesced search, referenced by plans
   std::vector<GmPerm> cperms;                         // core-prefix permutations (k > 0 coalescing)
+  bool paused = false;                                // kept current but not searched
 };
 
 // Validates a query; on failure returns the status code (EINVAL or

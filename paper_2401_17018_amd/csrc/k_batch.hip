@@ -285,12 +285,13 @@ __global__ void k_rows_commit(const uint32_t* __restrict__ touched, const uint64
   }
 }
 
-// Commit the G' rows, or put the saved rows back when the search was aborted.
+// Commit the G' rows, or put the saved rows back when a search launch of the
+// batch passed its deadline.
 __global__ void k_rows_finish(const uint32_t* __restrict__ touched, const uint64_t* __restrict__ r2_off,
                               const uint32_t* __restrict__ r2_len, const uint64_t* __restrict__ r0_off,
                               const uint32_t* __restrict__ r0_len, uint32_t n_touched, GmGraphDev G,
                               const GmCounters* __restrict__ ctr, uint32_t restore) {
-  const bool back = restore || ctr->aborted != 0;
+  const bool back = restore || ctr->aborted != 0 || ctr->timed_out != 0;
   for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_touched; t += gridDim.x * blockDim.x) {
     const uint32_t v = touched[t];
     G.row_off[v] = back ? r0_off[t] : r2_off[t];

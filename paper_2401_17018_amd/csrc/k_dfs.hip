@@ -79,6 +79,15 @@ constexpr uint32_t POLL_STEPS = GM_POLL_STEPS;
 #define GM_WIN_MAX 256
 #endif
 constexpr uint32_t WIN_MAX = GM_WIN_MAX;
+// a last level shared by the survivors of a level-(k-2) chunk is walked
+// once for all of them when its driving list has at most this many
+// entries (the walk cannot be handed over, and a chunk's pairs then stay
+// within about a millisecond of one wave's time); longer ones take the
+// per-survivor descent, whose ranges the hand-over can split
+#ifndef GM_SHARED_MAX
+#define GM_SHARED_MAX 4096
+#endif
+constexpr uint32_t SHARED_MAX = GM_SHARED_MAX;
 
 // Algorithmic bytes, counted in eighths of a byte by a fixed model of what
 // the method must read, whatever this kernel's layout makes it read: per
@@ -122,6 +131,8 @@ struct WaveState {
   uint32_t st_n;
   uint32_t st_min;         // shortest static list (0xFFFFFFFF: none)
   uint64_t st_h;           // checksum salt + element terms of order[0 .. k-3]
+  uint64_t sh_mask;        // with shared = 1: the level-(k-2) survivors that share level k-1
+  uint32_t shared;
   uint32_t pf_c[GM_WAVE];  // survivor's internal id
   uint32_t pf_x[GM_WAVE];  // its external id
   uint32_t pf_len[GM_WAVE];
@@ -233,10 +244,26 @@ __device__ inline bool visible(const GmBatchHash& H, uint32_t a, uint32_t c, uin
   return false;
 }
 
-// Tuple checksum: h = mix(mix(q << 1 | sign) + sum_j mix(f_j + G (j + 1))).
-// Element term of position j:
+// Tuple checksum: h = mix(mix(q << 1 | sign) + sum_j (f_j + 1) K_j), sums and
+// products mod 2^64, with the odd position keys K_j = mix(G (j + 1)) | 1.
+constexpr uint64_t hk_mix(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+constexpr uint64_t hk_key(uint32_t j) { return hk_mix(GM_GOLDEN * (uint64_t)(j + 1)) | 1ull; }
+static_assert(GM_MAX_K == 16, "position key table sized for 16 query vertices");
+__constant__ uint64_t c_hk[GM_MAX_K] = {
+    hk_key(0), hk_key(1), hk_key(2),  hk_key(3),  hk_key(4),  hk_key(5),  hk_key(6),  hk_key(7),
+    hk_key(8), hk_key(9), hk_key(10), hk_key(11), hk_key(12), hk_key(13), hk_key(14), hk_key(15)};
+
+// Element term of position j: (v + 1) K_j = v K_j + K_j.
 __device__ inline uint64_t elem_hash(uint32_t v, uint32_t j) {
-  return gm_mix64((uint64_t)v + GM_GOLDEN * (uint64_t)(j + 1));
+  const uint64_t kj = c_hk[j];
+  return (uint64_t)v * kj + kj;
 }
 
 struct Acc {
@@ -562,6 +589,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       S.oth_n[l] = nb - 1;
       S.cur[l] = 0;
       S.mask[l] = 0;
+      if (l == k - 1) S.shared = 0u;
     };
 
     // Lanes 0-31 fetch the lists of order[l] (one memory round trip for
@@ -676,6 +704,32 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       return true;
     };
 
+    // Last level shared by a chunk's survivors.  When none of the last query
+    // vertex's lists comes from order[k-2] (its matched neighbours all come
+    // earlier in the order), its candidates are the same for every survivor
+    // s of a level-(k-2) chunk, but for s itself.  Level k-1 is then set up
+    // once from the static lists (the driver picked as for each survivor)
+    // and walked once; every candidate that passes is paired with every
+    // survivor, (s, c) being a match unless c = s where the labels allow it
+    // (leaf_step).  Not for lists longer than SHARED_MAX, whose per-survivor
+    // ranges the hand-over can split.
+    auto init_leaf_shared = [&](uint64_t m) -> bool {
+      const uint32_t nb1 = uni(S.st_n);
+      if (nb1 == 0 || uni(S.st_min) > SHARED_MAX) return false;
+      uint32_t v = 0, sub = 0;
+      uint64_t base = 0;
+      if ((uint32_t)lane < nb1) {
+        v = S.st_v[lane];
+        base = S.st_base[lane];
+        sub = S.st_len[lane];
+      }
+      finish_level(k - 1, nb1, (uint32_t)lane < nb1, v, base, sub);
+      S.sh_mask = m;
+      S.shared = 1u;
+      TALLY_ALWAYS(7, (uint32_t)__popcll(m));
+      return true;
+    };
+
     // After a level-(k-2) chunk: every survivor lane records its external id,
     // its element term and (when order[k-2] is a matched neighbour of the
     // last vertex) its own row's subrange for the last vertex's label.
@@ -770,8 +824,9 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // ---- hand the upper half of the shallowest unexplored work to an idle wave
     auto try_donate_impl = [&](uint32_t lcur) {
       // the shallowest splittable work (rules shared with the host model)
-      const HoSplit sp = ho_choose(WaveView{S}, base_l, lcur, k, core, L0, P.split_leaf, P.split_inner,
-                                   ho_rule_default());
+      // (a shared last level is not split: its survivors are not in the task record)
+      const HoSplit sp = ho_choose(WaveView{S}, base_l, lcur, k, core, L0,
+                                   uni(S.shared) ? 0xFFFFFFFFu : P.split_leaf, P.split_inner, ho_rule_default());
       const uint32_t lv = sp.lv, kind = sp.kind;
       const uint64_t give = sp.give;
       if (kind == 0) return;
@@ -828,22 +883,22 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 
     // ---- keep candidate e[j] (lane, chunk j) only if it is in the sorted
     // list [base, base + olen) of row wv and that entry is visible; the
-    // LEAF_UNROLL lower-bound searches run interleaved.
-    auto probe_list = [&](bool (&ok)[LEAF_UNROLL], const uint32_t (&e)[LEAF_UNROLL], uint64_t base, uint32_t olen,
-                          uint32_t wv) {
+    // lower-bound searches of the caller's chunks run interleaved.
+    auto probe_list = [&](auto& ok, const auto& e, uint64_t base, uint32_t olen, uint32_t wv) {
+      constexpr int NU = (int)(sizeof(e) / sizeof(e[0]));  // chunks of the caller's step
       uint32_t n_probe = 0;
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
+      for (int j = 0; j < NU; ++j) n_probe += (uint32_t)__popcll(__ballot(ok[j]));
       u_bytes += MB_WORD * n_probe * mb_search(olen);
       CNT(2, n_probe);
       CNT(4, olen);
-      uint32_t lo[LEAF_UNROLL], cnt[LEAF_UNROLL];
+      uint32_t lo[NU], cnt[NU];
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) {
+      for (int j = 0; j < NU; ++j) {
         lo[j] = 0;
         cnt[j] = ok[j] ? olen : 0u;
       }
-      uint32_t e2[LEAF_UNROLL];
+      uint32_t e2[NU];
       if (olen <= WIN_MAX) {
         // a short list: all of it into the wave's LDS window (every load
         // issued before any store, so one memory round trip), then the
@@ -856,7 +911,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         for (;;) {
           bool any = false;
 #pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
+          for (int j = 0; j < NU; ++j) {
             if (cnt[j]) {
               any = true;
               const uint32_t half = cnt[j] >> 1;
@@ -871,24 +926,24 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           if (!__ballot(any)) break;
         }
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
+        for (int j = 0; j < NU; ++j) {
           const bool in = lo[j] < olen;
           e2[j] = S.win[in ? lo[j] : olen - 1];
           if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
         }
       } else {
         for (;;) {
-          uint32_t v[LEAF_UNROLL];
+          uint32_t v[NU];
           bool any = false;
 #pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
+          for (int j = 0; j < NU; ++j) {
             // clamped so a finished search still reads inside the list (olen >= 1)
             const uint32_t at = lo[j] + (cnt[j] >> 1);
             v[j] = col[base + (at < olen ? at : olen - 1)] & GM_IDMASK;
           }
-          CNT(1, LEAF_UNROLL);
+          CNT(1, NU);
 #pragma unroll
-          for (int j = 0; j < LEAF_UNROLL; ++j) {
+          for (int j = 0; j < NU; ++j) {
             if (cnt[j]) {
               any = true;
               const uint32_t half = cnt[j] >> 1;
@@ -903,7 +958,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           if (!__ballot(any)) break;
         }
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
+        for (int j = 0; j < NU; ++j) {
           const bool in = lo[j] < olen;
           e2[j] = col[base + (in ? lo[j] : olen - 1)];
           if (ok[j] && (!in || (e2[j] & GM_IDMASK) != (e[j] & GM_IDMASK))) ok[j] = false;
@@ -911,10 +966,10 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       uint32_t nfl = 0;
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j) nfl += (uint32_t)__popcll(__ballot(ok[j] && (e2[j] & GM_FLAG)));
+      for (int j = 0; j < NU; ++j) nfl += (uint32_t)__popcll(__ballot(ok[j] && (e2[j] & GM_FLAG)));
       u_bytes += MB_HASH_PROBE * nfl;
 #pragma unroll
-      for (int j = 0; j < LEAF_UNROLL; ++j)
+      for (int j = 0; j < NU; ++j)
         if (ok[j] && (e2[j] & GM_FLAG)) ok[j] = visible(P.H, wv, e[j] & GM_IDMASK, ord, sign);
     };
 
@@ -939,26 +994,31 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         ok[j] = idx < len;
         e[j] = col[drv + (ok[j] ? idx : len - 1)];
       }
-      if (need_x) {
+      // external ids without a branch around the loads (a branch makes the
+      // compiler wait for each load inside it); without a checksum every
+      // lane reads entry 0 of the table instead
 #pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) {
-          const uint32_t idx = cur + (uint32_t)(j * GM_WAVE + lane);
-          x[j] = ext[drv + (ok[j] ? idx : len - 1)];
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < LEAF_UNROLL; ++j) x[j] = 0;
+      for (int j = 0; j < LEAF_UNROLL; ++j) {
+        const uint32_t idx = cur + (uint32_t)(j * GM_WAVE + lane);
+        x[j] = ext[need_x ? drv + (ok[j] ? idx : len - 1) : 0ull];
       }
+      // a level shared by several survivors: the byte model counts this
+      // step once per survivor, as their own descents would read it
+      const bool shared = uni(S.shared) != 0u;
+      const uint64_t shm = shared ? uni64(S.sh_mask) : 0ull;
+      const uint32_t ns = shared ? (uint32_t)__popcll(shm) : 1u;
+      const uint64_t ub0 = u_bytes;
       // candidates scanned and their bytes, counted once per wave
       uint32_t n_in = 0;
 #pragma unroll
       for (int j = 0; j < LEAF_UNROLL; ++j) n_in += (uint32_t)__popcll(__ballot(ok[j]));
-      u_scan += n_in;
+      u_scan += (uint64_t)n_in * ns;
       u_bytes += (uint64_t)n_in * MB_CAND;
       CNT(0, 1);
-      CNT(3, n_in);
+      CNT(3, n_in * ns);
       const uint32_t fo_all = S.fo[lane & (GM_MAX_K - 1)];
-      for (uint32_t im = uni(pl->injm[l]); im; im &= im - 1) {
+      // (a shared level leaves the survivor's own position to the pairs)
+      for (uint32_t im = uni(pl->injm[l]) & (shared ? ~(1u << (k - 2)) : ~0u); im; im &= im - 1) {
         const uint32_t fv = lane_val(fo_all, __builtin_ctz(im));
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) ok[j] = ok[j] && ((e[j] & GM_IDMASK) != fv);
@@ -980,7 +1040,42 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         if (!__ballot(anyok)) break;
         probe_list(ok, e, uni64(S.oth_base[ob + i]), uni(S.oth_len[ob + i]), uni(S.oth_v[ob + i]));
       }
-      if (nperm == 1) {
+      if (shared) {
+        u_bytes = ub0 + (u_bytes - ub0) * ns;
+        // every candidate left pairs with every survivor s (its data vertex
+        // and prefix terms sit in lane s), but s itself where order[k-2] and
+        // the last vertex share a label; one chunk's term at a time
+        const bool inj_s = ((uni(pl->injm[l]) >> (k - 2)) & 1u) != 0u;
+        const uint32_t my_c = S.pf_c[lane];
+        const uint64_t my_h = uni64(S.st_h) + S.pf_h[lane];
+#pragma unroll
+        for (int j = 0; j < LEAF_UNROLL; ++j) {
+          if (!__ballot(ok[j])) continue;
+          const uint64_t t = elem_hash(x[j], u);
+          const uint32_t cj = e[j] & GM_IDMASK;
+          for (uint64_t mm = shm; mm; mm &= mm - 1) {
+            const uint32_t s = (uint32_t)__builtin_ctzll(mm);
+            const bool ok2 = ok[j] && !(inj_s && cj == lane_val(my_c, s));
+            const uint64_t m2 = __ballot(ok2);
+            A.cnt += (uint64_t)__popcll(m2);
+            if (flags & (GM_F_HASH | GM_F_PER_UPDATE)) {
+              const uint64_t h = ok2 ? gm_mix64(lane_val64(my_h, s) + t) : 0ull;
+              A.sum += h;
+              A.xr ^= h;
+              if (flags & GM_F_PER_UPDATE) {
+                const uint64_t ws = wave_sum64(h);
+                const uint64_t wx = wave_xor64(h);
+                if (lane == 0 && m2) {
+                  unsigned long long* r = P.upd_res + (uint64_t)ord * 3;
+                  atomicAdd(r + 0, (unsigned long long)__popcll(m2));
+                  atomicAdd(r + 1, (unsigned long long)ws);
+                  atomicXor(r + 2, (unsigned long long)wx);
+                }
+              }
+            }
+          }
+        }
+      } else if (nperm == 1) {
         const uint64_t hpre = uni64(S.hpre);
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) {
@@ -1042,19 +1137,24 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // candidate t of the concatenation; the other survivors are left in
     // the level's mask for the regular descent.  my_len = this lane's
     // survivor list length (0 if not a survivor).
-    auto leaf_packed = [&](uint32_t l, uint64_t m, uint32_t my_len) {
-      if (nperm > 1) return;  // coalesced plans take the regular last level
+    auto leaf_packed = [&](uint32_t l, uint64_t m, uint32_t my_len) -> bool {
+      if (nperm > 1) return false;  // coalesced plans take the regular last level
       const uint32_t lf = k - 1;
       const uint32_t u = uni(pl->order[lf]);
       const uint32_t u2 = uni(pl->order[l]);
-      if (!((uni(pl->back[lf]) >> u2) & 1u)) return;
+      if (!((uni(pl->back[lf]) >> u2) & 1u)) {
+        // every list of the last vertex is static: one walk for the chunk
+        if (!P.shared_leaf || (flags & GM_F_TUPLES) || !init_leaf_shared(m)) return false;
+        S.mask[l] = 0;  // the chunk's survivors are all taken by the shared level
+        return true;
+      }
       const bool in_m = (m >> lane) & 1ull;
       const uint32_t st_min = uni(S.st_min);
       // survivors with an empty list have no extension at all
       const uint64_t empty = __ballot(in_m && my_len == 0);
       const uint64_t pm = __ballot(in_m && my_len != 0 && my_len <= PACK_MAX && my_len <= st_min);
       S.mask[l] = m & ~pm & ~empty;
-      if (!pm) return;
+      if (!pm) return false;
       TALLY_ALWAYS(7, (uint32_t)__popcll(pm));
       const uint32_t lenv = ((pm >> lane) & 1ull) ? my_len : 0u;
       const uint32_t incl = wave_incl_scan(lenv, lane);  // end of each survivor's range
@@ -1070,23 +1170,35 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         // every 4th step is often enough
         if ((t0 & (4 * LEAF_UNROLL * GM_WAVE - 1)) == 0 && poll(l)) {
           abort_now = true;
-          return;
+          return false;
         }
         // survivor of each candidate t: the first lane whose range ends
-        // after t.  incl is non-decreasing over the 64 lanes (lanes that
-        // are not packed survivors add 0), so a 6-step binary search over
-        // it finds that lane, whatever the number of survivors in the
-        // window.  Lanes past T read survivor b0's first entry.
+        // after t, i.e. the number of lanes whose range ends at or before
+        // t (incl is non-decreasing over the 64 lanes; lanes that are not
+        // packed survivors add 0).  Per chunk [tb, tb + 64): s0 ranges end
+        // at or before tb, and the few that end inside the chunk are
+        // counted one by one; with many of them, a 6-step binary search
+        // over the lanes.  Lanes past T read survivor b0's first entry.
         uint32_t sl[LEAF_UNROLL], off[LEAF_UNROLL];
         bool ok[LEAF_UNROLL];
 #pragma unroll
         for (int j = 0; j < LEAF_UNROLL; ++j) {
-          const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
+          const uint32_t tb = t0 + (uint32_t)(j * GM_WAVE);
+          const uint32_t t = tb + (uint32_t)lane;
           ok[j] = t < T;
-          uint32_t pos = 0;
+          const uint64_t ends_in = __ballot(incl > tb && incl <= tb + (GM_WAVE - 1));
+          uint32_t pos;
+          if (__popcll(ends_in) <= 4) {
+            pos = (uint32_t)__popcll(__ballot(incl <= tb));
+            for (uint64_t m = ends_in; m; m &= m - 1)
+              pos += lane_val(incl, (uint32_t)__builtin_ctzll(m)) <= t ? 1u : 0u;
+            pos = pos < GM_WAVE ? pos : GM_WAVE - 1;
+          } else {
+            pos = 0;
 #pragma unroll
-          for (uint32_t step = GM_WAVE / 2; step; step >>= 1)
-            if (lane_at(incl, pos + step - 1) <= t) pos += step;
+            for (uint32_t step = GM_WAVE / 2; step; step >>= 1)
+              if (lane_at(incl, pos + step - 1) <= t) pos += step;
+          }
           const uint32_t lb = lane_at(excl, pos);
           sl[j] = ok[j] ? pos : b0;
           off[j] = ok[j] ? lb : t;
@@ -1097,7 +1209,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           const uint32_t t = t0 + (uint32_t)(j * GM_WAVE + lane);
           const uint64_t at = S.pf_base[sl[j]] + (t - off[j]);
           e[j] = col[at];
-          x[j] = need_x ? ext[at] : 0u;
+          x[j] = ext[need_x ? at : 0ull];  // no branch around the load (see leaf_step)
           cs[j] = S.pf_c[sl[j]];
         }
         uint32_t n_in = 0;
@@ -1140,6 +1252,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
           }
         }
       }
+      return false;
     };
 
     // core permutation p (0: the identity) of the prefix saved in fcore:
@@ -1280,9 +1393,13 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
               if (m) {
                 const uint32_t my_len = prefetch_leaf(l, eidx, c, ok);
                 const uint64_t t_pk = CYCLES();
-                leaf_packed(l, m, my_len);
+                const bool sh = leaf_packed(l, m, my_len);
                 TALLY(3, CYCLES() - t_pk);
                 if (abort_now) break;
+                if (sh) {
+                  l = k - 1;  // the shared last level, walked from its start
+                  continue;
+                }
                 m = uni64(S.mask[l]);
               }
             }
@@ -1364,10 +1481,15 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 }
 
 __global__ void k_upd_open(const GmSeed* __restrict__ seeds, const GmCounters* __restrict__ ctr, uint64_t seed_cap,
-                           const uint32_t* __restrict__ seed_open, uint8_t* __restrict__ upd_open) {
+                           const uint32_t* __restrict__ seed_open, uint8_t* __restrict__ upd_open,
+                           unsigned long long* __restrict__ q_open) {
   const uint64_t ns = ctr->n_seeds < seed_cap ? ctr->n_seeds : seed_cap;
   for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += (uint64_t)gridDim.x * blockDim.x)
-    if (seed_open[t] != 0u) upd_open[seeds[t].os >> 1] = 1u;
+    if (seed_open[t] != 0u) {
+      const GmSeed sd = seeds[t];
+      if (upd_open) upd_open[sd.os >> 1] = 1u;
+      if (q_open) atomicAdd(&q_open[sd.qd >> 8], 1ull);
+    }
 }
 
 }  // namespace
@@ -1394,10 +1516,10 @@ bool dfs_lean(const GmDfsParams& P) {
 }
 
 void launch_upd_open(const GmSeed* seeds, const GmCounters* ctr, uint64_t seed_cap, const uint32_t* seed_open,
-                     uint8_t* upd_open, hipStream_t s) {
+                     uint8_t* upd_open, unsigned long long* q_open, hipStream_t s) {
   const uint64_t want = (seed_cap + 255) / 256;
   const unsigned blocks = (unsigned)(want < 4096 ? (want ? want : 1) : 4096);
-  k_upd_open<<<blocks, 256, 0, s>>>(seeds, ctr, seed_cap, seed_open, upd_open);
+  k_upd_open<<<blocks, 256, 0, s>>>(seeds, ctr, seed_cap, seed_open, upd_open, q_open);
 }
 
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s) {

@@ -272,9 +272,13 @@ __global__ void k_pending_init(GmCounters* ctr) { ctr->pending = ctr->n_seeds - 
 
 // Seeds appended after this point form the next launch's window.
 __global__ void k_seed_window(GmCounters* ctr) {
+  if (ctr->aborted) {
+    ctr->timed_out = 1u;
+    ctr->aborted = 0u;
+  }
   ctr->seed_begin = ctr->n_seeds;
   ctr->seed_head = ctr->n_seeds;
-  if (ctr->t_start == 0) ctr->t_start = wall_clock64();
+  ctr->t_start = wall_clock64();
 }
 
 unsigned grid_for(uint64_t work, unsigned per_block) {

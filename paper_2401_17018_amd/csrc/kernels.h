@@ -47,10 +47,10 @@ struct GmCounters {
   unsigned long long bytes_update;
   unsigned long long cyc[6];      // idle, init, inner, leaf, hand-over cycles; tasks received
   unsigned long long pending;     // work items taken or handed over and not finished
-  unsigned int aborted;           // set when a wave passed the deadline; every wave then exits
-  unsigned int pad1;
+  unsigned int aborted;           // set when a wave passed the deadline; every wave of the launch then exits
+  unsigned int timed_out;         // some search launch of the batch passed its deadline (sticky)
   unsigned long long seed_begin;  // first seed of the current search launch (seeds [seed_begin, n_seeds))
-  unsigned long long t_start;     // device wall clock when the batch's search began (deadline origin)
+  unsigned long long t_start;     // device wall clock when the current search launch began (deadline origin)
 };
 
 constexpr uint32_t GM_NO_GROUP = 0xFFFFFFFFu;
@@ -93,7 +93,8 @@ struct GmDfsParams {
   const GmPerm* perms;            // coalesced search: permutation table referenced by plans
   uint32_t coalesce;              // 1: search representative plans only and permute their matches;
                                   // 2: also permute core prefixes (plans with n_cperm >= 2)
-  uint32_t pad3;
+  uint32_t shared_leaf;           // 1: a last level that does not depend on level k-2 is walked
+                                  // once per level-(k-2) chunk for all its survivors
   const uint8_t* qel;             // [nq][16][16] edge label of query edge {u, w} (used when G.elb > 0)
   // per seed, its work items not yet finished (the seed's own item plus one
   // per hand-over of its work); 0xFFFFFFFF = not started.  NULL: untracked.
@@ -200,7 +201,8 @@ void launch_pending_init(GmCounters* ctr, hipStream_t s);
 void launch_seed_keys(const GmSeed* seeds, uint64_t n, int ib, uint64_t* keys, hipStream_t s);
 void launch_seed_gather(const GmSeed* in, const uint64_t* keys, uint64_t n, int ib, GmSeed* out, hipStream_t s);
 // opens the seed window of the next search launch: seed_begin = seed_head =
-// n_seeds; sets the deadline origin on the first call of a batch
+// n_seeds, the deadline origin is now, and an abort of the previous launch
+// is moved to the sticky timed_out flag (the next launch runs)
 void launch_seed_window(GmCounters* ctr, hipStream_t s);
 // Update-edge grouping by (query, directed query edge, a).  keys: qd << (ib +
 // pb) | a << pb | position (sorted by the caller over 16 + ib + pb bits);
@@ -236,10 +238,11 @@ void launch_seeds(const uint32_t* canon_a, const uint32_t* canon_b, const uint8_
 
 // search (k_dfs.hip)
 void launch_dfs(const GmDfsParams& P, unsigned blocks, hipStream_t s);
-// upd_open[ord] = 1 for every canonical update with a seed whose search did
-// not finish (seed_open != 0); upd_open must be zeroed first
+// For every seed whose search did not finish (seed_open != 0):
+// upd_open[ord] = 1 (if upd_open) and q_open[q] += 1 (if q_open); both must
+// be zeroed first
 void launch_upd_open(const GmSeed* seeds, const GmCounters* ctr, uint64_t seed_cap, const uint32_t* seed_open,
-                     uint8_t* upd_open, hipStream_t s);
+                     uint8_t* upd_open, unsigned long long* q_open, hipStream_t s);
 unsigned dfs_block_threads();
 unsigned dfs_resident_waves_per_cu();
 unsigned dfs_waves_per_block();

@@ -349,6 +349,7 @@ struct gamma_ctx {
       uint32_t max_el = 0;
       for (uint32_t e : q.elabels) max_el = std::max(max_el, e);
       if (has_graph && max_el >= n_el) d.n_plans = 0;
+      if (q.paused) d.n_plans = 0;  // no seeds, so no search and no results
       qd.push_back(d);
       const size_t t0 = qel.size();
       qel.resize(t0 + GM_MAX_K * GM_MAX_K, 0);
@@ -532,6 +533,7 @@ gamma_status gamma_create(const gamma_options* opt, gamma_ctx** out) {
   c->tun.handover_gate = 2;
   c->tun.coalesced_search = 2;
   c->tun.group_seeds = 1;
+  c->tun.shared_leaf = 2;
   *out = c;
   return GAMMA_OK;
 }
@@ -888,15 +890,18 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     uint32_t* r0l = C.ensure<uint32_t>(C.r0_len, std::max<uint32_t>(n_touched, 1));
     const uint64_t seed_cap = std::max<uint64_t>((uint64_t)n_canon * C.total_plans, 1);
     GmSeed* sd = C.ensure<GmSeed>(C.seeds, seed_cap);
-    const size_t qres_n = std::max<size_t>((size_t)nq * 6, 6);
+    // per query: (count, sum, xor) per sign, then the number of its seeds
+    // whose search did not finish
+    const size_t qres_n = std::max<size_t>((size_t)nq * 7, 7);
     unsigned long long* qres = C.ensure<unsigned long long>(C.qres, qres_n);
     unsigned long long* upd = nullptr;
-    uint32_t* sopen = nullptr;  // per-seed completion, tracked with per-update results
+    // per-seed completion, tracked with per-update results and under a deadline
+    const bool track = (flags & GAMMA_F_PER_UPDATE) || C.opt.deadline_ms;
+    uint32_t* sopen = track ? C.ensure<uint32_t>(C.seed_open, seed_cap) : nullptr;
     uint8_t* uopen = nullptr;
     const size_t uopen_words = ((size_t)n_canon + 3) / 4 + 1;
     if (flags & GAMMA_F_PER_UPDATE) {
       upd = C.ensure<unsigned long long>(C.upd_res, std::max<size_t>((size_t)n_canon * 3, 3));
-      sopen = C.ensure<uint32_t>(C.seed_open, seed_cap);
       uopen = (uint8_t*)C.ensure<uint32_t>(C.upd_open, uopen_words);
     }
     const uint32_t wpc = C.tun.waves_per_cu;
@@ -1050,6 +1055,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.split_inner = C.tun.split_inner;
       P.split_leaf = C.tun.split_leaf;
       P.gate = C.tun.handover_gate;
+      P.shared_leaf = C.tun.shared_leaf == 2 ? 1u : 0u;
       P.perms = (const GmPerm*)C.permtab.p;
       // plans permute matches only when some query (or core) has symmetries;
       // without them coalescing changes nothing and the lean search applies
@@ -1064,6 +1070,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.group_list = grp_lists;
       for (uint32_t qi = 0; qi < (per_query ? nq : 1u); ++qi) {
         if (per_query) {
+          if (C.queries[qi].paused) continue;
           if (qi) gm::launch_seed_window(ctr, s);
           gm::launch_seeds(ca, cb, csg, cel, n_canon, (const GmQueryDev*)C.qdev.p, nq, (const GmPlan*)C.plans.p,
                            (const uint16_t*)C.cand.p, n, sd, seed_cap, ctr, qi,
@@ -1077,10 +1084,8 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       }
     }
     chk(hipEventRecord(C.ev[5], s), "event");
-    if (uopen) {
-      gm::fill_u32((uint32_t*)uopen, 0, uopen_words, s);
-      if (nq && n_canon) gm::launch_upd_open(sd, ctr, seed_cap, sopen, uopen, s);
-    }
+    if (uopen) gm::fill_u32((uint32_t*)uopen, 0, uopen_words, s);
+    if (sopen && nq && n_canon) gm::launch_upd_open(sd, ctr, seed_cap, sopen, uopen, qres + (size_t)nq * 6, s);
 
     // ---------------------------------------------------------- commit G', refresh filter on G'
     // a dry run (or a search past its deadline) puts the saved rows back
@@ -1138,6 +1143,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
         r.hash_sum[sgn] = (flags & GAMMA_F_HASH) ? p[1] : 0;
         r.hash_xor[sgn] = (flags & GAMMA_F_HASH) ? p[2] : 0;
       }
+      r.open_seeds = h_qres[(size_t)nq * 6 + q];
     }
     std::memset(out, 0, sizeof(*out));
     out->n_queries = nq;
@@ -1210,7 +1216,7 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
     st.ms_commit = el(5, 6);
     ms = el(0, 7);
     st.ms_total = ms;
-    if (h_ctr->aborted) {
+    if (h_ctr->aborted || h_ctr->timed_out) {
       // rows were put back on the device: the graph is as before the batch
       C.has_result = false;
       return fail(c, GAMMA_ETIMEDOUT, "apply_batch: search deadline exceeded; batch not committed");
@@ -1376,7 +1382,8 @@ bool tuning_ok(const gamma_tuning& t) {
          t.poll_cycles >= 500 && t.poll_cycles <= 1000000 && t.split_inner >= 2 &&
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
          (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
-         t.coalesced_search >= 1 && t.coalesced_search <= 3 && t.group_seeds >= 1 && t.group_seeds <= 3;
+         t.coalesced_search >= 1 && t.coalesced_search <= 3 && t.group_seeds >= 1 && t.group_seeds <= 3 &&
+         (t.shared_leaf == 1 || t.shared_leaf == 2);
 }
 }  // namespace
 
@@ -1392,8 +1399,33 @@ gamma_status gamma_set_tuning(gamma_ctx* c, const gamma_tuning* in) {
   if (in->handover_gate) t.handover_gate = in->handover_gate;
   if (in->coalesced_search) t.coalesced_search = in->coalesced_search;
   if (in->group_seeds) t.group_seeds = in->group_seeds;
+  if (in->shared_leaf) t.shared_leaf = in->shared_leaf;
   if (!tuning_ok(t)) return fail(c, GAMMA_EINVAL, "set_tuning: value out of range");
   c->tun = t;
+  return GAMMA_OK;
+}
+
+gamma_status gamma_set_query_active(gamma_ctx* c, uint32_t qid, uint32_t active) {
+  if (!c) return GAMMA_EINVAL;
+  return guarded(c, [&]() -> gamma_status {
+    if (qid >= c->queries.size()) return fail(c, GAMMA_EINVAL, "set_query_active: no such query");
+    const bool paused = active == 0;
+    if (c->queries[qid].paused == paused) return GAMMA_OK;
+    chk(hipSetDevice(c->device), "set device");
+    c->queries[qid].paused = paused;
+    try {
+      c->upload_plans();
+    } catch (const StatusError&) {
+      c->queries[qid].paused = !paused;
+      throw;
+    }
+    return GAMMA_OK;
+  });
+}
+
+gamma_status gamma_set_deadline(gamma_ctx* c, uint32_t deadline_ms) {
+  if (!c) return GAMMA_EINVAL;
+  c->opt.deadline_ms = deadline_ms;
   return GAMMA_OK;
 }
 
@@ -1409,7 +1441,7 @@ gamma_status gamma_autotune(gamma_ctx* c, uint32_t n_upd, const uint32_t* src, c
     return a.waves_per_cu == b.waves_per_cu && a.steal == b.steal && a.poll_cycles == b.poll_cycles &&
            a.split_inner == b.split_inner && a.split_leaf == b.split_leaf && a.query_launch == b.query_launch &&
            a.handover_gate == b.handover_gate && a.coalesced_search == b.coalesced_search &&
-           a.group_seeds == b.group_seeds;
+           a.group_seeds == b.group_seeds && a.shared_leaf == b.shared_leaf;
   };
   gamma_status err = GAMMA_OK;
   // median device time of `reps` dry runs at tuning t (< 0: failed)

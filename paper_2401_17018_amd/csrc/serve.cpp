@@ -14,7 +14,11 @@
 // Batches are applied and committed in order; a request completes when its
 // batch is committed.  With TUPLES, admission also bounds a batch by its
 // estimated match-buffer use (a moving estimate of tuple records per
-// update), and each batch's records are copied out after its commit.  On an edge-labelled graph requests name triples
+// update), and each batch's records are copied out after its commit.  In
+// every mode a work budget (max_batch_ms) can bound a batch by its
+// estimated device time, from a moving estimate of device ms per update, so
+// that a batch of many requests does not hold the ones queued behind it for
+// longer than the budget.  On an edge-labelled graph requests name triples
 // (u, v, label): a request that names a pair of the batch under another
 // label, or with the other op, also closes the batch.
 #include <hip/hip_runtime.h>
@@ -65,6 +69,7 @@ struct gamma_server {
   bool tuples = false;
   double budget = 0;          // tuple records a batch may be estimated to fill
   double per_update = -1.0;   // estimated tuple records per update (< 0: no batch seen yet)
+  double ms_per_update = -1.0;  // estimated device ms per update (< 0: no batch seen yet)
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
 
@@ -95,6 +100,10 @@ struct gamma_server {
             if (opt.coalesce == 2 || nupd + r.op.size() > opt.max_batch_updates) break;
             // admission by estimated match-buffer memory
             if (tuples && (per_update < 0 || (double)(nupd + r.op.size()) * per_update > budget)) break;
+            // admission by estimated device time
+            if (opt.max_batch_ms && ms_per_update >= 0 &&
+                (double)(nupd + r.op.size()) * ms_per_update > (double)opt.max_batch_ms)
+              break;
             bool conflict = false;
             for (size_t i = 0; i < r.op.size() && !conflict; ++i) {
               const uint64_t a = std::min(r.src[i], r.dst[i]), b = std::max(r.src[i], r.dst[i]);
@@ -143,6 +152,8 @@ struct gamma_server {
       if (st >= 0) {
         rec.info.n_canonical = res.n_canonical;
         rec.info.ms_device = res.stats.ms_total;
+        const double mrate = (double)res.stats.ms_total / std::max<double>(op.size(), 1.0);
+        ms_per_update = ms_per_update < 0 ? mrate : 0.5 * ms_per_update + 0.5 * mrate;
         rec.q.assign(res.queries, res.queries + res.n_queries);
         if (tuples) {
           const uint64_t nt = res.n_tuples;

@@ -321,3 +321,91 @@ def test_deadline_aborts_and_leaves_graph_unchanged():
         assert np.array_equal(erp, g.row_ptr) and np.array_equal(ecol, g.col)
         res = ctx.apply_batch(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint8))
         assert res.counts.sum() == 0
+
+
+def test_per_query_time_limit_reports_unsolved_queries():
+    """With one search launch per query the deadline is a time limit per
+    query (Sec. VI-A): a query with ~10^11 incremental matches passes it and
+    is reported unsolved (open seeds), the light queries before and after it
+    finish with the figures they have without a deadline, and the batch is
+    not committed.  With one launch for all queries the deadline covers the
+    launch, and the light queries' figures are exact where they report no
+    open seed."""
+    lo, hi = W.rmat_edges(14, 200000, 9)
+    rp, col = W.csr_from_edges(1 << 14, lo, hi)
+    g = W.Graph(1 << 14, rp, col, np.zeros(1 << 14, np.uint32))
+    light = W.query_from_edges(3, [(0, 1), (1, 2), (2, 0)], (0,) * 3)
+    heavy = W.query_from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 5)], (0,) * 6)
+    k4 = W.query_from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0), (0, 2), (1, 3)], (0,) * 4)
+    b = _mixed_batch(g, 3, 2000, 500)
+    with make_ctx(cap=0) as ctx:
+        ctx.load_graph(g.row_ptr, g.col, g.labels)
+        for q in (light, heavy, k4):
+            ctx.register_query(q.k, q.labels, q.edges)
+        ctx.set_query_active(1, False)
+        ref = ctx.apply_batch(b.src, b.dst, b.op, hash=True, dry_run=True)
+        assert ref.count(1, 1) == 0 and ref.count(1, 0) == 0 and not ref.open_seeds.any()
+        assert ref.counts[0].sum() > 0 and ref.counts[2].sum() > 0
+        ctx.set_query_active(1, True)
+        ctx.set_tuning(query_launch=2)
+        ctx.set_deadline(200)  # the light queries (10^5 and 10^7 matches) take a few ms each
+        with pytest.raises(GammaError) as ei:
+            ctx.apply_batch(b.src, b.dst, b.op, hash=True)
+        e = ei.value
+        assert e.status == capi.GAMMA_ETIMEDOUT
+        assert e.open_seeds[1] > 0 and e.open_seeds[0] == 0 and e.open_seeds[2] == 0
+        for qi in (0, 2):
+            assert [int(x) for x in e.counts[qi]] == [int(x) for x in ref.counts[qi]]
+            assert [int(x) for x in e.hash_sum[qi]] == [int(x) for x in ref.hash_sum[qi]]
+            assert [int(x) for x in e.hash_xor[qi]] == [int(x) for x in ref.hash_xor[qi]]
+        erp, ecol, _ = ctx.export_graph()
+        assert np.array_equal(erp, g.row_ptr) and np.array_equal(ecol, g.col)
+        ctx.set_tuning(query_launch=1)
+        with pytest.raises(GammaError) as ei:
+            ctx.apply_batch(b.src, b.dst, b.op, hash=True)
+        e = ei.value
+        assert e.open_seeds[1] > 0
+        for qi in (0, 2):
+            if e.open_seeds[qi] == 0:
+                assert [int(x) for x in e.counts[qi]] == [int(x) for x in ref.counts[qi]]
+        # without a deadline the light queries' results are unchanged by the heavy one's absence
+        ctx.set_query_active(1, False)
+        ctx.set_deadline(0)
+        res = ctx.apply_batch(b.src, b.dst, b.op, hash=True)
+        assert np.array_equal(res.counts, ref.counts) and np.array_equal(res.hash_sum, ref.hash_sum)
+
+
+@pytest.mark.parametrize("query_launch", [1, 2])
+def test_paused_query_is_kept_current(query_launch):
+    """A paused query gets no seeds and reports nothing, the other queries'
+    results are unchanged, and its candidate table follows every batch: once
+    resumed it reports what a context that never paused it reports."""
+    g = _er(3000, 24000, 41, 3)
+    qa = W.query_from_edges(4, [(0, 1), (1, 2), (2, 0), (2, 3)], (0, 1, 0, 2))
+    qb = W.query_from_edges(5, [(0, 1), (1, 2), (2, 3), (3, 4), (4, 0)], (1, 0, 1, 2, 0))
+    b1 = _mixed_batch(g, 51, 400, 150)
+    rp, col = O2.updated_graph(g, b1)
+    g1 = W.Graph(g.n, rp, col, g.labels)
+    b2 = _mixed_batch(g1, 52, 400, 150)
+    outs = []
+    for pause in (False, True):
+        with make_ctx(cap=0) as ctx:
+            ctx.set_tuning(query_launch=query_launch)
+            ctx.load_graph(g.row_ptr, g.col, g.labels)
+            ctx.register_query(qa.k, qa.labels, qa.edges)
+            ctx.register_query(qb.k, qb.labels, qb.edges)
+            if pause:
+                ctx.set_query_active(1, False)
+            r1 = ctx.apply_batch(b1.src, b1.dst, b1.op, hash=True, per_update=True)
+            if pause:
+                ctx.set_query_active(1, True)
+            r2 = ctx.apply_batch(b2.src, b2.dst, b2.op, hash=True)
+            outs.append((r1, r2))
+    (n1, n2), (p1, p2) = outs
+    assert p1.counts[1].sum() == 0 and p1.hash_sum[1].sum() == 0
+    assert np.array_equal(p1.counts[0], n1.counts[0]) and np.array_equal(p1.hash_sum[0], n1.hash_sum[0])
+    assert n1.counts[1].sum() > 0 and n2.counts[1].sum() > 0
+    assert np.array_equal(p2.counts, n2.counts) and np.array_equal(p2.hash_sum, n2.hash_sum)
+    assert np.array_equal(p2.hash_xor, n2.hash_xor)
+    ref = O2.run(g1, qb, b2, qid=1, want_tuples=False)
+    assert (int(n2.counts[1][0]), int(n2.counts[1][1])) == ref.count

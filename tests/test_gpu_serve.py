@@ -71,14 +71,15 @@ def _graph(ctx, labels):
     return W.Graph(len(lab), rp, col, lab)
 
 
-@pytest.mark.parametrize("seed,max_size", [(1, 40), (2, 300)])
-def test_served_stream_isolation(seed, max_size):
+@pytest.mark.parametrize("seed,max_size,max_batch_ms", [(1, 40, 0), (2, 300, 0), (3, 300, 1)])
+def test_served_stream_isolation(seed, max_size, max_batch_ms):
+    """max_batch_ms = 1: admission by estimated device time as well."""
     g = _er(1200, 7000, 30 + seed, 3)
     qs = _queries(seed, [3, 4, 5])
     reqs = _request_stream(g, seed, 48, max_size)
     with make_ctx(cap=0) as ctx:
         _setup(ctx, g, qs)
-        with Server(ctx, max_batch_updates=2 * max_size) as srv:
+        with Server(ctx, max_batch_updates=2 * max_size, max_batch_ms=max_batch_ms) as srv:
             tickets = [srv.submit(*r) for r in reqs]
             srv.drain()
             done = srv.poll(4096)

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from oracle import plain as O2
 from paper_2401_17018_amd import GammaError, capi
 from test_gpu_parity import _er, _mixed_batch, _skewed_graph, check_against_o2, make_ctx
 
@@ -84,6 +85,7 @@ TUNINGS = [
     dict(waves_per_cu=32, steal=1, poll_cycles=1000000, split_inner=1 << 20, split_leaf=1 << 20),
     dict(waves_per_cu=12, steal=2),
     dict(waves_per_cu=1, steal=1, poll_cycles=3000, handover_gate=1),
+    dict(waves_per_cu=8, steal=1, shared_leaf=1),  # every survivor walks its own last level
 ]
 
 
@@ -111,7 +113,8 @@ def test_set_tuning_rejects_out_of_range():
     with make_ctx(cap=0) as ctx:
         before = ctx.get_tuning()
         for bad in (dict(split_inner=1), dict(waves_per_cu=33), dict(steal=3), dict(query_launch=7),
-                    dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=4)):
+                    dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=4),
+                    dict(shared_leaf=3)):
             with pytest.raises(GammaError) as ei:
                 ctx.set_tuning(**bad)
             assert ei.value.status == capi.GAMMA_EINVAL
@@ -223,3 +226,49 @@ def test_update_edge_grouping_shares_level_two(qname):
         _same(plain_full, full)
     assert int(plain_lean.counts.sum()) > 0
     check_against_o2(res["grouped_handover"][1], g, q, b, check_tuples=not res["grouped_handover"][1].truncated)
+
+
+SHARED_QUERIES = {
+    "star4": (4, [(0, 1), (0, 2), (0, 3)], (0, 1, 1, 0)),
+    "star5_equal": (5, [(0, 1), (0, 2), (0, 3), (0, 4)], (0, 0, 0, 0, 0)),  # the survivor itself is a candidate
+    "tree_cycle6": (6, [(0, 1), (1, 2), (2, 0), (2, 3), (1, 4), (0, 5)], (0, 1, 0, 1, 0, 1)),
+    "two_static_lists": (5, [(0, 1), (1, 2), (0, 3), (1, 3), (2, 4)], (0, 1, 0, 1, 1)),
+}
+
+
+@pytest.mark.parametrize("qname", list(SHARED_QUERIES))
+def test_shared_last_level_identical(qname):
+    """A last level whose lists all come from vertices matched before
+    order[k-2] is walked once per level-(k-2) chunk and paired with every
+    survivor (shared_leaf = 2).  Counts, checksums and per-update
+    attribution equal the per-survivor descent (shared_leaf = 1) and the
+    oracle, with and without forced hand-over; so do the candidates counted."""
+    from paper_2401_17018_amd import describe_query
+    k, edges, labels = SHARED_QUERIES[qname]
+    q = W.query_from_edges(k, edges, labels)
+    adj = {(a, c) for a, c in edges} | {(c, a) for a, c in edges}
+    plans, _ = describe_query(q.k, q.labels, q.edges)
+    assert any((p["order"][k - 1], p["order"][k - 2]) not in adj for p in plans)
+    g = _skewed_graph(5)
+    b = _mixed_batch(g, 8, 300, 100)
+    res = {}
+    with make_ctx(cap=0) as ctx:
+        ctx.load_graph(g.row_ptr, g.col, g.labels)
+        ctx.register_query(q.k, q.labels, q.edges)
+        for name, t in [("off", dict(shared_leaf=1)), ("on", dict(shared_leaf=2)),
+                        ("on_handover", dict(shared_leaf=2, poll_cycles=500, split_inner=2, split_leaf=2,
+                                             handover_gate=1024, waves_per_cu=4))]:
+            ctx.set_tuning(coalesced_search=1, **t)
+            res[name] = ctx.apply_batch(b.src, b.dst, b.op, hash=True, per_update=True, dry_run=True)
+    off = res["off"]
+    for name in ("on", "on_handover"):
+        _same(off, res[name])
+        assert np.array_equal(off.upd_hash_xor, res[name].upd_hash_xor)
+        assert res[name].stats["cand_scanned"] == off.stats["cand_scanned"]
+    assert int(off.counts.sum()) > 0
+    ref = O2.run(g, q, b, qid=0, want_tuples=False)
+    assert (int(off.counts[0, 0]), int(off.counts[0, 1])) == ref.count
+    assert (int(res["on"].hash_sum[0, 0]), int(res["on"].hash_sum[0, 1])) == ref.hsum
+    assert (int(res["on"].hash_xor[0, 0]), int(res["on"].hash_xor[0, 1])) == ref.hxor
+    assert np.array_equal(res["on"].upd_count, ref.seed_count)
+    assert np.array_equal(res["on"].upd_hash_sum, ref.seed_hsum)
