@@ -277,6 +277,19 @@ def cpu_baseline(w, queries, budget_s: float = 20.0, batch=None):
     }
 
 
+CYC = ("cyc_idle", "cyc_init", "cyc_inner", "cyc_leaf", "cyc_handover")
+
+
+def cycle_split(stats):
+    """Share of the search's wave-cycles per activity over the timed
+    batches (a profiling build only; None when the library does not count)."""
+    tot = {k: sum(int(st.get(k, 0)) for st in stats) for k in CYC}
+    allc = sum(tot.values())
+    if not allc:
+        return None
+    return {k[4:]: round(v / allc, 4) for k, v in tot.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,7 +317,14 @@ def main():
                     help="materialise every match (TUPLES) and copy the tuples to the host inside the timed step")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--library", default="",
+                    help="load this build of the library instead of paper_2401_17018_amd/libgamma.so (e.g. the "
+                         "profiling build, paper_2401_17018_amd/libgamma_prof.so, whose search reports its "
+                         "cycle split: cycle_split in the output)")
     args = ap.parse_args()
+    if args.library:
+        from paper_2401_17018_amd import capi
+        capi.load_library(os.path.abspath(args.library))
     if args.copy_calibration_mib:
         # a plain copy kernel of known size: HBM counters read for it give the
         # bytes-per-count factor used to turn FETCH_SIZE / WRITE_SIZE into bytes
@@ -468,6 +488,7 @@ def main():
                 "updates": "canonical edge updates incl. the deleted vertices' edges"} if vdels is not None else {}),
         },
         "phases_ms": phases,
+        "cycle_split": cycle_split(stats),
         **({"same_batch": same_batch} if same_batch else {}),
         "roofline": roofline(achieved, avg_bytes, avg_dfs_s, traffic),
     }
@@ -608,6 +629,7 @@ def run_batched(args):
         },
         "autotune": {k: tune[k] for k in ("best_ms", "base_ms", "max_points", "reps")},
         "roofline": roofline(achieved, avg_bytes, avg_dfs_s, counter_traffic(w.name)),
+        "cycle_split": cycle_split(stats),
     }
     print(json.dumps(out))
 

@@ -125,11 +125,15 @@ typedef struct gamma_tuning {
                              that waves starting together share rows.  1 = generation order
                              (default).  With query_launch = 2 seeds stay in generation order.
                              Results are identical in every mode. */
-  uint32_t shared_leaf;   /* 2 = on (default): when none of the last query vertex's lists comes
-                             from the vertex matched just before it, its candidates are read
-                             and filtered once per chunk of 64 partial matches and paired with
-                             each of them; 1 = off (each partial match walks them itself).
-                             Results are identical either way. */
+  uint32_t shared_leaf;   /* set-ups shared between partial matches that differ only in the
+                             vertex matched last.  3 = the last level: when none of the last
+                             query vertex's lists comes from the vertex matched just before
+                             it, its candidates are read and filtered once per chunk of 64
+                             partial matches and paired with each of them.  2 (default) = that,
+                             and an inner level whose lists do not come from the vertex
+                             matched just before it keeps its set-up from one such partial
+                             match to the next.  1 = neither.  Results are identical in every
+                             mode. */
 } gamma_tuning;
 
 /* Per query results of one batch.  Index 1 = insertion results (+),

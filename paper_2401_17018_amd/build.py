@@ -3,6 +3,12 @@
 Every source under csrc/ is compiled with --offload-arch=gfx950 and linked
 into paper_2401_17018_amd/libgamma.so.  Packed-FP32 instructions are
 disabled for all device code.
+
+`python build.py --profile` builds libgamma_prof.so beside it instead: the
+same library with GM_DFS_PROFILE=1, whose search kernel also splits its
+wave-cycles into idle, level set-up, inner levels, last level and
+hand-over (the cyc_* batch statistics).  Nothing loads it unless asked
+(bench.py --library).
 """
 from __future__ import annotations
 
@@ -55,9 +61,9 @@ def _resources(stderr: str) -> dict:
     return out
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc"] + COMMON + DEVICE
+def _compile(src: str, bdir: str = BUILD_DIR, extra=()) -> str:
+    obj = os.path.join(bdir, os.path.basename(src) + ".o")
+    cmd = ["hipcc"] + COMMON + DEVICE + list(extra)
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     watch = os.path.basename(src) in WATCH
@@ -68,27 +74,30 @@ def _compile(src: str) -> str:
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))
     if watch:
-        with open(os.path.join(BUILD_DIR, os.path.basename(src) + ".resources.json"), "w") as f:
+        with open(os.path.join(bdir, os.path.basename(src) + ".resources.json"), "w") as f:
             json.dump(_resources(r.stderr), f, indent=1)
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, profile: bool = False) -> str:
+    out = os.path.join(HERE, "libgamma_prof.so") if profile else OUT
+    bdir = BUILD_DIR + ("_prof" if profile else "")
+    extra = ["-DGM_DFS_PROFILE=1"] if profile else []
+    os.makedirs(bdir, exist_ok=True)
     srcs = sources()
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda f: _compile(f, bdir, extra), srcs))
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr[-6000:])
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, profile="--profile" in sys.argv[1:])
     sys.exit(0)

@@ -115,6 +115,8 @@ struct WaveState {
   uint64_t mask[GM_MAX_K]; // survivors of the current chunk not descended into yet
   uint32_t drvv[GM_MAX_K]; // data vertex whose row drives level l
   uint32_t oth_n[GM_MAX_K];
+  uint32_t flen[GM_MAX_K]; // driver length as set up (the hand-over may shorten len)
+  uint32_t lvl_ok;         // bit l: level l's set-up was made under the current f(order[0 .. l-2])
   uint64_t hpre;           // checksum salt + element terms of every position but the last vertex
   uint64_t hpp[GM_MAX_PERM]; // the same for each permutation of a coalesced plan
   uint64_t tally[8];       // idle, init, inner, leaf, hand-over cycles; tasks received; hand-overs; nodes
@@ -585,6 +587,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       S.drv[l] = lane_val64(base, besti);
       S.len[l] = best;
+      S.flen[l] = best;
       S.drvv[l] = lane_val(v, besti);
       S.oth_n[l] = nb - 1;
       S.cur[l] = 0;
@@ -669,6 +672,34 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
         S.hpre = h;
         if (nperm > 1) perm_prefixes(u);
       }
+      S.lvl_ok = uni(S.lvl_ok) | (1u << l);
+      return true;
+    };
+
+    // Re-enter inner level nl (3 <= nl <= k-2) for a new survivor of level
+    // nl-1 without setting it up again: when none of its lists comes from
+    // order[nl-1] (nor, at level k-2, the last level's static lists), its
+    // set-up depends only on f(order[0 .. nl-2]), unchanged since it was
+    // made (lvl_ok).  Only the range (which a hand-over may have shortened)
+    // and, at level k-2, the checksum terms of the prefix are renewed; the
+    // injectivity against the new survivor is checked per candidate anyway.
+    auto reenter = [&](uint32_t nl) -> bool {
+      if (nl < 3 || nl + 1 >= k || !((uni(S.lvl_ok) >> nl) & 1u)) return false;
+      const uint32_t up = uni(pl->order[nl - 1]);
+      if ((uni(pl->back[nl]) >> up) & 1u) return false;
+      if (nl == pf_lvl) {
+        if ((uni(pl->back[k - 1]) >> up) & 1u) return false;
+        uint64_t h = gm_mix64(((uint64_t)q << 1) | sign);
+        for (uint32_t j = 0; j < nl; ++j) {
+          const uint32_t uj = uni(pl->order[j]);
+          h += elem_hash(uni(S.fx[uj]), uj);
+        }
+        S.st_h = h;
+      }
+      S.len[nl] = uni(S.flen[nl]);
+      S.cur[nl] = 0;
+      S.mask[nl] = 0;
+      TALLY_ALWAYS(7, 1);
       return true;
     };
 
@@ -1258,6 +1289,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     // core permutation p (0: the identity) of the prefix saved in fcore:
     // query vertex v takes fcore[pi(v)]; positions < L0 are the core
     auto apply_cperm = [&](uint32_t p) {
+      S.lvl_ok = 0u;  // the prefix moves: every set-up below is stale
       CPerm pp = cperm0 + p;
       uint32_t v = 0, nf = 0, nx = 0;
       if ((uint32_t)lane < L0) {
@@ -1298,6 +1330,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
     };
     // back to the core prefix as found (the identity permutation)
     auto restore_core = [&]() {
+      S.lvl_ok = 0u;
       if ((uint32_t)lane < L0) {
         const uint32_t v = pl->order[lane];
         const uint32_t c = S.fcore[v];
@@ -1321,6 +1354,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       }
       S.pvalid = lane_val(tword, HO_W_GIVE_LO);
       S.pidx = 0xFFFFFFFFu;
+      S.lvl_ok = 0u;
       base_l = L0 - 1;
       S.cur[L0 - 1] = 0;
       S.len[L0 - 1] = 0;
@@ -1331,6 +1365,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
       S.mask[L0] = 0;
       go = true;
     } else {
+      S.lvl_ok = 0u;
       go = init_level(l, !handed);
     }
     if (!go) {
@@ -1442,6 +1477,12 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
             continue;
           }
           nl = l + 1;
+          // set-ups below nl were made under the previous survivor of level l
+          S.lvl_ok = uni(S.lvl_ok) & ((2u << nl) - 1u);
+          if (P.reenter && reenter(nl)) {
+            l = nl;
+            continue;
+          }
         }
         // one set-up site for every descent (the set-up is inlined where it
         // is called, and each copy costs registers)

@@ -95,6 +95,8 @@ struct GmDfsParams {
                                   // 2: also permute core prefixes (plans with n_cperm >= 2)
   uint32_t shared_leaf;           // 1: a last level that does not depend on level k-2 is walked
                                   // once per level-(k-2) chunk for all its survivors
+  uint32_t reenter;               // 1: an inner level that does not depend on the level before
+                                  // it keeps its set-up from one survivor of that level to the next
   const uint8_t* qel;             // [nq][16][16] edge label of query edge {u, w} (used when G.elb > 0)
   // per seed, its work items not yet finished (the seed's own item plus one
   // per hand-over of its work); 0xFFFFFFFF = not started.  NULL: untracked.

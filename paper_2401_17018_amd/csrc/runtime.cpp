@@ -1055,7 +1055,8 @@ gamma_status gamma_apply_batch_el(gamma_ctx* c, uint32_t n_upd, const uint32_t* 
       P.split_inner = C.tun.split_inner;
       P.split_leaf = C.tun.split_leaf;
       P.gate = C.tun.handover_gate;
-      P.shared_leaf = C.tun.shared_leaf == 2 ? 1u : 0u;
+      P.shared_leaf = C.tun.shared_leaf >= 2 ? 1u : 0u;
+      P.reenter = C.tun.shared_leaf == 2 ? 1u : 0u;
       P.perms = (const GmPerm*)C.permtab.p;
       // plans permute matches only when some query (or core) has symmetries;
       // without them coalescing changes nothing and the lean search applies
@@ -1383,7 +1384,7 @@ bool tuning_ok(const gamma_tuning& t) {
          t.split_inner <= (1u << 20) && t.split_leaf >= 2 && t.split_leaf <= (1u << 20) &&
          (t.query_launch == 1 || t.query_launch == 2) && t.handover_gate >= 1 && t.handover_gate <= 1024 &&
          t.coalesced_search >= 1 && t.coalesced_search <= 3 && t.group_seeds >= 1 && t.group_seeds <= 3 &&
-         (t.shared_leaf == 1 || t.shared_leaf == 2);
+         t.shared_leaf >= 1 && t.shared_leaf <= 3;
 }
 }  // namespace
 

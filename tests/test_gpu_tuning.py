@@ -85,7 +85,8 @@ TUNINGS = [
     dict(waves_per_cu=32, steal=1, poll_cycles=1000000, split_inner=1 << 20, split_leaf=1 << 20),
     dict(waves_per_cu=12, steal=2),
     dict(waves_per_cu=1, steal=1, poll_cycles=3000, handover_gate=1),
-    dict(waves_per_cu=8, steal=1, shared_leaf=1),  # every survivor walks its own last level
+    dict(waves_per_cu=8, steal=1, shared_leaf=1),  # every survivor walks its own last level, sets up every level
+    dict(waves_per_cu=8, steal=1, shared_leaf=3),  # shared last level, every inner level set up anew
 ]
 
 
@@ -114,7 +115,7 @@ def test_set_tuning_rejects_out_of_range():
         before = ctx.get_tuning()
         for bad in (dict(split_inner=1), dict(waves_per_cu=33), dict(steal=3), dict(query_launch=7),
                     dict(poll_cycles=10), dict(handover_gate=2000), dict(group_seeds=4),
-                    dict(shared_leaf=3)):
+                    dict(shared_leaf=4)):
             with pytest.raises(GammaError) as ei:
                 ctx.set_tuning(**bad)
             assert ei.value.status == capi.GAMMA_EINVAL
@@ -233,6 +234,9 @@ SHARED_QUERIES = {
     "star5_equal": (5, [(0, 1), (0, 2), (0, 3), (0, 4)], (0, 0, 0, 0, 0)),  # the survivor itself is a candidate
     "tree_cycle6": (6, [(0, 1), (1, 2), (2, 0), (2, 3), (1, 4), (0, 5)], (0, 1, 0, 1, 0, 1)),
     "two_static_lists": (5, [(0, 1), (1, 2), (0, 3), (1, 3), (2, 4)], (0, 1, 0, 1, 1)),
+    # static inner levels; on the uniform-degree graph below (hub rows would
+    # give a 7-vertex tree ~10^13 matches per batch)
+    "tree7": (7, [(0, 1), (0, 2), (1, 3), (1, 4), (2, 5), (2, 6)], (0, 1, 2, 0, 1, 2, 0)),
 }
 
 
@@ -240,31 +244,34 @@ SHARED_QUERIES = {
 def test_shared_last_level_identical(qname):
     """A last level whose lists all come from vertices matched before
     order[k-2] is walked once per level-(k-2) chunk and paired with every
-    survivor (shared_leaf = 2).  Counts, checksums and per-update
-    attribution equal the per-survivor descent (shared_leaf = 1) and the
-    oracle, with and without forced hand-over; so do the candidates counted."""
+    survivor (shared_leaf = 3), and inner levels whose lists do not come
+    from the vertex matched before them keep their set-up between that
+    vertex's candidates (shared_leaf = 2).  Counts, checksums and per-update
+    attribution equal the plain descent (shared_leaf = 1) and the oracle,
+    with and without forced hand-over; so do the candidates and nodes."""
     from paper_2401_17018_amd import describe_query
     k, edges, labels = SHARED_QUERIES[qname]
     q = W.query_from_edges(k, edges, labels)
     adj = {(a, c) for a, c in edges} | {(c, a) for a, c in edges}
     plans, _ = describe_query(q.k, q.labels, q.edges)
     assert any((p["order"][k - 1], p["order"][k - 2]) not in adj for p in plans)
-    g = _skewed_graph(5)
+    g = _er(3000, 15000, 5, 3) if qname == "tree7" else _skewed_graph(5)
     b = _mixed_batch(g, 8, 300, 100)
     res = {}
-    with make_ctx(cap=0) as ctx:
+    with make_ctx(cap=0, deadline_ms=60000) as ctx:
         ctx.load_graph(g.row_ptr, g.col, g.labels)
         ctx.register_query(q.k, q.labels, q.edges)
-        for name, t in [("off", dict(shared_leaf=1)), ("on", dict(shared_leaf=2)),
+        for name, t in [("off", dict(shared_leaf=1)), ("leaf", dict(shared_leaf=3)), ("on", dict(shared_leaf=2)),
                         ("on_handover", dict(shared_leaf=2, poll_cycles=500, split_inner=2, split_leaf=2,
                                              handover_gate=1024, waves_per_cu=4))]:
             ctx.set_tuning(coalesced_search=1, **t)
             res[name] = ctx.apply_batch(b.src, b.dst, b.op, hash=True, per_update=True, dry_run=True)
     off = res["off"]
-    for name in ("on", "on_handover"):
+    for name in ("leaf", "on", "on_handover"):
         _same(off, res[name])
         assert np.array_equal(off.upd_hash_xor, res[name].upd_hash_xor)
         assert res[name].stats["cand_scanned"] == off.stats["cand_scanned"]
+        assert res[name].stats["dfs_nodes"] == off.stats["dfs_nodes"]
     assert int(off.counts.sum()) > 0
     ref = O2.run(g, q, b, qid=0, want_tuples=False)
     assert (int(off.counts[0, 0]), int(off.counts[0, 1])) == ref.count
