@@ -296,8 +296,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large",
-                    choices=["tiny", "mid", "large", "batched", "served", "symmetric", "core", "elabel",
-                             "vertices"])
+                    choices=["tiny", "mid", "large", "batched", "served", "served-large", "symmetric", "core",
+                             "elabel", "vertices"])
+    ap.add_argument("--requests", type=int, default=40,
+                    help="served-large: requests in the stream (the mid-graph stream has 200)")
     ap.add_argument("--vertex-deletions", type=int, default=64, help="vertices deleted per batch (vertices workload)")
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="offered loads (x capacity) for the served workload")
     ap.add_argument("--tune-points", type=int, default=24, help="autotuner evaluations (batched workload)")
@@ -353,7 +355,7 @@ def main():
         n_batches += 1  # the batch the repeated dry runs use
     if args.workload == "batched":
         return run_batched(args)
-    if args.workload == "served":
+    if args.workload in ("served", "served-large"):
         return run_served(args)
     if args.workload == "symmetric":
         return run_symmetric(args)
@@ -752,28 +754,67 @@ def run_served(args):
     """Served stream: Poisson arrivals of update requests at offered loads
     of the plain path's capacity, with continuous batching against one
     device batch per request.  Capacity = updates/s of the plain path
-    applying the first requests one at a time (dry runs)."""
+    applying the first requests one at a time (dry runs).
+
+    served-large: the large graph (2^24 vertices) and 32 queries of 4..10
+    vertices; each query first runs alone (one launch per query) under
+    the per-query limit (--query-limit-ms, x4 for requests of up to 10^4
+    updates) on each of the first five requests, and the queries past it
+    are reported unsolved (Sec. VI-A) and paused for the served runs."""
     import threading
     import numpy as np
     import workloads as W
-    from paper_2401_17018_amd import Context, Server
+    from paper_2401_17018_amd import Context, GammaError, Server, capi
 
+    large = args.workload == "served-large"
     t0 = time.time()
-    w = W.served_stream()
+    w = W.served_stream(large=True, n_requests=args.requests) if large else W.served_stream()
     reqs, gaps = w.batches, w.meta["gaps"]
     sizes = np.array([len(r) for r in reqs], np.float64)
     print("[bench] workload %s generated in %.1fs: %d requests, %d updates, %d queries" % (
         w.name, time.time() - t0, len(reqs), int(sizes.sum()), len(w.queries)), file=sys.stderr, flush=True)
+    nq = len(w.queries)
+    unsolved = []
+    limit_ms = 4 * args.query_limit_ms
+    if large:
+        t0 = time.time()
+        with Context(device=0) as c:
+            c.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
+            for q in w.queries:
+                c.register_query(q.k, q.labels, q.edges)
+            bad = set()
+            for r in reqs[:5]:
+                c.set_tuning(query_launch=2)
+                c.set_deadline(limit_ms)
+                try:
+                    op = c.apply_batch(r.src, r.dst, r.op, hash=True, dry_run=True).open_seeds
+                except GammaError as e:
+                    if e.status != capi.GAMMA_ETIMEDOUT:
+                        raise
+                    op = e.open_seeds
+                bad |= {i for i in range(nq) if op[i] > 0}
+                for i in range(nq):
+                    c.set_query_active(i, False)
+                c.set_deadline(0)
+                c.apply_batch(r.src, r.dst, r.op, hash=False)
+                for i in range(nq):
+                    c.set_query_active(i, True)
+        unsolved = sorted(bad)
+        print("[bench] classification %.1fs: %d of %d queries unsolved within %d ms on the first requests: %s" % (
+            time.time() - t0, len(unsolved), nq, limit_ms, [(w.queries[i].k, w.queries[i].kind) for i in unsolved]),
+            file=sys.stderr, flush=True)
 
     def fresh():
-        c = Context(device=0)
+        c = Context(device=0, deadline_ms=args.deadline_s * 1000 if large else 0)
         c.load_graph(w.graph.row_ptr, w.graph.col, w.graph.labels)
         for q in w.queries:
             c.register_query(q.k, q.labels, q.edges)
+        for i in unsolved:
+            c.set_query_active(i, False)
         return c
 
     with fresh() as ctx:
-        n_cal = 30
+        n_cal = min(30, len(reqs) // 2)
         ctx.apply_batch(reqs[0].src, reqs[0].dst, reqs[0].op, hash=True, dry_run=True)  # warm-up
         t_cal = 0.0
         for r in reqs[:n_cal]:
@@ -811,6 +852,7 @@ def run_served(args):
             lat = [d["t_done_ms"] - d["t_submit_ms"] for d in done]
             span_s = (max(d["t_done_ms"] for d in done) - min(d["t_submit_ms"] for d in done)) / 1e3
             run = {"load": lam, "coalesce": coalesce, "requests": len(done), "device_batches": n_bat,
+                   "failed": sum(1 for d in done if d["status"] < 0),
                    "updates_per_s": float(sizes.sum()) / span_s, "matches_per_s": mat / span_s,
                    "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "span_s": span_s}
             runs.append(run)
@@ -842,6 +884,8 @@ def run_served(args):
             "requests": len(reqs),
             "request_sizes": "log-uniform [100, 10000], 85% insertions",
             "capacity_updates_per_s": capacity,
+            "unsolved": [{"qid": i, "k": w.queries[i].k, "kind": w.queries[i].kind} for i in unsolved],
+            "query_limit_ms": limit_ms if large else None,
             "latency": "request completion (its batch committed) minus arrival",
         },
         "served": runs,

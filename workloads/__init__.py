@@ -637,29 +637,44 @@ def _batched_spec(seed: int, n_queries: int, sparse_max: int = 12):
 
 
 def served_stream(seed: int = 0, n_requests: int = 200, n_queries: int = 32, size_lo: int = 100,
-                  size_hi: int = 10000, ins_frac: float = 0.85, threads: int = 0) -> Workload:
+                  size_hi: int = 10000, ins_frac: float = 0.85, threads: int = 0, large: bool = False) -> Workload:
     """A request stream for the served path: the mid graph, the first
     n_queries standing queries of batched_queries() with sparse sizes
     capped at 8 (larger sparse queries are unsolved), and n_requests update
     requests valid in sequence, of log-uniform size in [size_lo, size_hi]
     with ins_frac insertions (held-out edges) and the rest deletions of
     present edges.  meta["gaps"] holds unit-mean exponential inter-arrival
-    gaps (a Poisson process once scaled to the offered load)."""
-    d = Draws(sub_seed(seed, TAG_STREAM + 11), TAG_STREAM)
+    gaps (a Poisson process once scaled to the offered load).
+
+    large=True: the large workload's graph (R-MAT scale 24, 2^28 edges, 32
+    Zipf(1.0) labels) with queries of 4..10 vertices whose walks keep to the
+    large workload's label ranks (sparse >= 20, dense >= 12)."""
+    d = Draws(sub_seed(seed, TAG_STREAM + 11 + (500 if large else 0)), TAG_STREAM)
     lo, hi = math.log10(size_lo), math.log10(size_hi)
     u = d.block(n_requests).astype(np.float64) / 2.0 ** 64
     sizes = np.floor(10.0 ** (lo + u * (hi - lo))).astype(np.int64)
     n_ins = np.rint(sizes * ins_frac).astype(np.int64)
     n_del = sizes - n_ins
     gaps = -np.log1p(-d.block(n_requests).astype(np.float64) / 2.0 ** 64)
-    g, pl, ph = rmat_graph_with_pool(20, 8 << 20, int(n_ins.sum()), 16, 1.2, seed, threads=threads,
-                                     name="served-rmat20")
+    name = "served-large-rmat24" if large else "served-rmat20"
+    if large:
+        g, pl, ph = rmat_graph_with_pool(24, 16 << 24, int(n_ins.sum()), 32, 1.0, seed, threads=threads, name=name)
+    else:
+        g, pl, ph = rmat_graph_with_pool(20, 8 << 20, int(n_ins.sum()), 16, 1.2, seed, threads=threads, name=name)
     pool = keys_of(pl, ph)
-    ins0 = pool[: int(n_ins[0])]
+    # queries are extracted on G u (the first request's insertions); on the
+    # large graph on G u (the first 2 * 10^4 insertions of the stream), so
+    # that walks over its rare labels find an inserted edge to start from
+    ins0 = pool[: max(int(n_ins[0]), min(int(n_ins.sum()), 20000))] if large else pool[: int(n_ins[0])]
     queries, protect = [], set()
-    for qi, (k, kind) in enumerate(_batched_spec(seed, n_queries, sparse_max=8)):
-        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)),
-                          min_label=BATCHED_QUERY_MIN_LABEL)
+    spec = _batched_spec(seed, n_queries, sparse_max=10 if large else 8)
+    for qi, (k, kind) in enumerate(spec):
+        if large:
+            k = min(k, 10)
+            ml = LARGE_SPARSE_QUERY_MIN_LABEL if kind == "sparse" else LARGE_QUERY_MIN_LABEL
+        else:
+            ml = BATCHED_QUERY_MIN_LABEL
+        q = extract_query(g, ins0, k, kind, sub_seed(seed, TAG_QUERY + 97 * (qi + 1)), min_label=ml)
         queries.append(q)
         for (x, y) in q.edges.tolist():
             a, b = q.planted[x], q.planted[y]
@@ -673,7 +688,7 @@ def served_stream(seed: int = 0, n_requests: int = 200, n_queries: int = 32, siz
         dels = shadow.sample_deletions(int(n_del[i]), bd, protect) if n_del[i] else np.zeros(0, np.uint64)
         shadow.add(ins)
         reqs.append(make_batch(ins, dels, bd))
-    return Workload("served-rmat20", g, queries, reqs, {"seed": seed, "gaps": gaps, "sizes": sizes})
+    return Workload(name, g, queries, reqs, {"seed": seed, "gaps": gaps, "sizes": sizes})
 
 
 def batched_queries(seed: int = 0, n_batches: int = 1, n_queries: int = 64, threads: int = 0,
