@@ -399,6 +399,7 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 #else
 #define TALLY(i, v) \
   do {              \
+    (void)(v);      \
   } while (0)
 #define CYCLES() 0ull
 #endif
@@ -1342,29 +1343,35 @@ __global__ __launch_bounds__(DFS_THREADS) GM_DFS_ATTR void k_dfs(GmDfsParams P) 
 
     uint32_t l = base_l;
     bool pf_ok = false;  // level k-2's prefetch records belong to its current chunk
-    bool go;
-    if (ptask) {
-      // a share of another wave's core permutations: its core prefix (the
-      // identity) and the permutations to enter.  Level L0-1 stands used up
-      // below it, so that stepping back from L0 ends the task.
-      if ((uint32_t)lane < L0) {
-        const uint32_t v = pl->order[lane];
-        S.fcore[v] = S.f[v];
-        S.fxcore[v] = S.fx[v];
+    bool go = false;
+    bool entered = false;
+    // (core permutation tasks exist in the full build only)
+    if constexpr (FULL) {
+      if (ptask) {
+        // a share of another wave's core permutations: its core prefix (the
+        // identity) and the permutations to enter.  Level L0-1 stands used up
+        // below it, so that stepping back from L0 ends the task.
+        if ((uint32_t)lane < L0) {
+          const uint32_t v = pl->order[lane];
+          S.fcore[v] = S.f[v];
+          S.fxcore[v] = S.fx[v];
+        }
+        S.pvalid = lane_val(tword, HO_W_GIVE_LO);
+        S.pidx = 0xFFFFFFFFu;
+        S.lvl_ok = 0u;
+        base_l = L0 - 1;
+        S.cur[L0 - 1] = 0;
+        S.len[L0 - 1] = 0;
+        S.mask[L0 - 1] = 0;
+        l = L0;
+        S.cur[L0] = 0;
+        S.len[L0] = 0;
+        S.mask[L0] = 0;
+        go = true;
+        entered = true;
       }
-      S.pvalid = lane_val(tword, HO_W_GIVE_LO);
-      S.pidx = 0xFFFFFFFFu;
-      S.lvl_ok = 0u;
-      base_l = L0 - 1;
-      S.cur[L0 - 1] = 0;
-      S.len[L0 - 1] = 0;
-      S.mask[L0 - 1] = 0;
-      l = L0;
-      S.cur[L0] = 0;
-      S.len[L0] = 0;
-      S.mask[L0] = 0;
-      go = true;
-    } else {
+    }
+    if (!entered) {
       S.lvl_ok = 0u;
       go = init_level(l, !handed);
     }
