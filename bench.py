@@ -317,6 +317,11 @@ def main():
                          "the run are reported unsolved and paused")
     ap.add_argument("--tuples", action="store_true",
                     help="materialise every match (TUPLES) and copy the tuples to the host inside the timed step")
+    ap.add_argument("--count-only", action="store_true",
+                    help="counts without checksums (every match still found and counted, none hashed); for "
+                         "profiling the search without its checksum work, not the default measurement")
+    ap.add_argument("--query-kind", default="", choices=["", "sparse", "dense"],
+                    help="large workload: register only the queries of this kind (profiling one query)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--library", default="",
@@ -386,7 +391,10 @@ def main():
     print("[bench] workload %s generated in %.1fs: n=%d m=%d queries=%s batches=%d" % (
         w.name, gen_s, w.graph.n, w.graph.m, [q.k for q in w.queries], len(w.batches)), file=sys.stderr, flush=True)
 
-    timed_queries = list(w.queries)
+    timed_queries = [q for q in w.queries if not args.query_kind or q.kind == args.query_kind]
+    if not timed_queries:
+        raise SystemExit("no query of kind %r in workload %s" % (args.query_kind, w.name))
+    hash_ = not args.count_only
     ctx = Context(device=0, steal=not args.no_steal, waves_per_cu=args.waves_per_cu,
                   tuple_capacity=(1 << 25) if args.tuples else 0, deadline_ms=args.deadline_s * 1000)
     if args.group_seeds:
@@ -405,7 +413,7 @@ def main():
     vd_of = (lambda i: vdels[i]) if vdels is not None else (lambda i: None)
     for i in range(args.warmup):
         b = batches[i]
-        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(i))
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=hash_, elab=b.elab, delete_vertices=vd_of(i))
         print("[bench] warmup %d: %.1f ms, matches %d" % (i, r.stats["ms_total"], int(r.counts.sum())),
               file=sys.stderr, flush=True)
 
@@ -414,7 +422,7 @@ def main():
     for i in range(args.steps):
         b = batches[args.warmup + i]
         t1 = time.perf_counter()
-        r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd_of(args.warmup + i),
+        r = ctx.apply_batch(b.src, b.dst, b.op, hash=hash_, elab=b.elab, delete_vertices=vd_of(args.warmup + i),
                             tuples=args.tuples)
         t2 = time.perf_counter()
         if args.tuples and r.truncated:
@@ -437,7 +445,7 @@ def main():
         vd = vd_of(args.warmup + args.steps)
         runs = []
         for i in range(args.reps + 1):
-            r = ctx.apply_batch(b.src, b.dst, b.op, hash=True, elab=b.elab, delete_vertices=vd, dry_run=True)
+            r = ctx.apply_batch(b.src, b.dst, b.op, hash=hash_, elab=b.elab, delete_vertices=vd, dry_run=True)
             if i:
                 runs.append(r.stats)
         tot = sorted(st["ms_total"] for st in runs)
@@ -453,7 +461,8 @@ def main():
     avg_dfs_s = sum(dfs_ms) / len(dfs_ms) / 1e3
     avg_bytes = sum(dfs_bytes) / len(dfs_bytes)
     achieved = avg_bytes / avg_dfs_s / 1e9 if avg_dfs_s > 0 else 0.0
-    traffic = counter_traffic(w.name)
+    # the committed counter summaries cover the default configuration only
+    traffic = counter_traffic(w.name) if hash_ and not args.query_kind and not args.tuples else None
     phases = {k: round(sum(s[k] for s in stats) / len(stats), 3)
               for k in ("ms_canon", "ms_merge", "ms_filter", "ms_seed", "ms_dfs", "ms_commit", "ms_total")}
     out = {
@@ -483,7 +492,9 @@ def main():
                else {}),
             "batch_updates": len(batches[args.warmup]),
             "mode": ("tuples written to HBM and copied to host memory, plus counts + hash" if args.tuples
-                     else "counts + hash (every match enumerated)"),
+                     else "counts + hash (every match enumerated)" if hash_
+                     else "counts only (every match found, none hashed)"),
+            **({"query_kind": args.query_kind} if args.query_kind else {}),
             **({"edge_labels": w.graph.n_elabels,
                 "query_edge_labels": [q.elabels.tolist() for q in timed_queries]} if w.graph.elab is not None else {}),
             **({"vertex_deletions_per_batch": args.vertex_deletions,
